@@ -1,0 +1,223 @@
+"""The five seeded screening workloads and the serving request stream.
+
+Each workload is a reference image, a list of planted templates (each with
+its true centre and object radius) and a probe list of
+(template id, scale id, reference radius) triples.  Sizes default to the
+benchmark shapes and can be shrunk for tests; every other structural choice
+(radius grids, rotations, scale ranges, feature sets) is kept.
+
+Workloads:
+  1  single scale: 512^2 u8, one exact 33x33 cut, radius 16, sum + sum of
+     squares, tolerance 1/20.
+  2  rotation + scale: 4096^2 u8, one template resampled at a random angle
+     and a scale in [0.75, 1.5] from an object of radius 32; probe radii
+     16..64 step 8; all three features.
+  3  batched: 8192^2 u8, 64 templates of radius U{8..96}, each resampled as
+     in workload 2; probe scales 0.5..2.0 step 0.25 of each template radius.
+  4  serving: request stream (see ``serving_requests``).
+  5  large batched: 16384^2 12-bit, one radius-48 cut at 16 rotations of
+     22.5 degrees, 32 radii geometric from 24 to 96 (0.5x..2x).
+
+Tolerances are inputs to the screen (relative, P/Q per feature).  The
+values here were set from the largest relative feature deviation between a
+planted template and the reference at its nearest probe radius over seeds
+0..4 (measured with the oracle), plus a margin: sums and squares match to a
+few percent under bilinear resampling, the gradient sum much less well
+(interpolation smooths the pixel noise that dominates |Gx|+|Gy|), and
+workload 3's coarse scale grid misses the true radius by up to ~12%.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .images import blob_image, cut_patch, make_rng, pick_centre, rotate_scale_patch
+
+# feature bits, as in the library's feature mask
+F_SUM, F_SQ, F_GRAD = 1, 2, 4
+
+
+@dataclass
+class PlantedTemplate:
+    pixels: np.ndarray
+    rho: int                 # template star radius (centre of ``pixels``)
+    cx: int                  # planted centre in the reference (column)
+    cy: int                  # planted centre in the reference (row)
+    obj_radius: float        # radius of the object in the reference
+    theta: float = 0.0
+    scale: float = 1.0
+    exact: bool = False      # exact cut / quarter turn: must always survive
+
+
+@dataclass
+class Workload:
+    cfg_id: int
+    name: str
+    ref: np.ndarray
+    depth: int
+    templates: list
+    probes: list             # (template_id, scale_id, r)
+    feat_mask: int
+    tol_P: tuple
+    tol_Q: int
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def H(self):
+        return self.ref.shape[0]
+
+    @property
+    def W(self):
+        return self.ref.shape[1]
+
+    def radii(self):
+        return sorted({p[2] for p in self.probes})
+
+
+def radius_grid_cfg5(r0: int = 24, r1: int = 96, n: int = 32) -> list:
+    """Radii round(r0 * (r1/r0)^(j/(n-1))), j = 0..n-1 (a geometric grid)."""
+    ratio = r1 / r0
+    return [int(math.floor(r0 * ratio ** (j / (n - 1)) + 0.5)) for j in range(n)]
+
+
+def _resampled_template(rng, ref, hi, obj_radius_fn, *, std_min, apron, margin_min):
+    """Draw theta ~ U[0,360), s ~ U[0.75,1.5] and a textured centre; return a
+    PlantedTemplate resampled from the reference."""
+    theta = float(rng.uniform(0.0, 360.0))
+    s = float(rng.uniform(0.75, 1.5))
+    rho, obj_r = obj_radius_fn(s)
+    half = rho + apron
+    margin = max(int(math.ceil(half * math.sqrt(2.0) / s)) + 2, margin_min)
+    cx, cy = pick_centre(rng, ref, margin, std_half=max(2, int(obj_r)), std_min=std_min)
+    pix = rotate_scale_patch(ref, cx, cy, theta, s, half, hi)
+    return PlantedTemplate(pix, rho, cx, cy, obj_r, theta, s, exact=False)
+
+
+def make_workload(cfg_id: int, seed: int = 0, *, H: int | None = None, W: int | None = None,
+                  n_templates: int | None = None, blobs_per_512sq: float = 200.0,
+                  sig_hi: float = 64.0) -> Workload:
+    """Build workload ``cfg_id`` from ``seed``.  ``H``/``W``/``n_templates``
+    shrink it for tests; ``blobs_per_512sq``/``sig_hi`` keep small images
+    textured (the default blob recipe is sized for large images)."""
+    rng = make_rng(cfg_id, seed)
+    bkw = {"blobs_per_512sq": blobs_per_512sq, "sig_hi": sig_hi}
+    if cfg_id == 1:
+        H = H or 512
+        W = W or H
+        ref = blob_image(H, W, rng, **bkw)
+        cx, cy = pick_centre(rng, ref, 16, std_half=16, std_min=10.0)
+        t = PlantedTemplate(cut_patch(ref, cx, cy, 16), 16, cx, cy, 16.0, exact=True)
+        return Workload(1, "single-scale 512^2 u8, r=16", ref, 8, [t], [(0, 0, 16)],
+                        F_SUM | F_SQ, (1, 1, 0), 20)
+    if cfg_id == 2:
+        H = H or 4096
+        W = W or H
+        ref = blob_image(H, W, rng, **bkw)
+        radii = list(range(16, 65, 8))
+        t = _resampled_template(rng, ref, 255, lambda s: (int(math.floor(32 * s + 0.5)), 32.0),
+                                std_min=10.0, apron=1, margin_min=min(64, min(H, W) // 2 - 40) + 1)
+        probes = [(0, k, r) for k, r in enumerate(radii) if 2 * r + 1 <= min(H, W)]
+        return Workload(2, "rotation+scale 4096^2 u8, r=16..64 step 8", ref, 8, [t], probes,
+                        F_SUM | F_SQ | F_GRAD, (4, 8, 65), 100)
+    if cfg_id == 3:
+        H = H or 8192
+        W = W or H
+        n_t = n_templates or 64
+        ref = blob_image(H, W, rng, **bkw)
+        sigmas = [0.5 + 0.25 * i for i in range(7)]
+        tmpls, probes = [], []
+        # templates must fit after the worst-case rotation at scale 0.75
+        rho_hi = max(8, min(96, int((min(H, W) / 2 - 3) / 1.9) - 1))
+        for ti in range(n_t):
+            rho_t = int(rng.integers(8, rho_hi + 1))
+
+            def fn(s, rho_t=rho_t):
+                return rho_t, rho_t / s
+            t = _resampled_template(rng, ref, 255, fn, std_min=10.0, apron=1, margin_min=8)
+            tmpls.append(t)
+            for k, sg in enumerate(sigmas):
+                r = int(math.floor(rho_t * sg + 0.5))
+                if r >= 1 and 2 * r + 1 <= min(H, W):
+                    probes.append((ti, k, r))
+        return Workload(3, f"batched {H}x{W} u8, {n_t} templates x 7 scales", ref, 8, tmpls,
+                        probes, F_SUM | F_SQ | F_GRAD, (45, 50, 80), 100)
+    if cfg_id == 5:
+        H = H or 16384
+        W = W or H
+        n_rot = n_templates or 16
+        ref = blob_image(H, W, rng, depth=12, **bkw)
+        rho = 48
+        half = rho + 1
+        margin = int(math.ceil(half * math.sqrt(2.0))) + 2
+        cx, cy = pick_centre(rng, ref, max(margin, 97), std_half=rho, std_min=160.0)
+        tmpls = []
+        for k in range(n_rot):
+            theta = 22.5 * k
+            pix = rotate_scale_patch(ref, cx, cy, theta, 1.0, half, 4095)
+            tmpls.append(PlantedTemplate(pix, rho, cx, cy, float(rho), theta, 1.0,
+                                         exact=(k % 4 == 0)))
+        radii = radius_grid_cfg5()
+        probes = [(t, j, r) for t in range(n_rot) for j, r in enumerate(radii)
+                  if 2 * r + 1 <= min(H, W)]
+        return Workload(5, f"large batched {H}x{W} 12-bit, {n_rot} rotations x 32 radii", ref, 12,
+                        tmpls, probes, F_SUM | F_SQ | F_GRAD, (5, 8, 50), 100)
+    raise ValueError(f"no fixed workload {cfg_id} (workload 4 is a request stream)")
+
+
+WORKLOADS = {1: "single-scale", 2: "rotation+scale", 3: "batched", 4: "serving", 5: "large batched"}
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    ref_key: int             # requests with equal keys share one reference image
+    side: int
+    templates: list          # PlantedTemplate
+    probes: list             # (template_id, scale_id, r)
+
+
+def serving_requests(n: int, rate_per_s: float, seed: int = 0, *, side_lo: int = 1024,
+                     side_hi: int = 8192, reuse: float = 0.3, max_templates: int = 8,
+                     rho_lo: int = 8, rho_hi: int = 128, max_scales: int = 9,
+                     blobs_per_512sq: float = 200.0):
+    """Poisson request stream.  Returns (requests, images) where ``images``
+    maps ref_key -> reference image.  Sides are log-uniform in
+    [side_lo, side_hi]; a fraction ``reuse`` of requests names a reference
+    that an earlier request already used; each request has 1..max_templates
+    templates of radius U{rho_lo..rho_hi} (capped so they fit) and
+    1..max_scales scales geometric in [0.5, 2] (one scale means {1})."""
+    rng = make_rng(4, seed)
+    t = 0.0
+    images, reqs = {}, []
+    for rid in range(n):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        if images and rng.uniform() < reuse:
+            key = int(rng.choice(sorted(images)))
+        else:
+            key = len(images)
+            side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
+            images[key] = blob_image(side, side, make_rng(40, seed * 100003 + key),
+                                     blobs_per_512sq=blobs_per_512sq)
+        ref = images[key]
+        side = ref.shape[0]
+        n_t = int(rng.integers(1, max_templates + 1))
+        n_s = int(rng.integers(1, max_scales + 1))
+        scales = [1.0] if n_s == 1 else [0.5 * 4.0 ** (i / (n_s - 1)) for i in range(n_s)]
+        tmpls, probes = [], []
+        for ti in range(n_t):
+            rho_max = min(rho_hi, int((side / 2 - 3) / 1.9) - 1)
+            rho = int(rng.integers(rho_lo, max(rho_lo, rho_max) + 1))
+
+            def fn(s, rho=rho):
+                return rho, rho / s
+            tm = _resampled_template(rng, ref, 255, fn, std_min=10.0, apron=1, margin_min=8)
+            tmpls.append(tm)
+            for k, sg in enumerate(scales):
+                r = int(math.floor(rho * sg + 0.5))
+                if r >= 1 and 2 * r + 1 <= side:
+                    probes.append((ti, k, r))
+        reqs.append(Request(rid, t, key, side, tmpls, probes))
+    return reqs, images

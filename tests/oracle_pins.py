@@ -1,0 +1,201 @@
+"""Pins of the C oracle against facts fixed outside it.
+
+Each ``check_*`` function raises AssertionError when the oracle library
+``lib`` disagrees with the paper, a closed form, a library routine or an
+independent enumerator.  ``test_oracle_pins.py`` runs them on the real
+oracle; ``test_oracle_mutants.py`` runs them on deliberately broken copies
+of the oracle to show that each plausible mistake is caught.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+from scipy.signal import correlate2d
+
+import oracle.core as oc
+from oracle import enum_star as en
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# s(r) = round(r / sqrt(2)), evaluated by hand for the radii the workloads use
+S_TABLE = {0: 0, 1: 1, 2: 1, 3: 2, 8: 6, 16: 11, 24: 17, 32: 23, 48: 34, 64: 45, 96: 68,
+           128: 91}
+
+
+def _rand_img(shape, seed, hi=255):
+    rng = np.random.default_rng(seed)
+    dt = np.uint8 if hi <= 255 else np.uint16
+    return rng.integers(0, hi + 1, shape).astype(dt)
+
+
+def check_half_width_and_area(lib):
+    for r, s in S_TABLE.items():
+        assert oc.square_half(r, lib) == s, (r, oc.square_half(r, lib), s)
+    for r in range(0, 131):
+        s = en.nearest_half_width(r)
+        # closed form: (2s+1)^2 square pixels + 2r^2+2r+1 diamond pixels
+        assert oc.star_area(r, lib) == (2 * s + 1) ** 2 + 2 * r * r + 2 * r + 1, r
+
+
+def read_golden_star():
+    rows = []
+    with open(os.path.join(GOLDEN, "star_r3.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(v) for v in line.split()])
+    return np.array(rows)
+
+
+def check_golden_7x7(lib):
+    want = read_golden_star()
+    got = np.array([[oc.star_weight(dx, dy, 3, lib) for dx in range(-3, 4)]
+                    for dy in range(-3, 4)])
+    assert (got == want).all(), got
+    # the weight seen through the feature sum of a unit impulse
+    img = np.zeros((7, 7), np.uint8)
+    for dy in range(-3, 4):
+        for dx in range(-3, 4):
+            img[:] = 0
+            img[3 + dy, 3 + dx] = 1
+            F = oc.star_features(img, [3], [3], 3, lib)[0]
+            assert F[0] == want[dy + 3, dx + 3] and F[1] == want[dy + 3, dx + 3]
+
+
+def check_enumerator(lib, sizes=((13, 11), (9, 16)), radii=(1, 2, 3, 4, 5)):
+    for seed, (H, W) in enumerate(sizes):
+        for hi in (255, 4095):
+            img = _rand_img((H, W), 10 + seed, hi)
+            rows = img.tolist()
+            for r in radii:
+                if 2 * r + 1 > min(H, W):
+                    continue
+                ys, xs = np.mgrid[0:H, 0:W]
+                F = oc.star_features(img, xs.ravel(), ys.ravel(), r, lib)
+                for i, (x, y) in enumerate(zip(xs.ravel(), ys.ravel())):
+                    e = en.star_features(rows, int(x), int(y), r)
+                    if e is None:
+                        assert (F[i] == -1).all()
+                    else:
+                        assert tuple(int(v) for v in F[i]) == e, (r, x, y, F[i], e)
+
+
+def _kernel(r):
+    """Integer star kernel built from the enumerator's pixel sets."""
+    w = np.zeros((2 * r + 1, 2 * r + 1), np.int64)
+    for dx, dy in en.square_pixels(r) + en.diamond_pixels(r):
+        w[dy + r, dx + r] += 1
+    return w
+
+
+def check_correlate(lib, H=24, W=21, radii=(1, 2, 4, 6)):
+    img = _rand_img((H, W), 3)
+    q_all = [img.astype(np.int64), img.astype(np.int64) ** 2,
+             np.array([[en.gradient_at(img.tolist(), x, y) for x in range(W)]
+                       for y in range(H)], np.int64)]
+    for r in radii:
+        ys, xs = np.mgrid[r:H - r, r:W - r]
+        F = oc.star_features(img, xs.ravel(), ys.ravel(), r, lib)
+        for q, qa in enumerate(q_all):
+            want = correlate2d(qa, _kernel(r), mode="valid")
+            assert (F[:, q].reshape(want.shape) == want).all(), (r, q)
+
+
+def check_closed_forms(lib):
+    # constant image: F = (c A, c^2 A, 0)
+    for c in (0, 7, 255):
+        img = np.full((15, 17), c, np.uint8)
+        for r in (1, 3, 5):
+            A = (2 * en.nearest_half_width(r) + 1) ** 2 + 2 * r * r + 2 * r + 1
+            ys, xs = np.mgrid[r:15 - r, r:17 - r]
+            F = oc.star_features(img, xs.ravel(), ys.ravel(), r, lib)
+            assert (F[:, 0] == c * A).all() and (F[:, 1] == c * c * A).all()
+            assert (F[:, 2] == 0).all()
+    # linear ramp I = a x + b y + c: the symmetric star returns A * I at the
+    # centre; away from the border G = 2|a| + 2|b| everywhere in the star
+    a, b, c0 = 2, 3, 5
+    H, W = 30, 36
+    yy, xx = np.mgrid[0:H, 0:W]
+    img = (a * xx + b * yy + c0).astype(np.uint8)
+    for r in (2, 4, 7):
+        A = (2 * en.nearest_half_width(r) + 1) ** 2 + 2 * r * r + 2 * r + 1
+        ys, xs = np.mgrid[r + 1:H - 1 - r, r + 1:W - 1 - r]
+        F = oc.star_features(img, xs.ravel(), ys.ravel(), r, lib)
+        assert (F[:, 0] == A * img[ys.ravel(), xs.ravel()].astype(np.int64)).all()
+        assert (F[:, 2] == A * (2 * abs(a) + 2 * abs(b))).all()
+
+
+_D4 = [
+    ("rot90", lambda a: np.rot90(a, 1)),
+    ("rot180", lambda a: np.rot90(a, 2)),
+    ("rot270", lambda a: np.rot90(a, 3)),
+    ("transpose", lambda a: a.T),
+    ("fliplr", lambda a: a[:, ::-1]),
+    ("flipud", lambda a: a[::-1, :]),
+]
+
+
+def check_d4(lib, H=19, W=23, radii=(2, 4, 7)):
+    img = _rand_img((H, W), 5)
+    idx = np.arange(H * W).reshape(H, W)
+    for name, T in _D4:
+        timg = np.ascontiguousarray(T(img))
+        tidx = T(idx)
+        th, tw = timg.shape
+        ys, xs = np.mgrid[0:th, 0:tw]
+        src = tidx[ys, xs].ravel()
+        oy, ox = np.divmod(src, W)
+        for r in radii:
+            Ft = oc.star_features(timg, xs.ravel(), ys.ravel(), r, lib)
+            Fo = oc.star_features(img, ox, oy, r, lib)
+            assert (Ft == Fo).all(), (name, r)
+
+
+def check_compare(lib):
+    # r = rho: the area and gradient factors cancel, |F - FT| Q <= P FT
+    for f in (0, 1, 2):
+        for F, ok in ((949, False), (950, True), (1000, True), (1050, True), (1051, False)):
+            assert oc.feature_pass(f, F, 1000, 16, 16, 1, 20, lib) == ok, (f, F)
+    # r = 16 (A = 1074) against rho = 8 (A = 314), exact equality at P = 0:
+    # sums and squares compare F * 314 with FT * 1074 ...
+    assert oc.feature_pass(0, 537, 157, 16, 8, 0, 1, lib)
+    assert not oc.feature_pass(0, 538, 157, 16, 8, 0, 1, lib)
+    assert not oc.feature_pass(1, 536, 157, 16, 8, 0, 1, lib)
+    # ... and gradients F * 314 * 16 with FT * 1074 * 8
+    assert oc.feature_pass(2, 537, 314, 16, 8, 0, 1, lib)
+    assert not oc.feature_pass(2, 537, 157, 16, 8, 0, 1, lib)
+    # monotone in the tolerance
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        f = int(rng.integers(0, 3))
+        r, rho = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        FT = int(rng.integers(0, 10 ** 6))
+        F = int(rng.integers(0, 10 ** 6))
+        prev = False
+        for P in (0, 1, 3, 10, 40, 200):
+            cur = oc.feature_pass(f, F, FT, r, rho, P, 100, lib)
+            assert cur or not prev
+            prev = cur
+
+
+def check_planted_exact(lib):
+    """An exact cut, and its quarter turns / transpose / mirror, survives at
+    its centre for every tolerance (P = 0 included), with all features."""
+    from synth import blob_image, make_rng, cut_patch
+    img = blob_image(96, 96, make_rng(99, 0), blobs_per_512sq=400)
+    cx, cy, rho = 50, 41, 9
+    probes = [(0, 0, rho)]
+    for kw in ({}, {"quarter_turns": 1}, {"quarter_turns": 2}, {"quarter_turns": 3},
+               {"transpose": True}, {"flip": True}):
+        tm = cut_patch(img, cx, cy, rho + 1, **kw)
+        bits = oc.screen_positions(img, [(tm, rho)], probes, 7, (0, 0, 0), 1, [cx], [cy], lib)
+        assert bits[0, 0] == 1, kw
+    # and a wrong location does not survive at P = 0
+    tm = cut_patch(img, cx, cy, rho + 1)
+    bits = oc.screen_positions(img, [(tm, rho)], probes, 7, (0, 0, 0), 1, [cx + 3], [cy], lib)
+    assert bits[0, 0] == 0
+
+
+ALL_CHECKS = [check_half_width_and_area, check_golden_7x7, check_enumerator, check_correlate,
+              check_closed_forms, check_d4, check_compare, check_planted_exact]
