@@ -1,0 +1,205 @@
+/*
+ * oss.h - octagonal-star screening library for AMD Instinct MI355X (gfx950).
+ *
+ * A pre-screen for rotation- and scale-invariant template matching
+ * (Liu, Shu & Wu, "Fast Screening Algorithm for Rotation and Scale
+ * Invariant Template Matching", Algorithm 1): every position of a reference
+ * image whose octagonal-star patch features cannot match a template's, at
+ * any of the probed scales, is ruled out.  The survivors are returned as a
+ * per-template mask and as a list of candidates.
+ *
+ * Definitions used throughout (pixel (x, y): column x, row y, 0-based):
+ *   star of radius r     superposition of the diamond |dx|+|dy| <= r and
+ *                        the congruent square max(|dx|,|dy|) <= s(r),
+ *                        s(r) = max{ s : (2s-1)^2 < 2 r^2 } = round(r/sqrt 2)
+ *                        (Sec. "Rotation Invariance", Fig. os, Eq. S_os);
+ *                        pixels in both count twice.  Weighted area
+ *                        A(r) = (2 s(r)+1)^2 + 2 r^2 + 2 r + 1.
+ *   features             F_q(x,y,r) = sum of q over the star for the
+ *                        quantities q = I (OSS_F_SUM), I^2 (OSS_F_SQ) and
+ *                        G = |I(x+1,y)-I(x-1,y)| + |I(x,y+1)-I(x,y-1)|
+ *                        (OSS_F_GRAD, indices clamped to the image)
+ *                        (Sec. "Patch Features"; Sec. "Rotation Invariance"
+ *                        for the rotation-robust gradient magnitude).
+ *   valid position       the star fits: r <= x <= W-1-r and r <= y <= H-1-r.
+ *   probe (t, k, r)      template t screened at reference radius r; k is
+ *                        the scale's bit in the candidate's scale bits.
+ *   feature test         with rho the template's radius, (c_ref, c_T) =
+ *                        (r, rho) for the gradient and (1, 1) otherwise,
+ *                        X_ref = F(x,y,r) A(rho) c_ref, X_T = F_T A(r) c_T:
+ *                        pass iff (Q-P) X_T <= Q X_ref <= (Q+P) X_T, exact.
+ *                        A probe passes where the position is valid and
+ *                        every compared feature passes (Algorithm 1, patch
+ *                        loop; Sec. "Scale Invariance", set membership with
+ *                        an exact relative interval in place of the
+ *                        quantised membership array).
+ *
+ * Conventions.  Every call returns an int status: OSS_OK (0) or a negative
+ * OSS_E_* code; oss_status_string names it.  No C++ exception crosses this
+ * interface.  Argument errors are reported before anything is launched.
+ * "stream" arguments are hipStream_t values passed as void* (NULL = the
+ * null stream); work is enqueued asynchronously on that stream.  The
+ * caller owns every pixel, mask, list and count buffer; the library owns
+ * the oss_ctx / oss_ref handles and the device memory behind them.  A
+ * context's internal workspaces are reused by every screen issued on it, so
+ * issue the calls of one context on one stream (or synchronise between
+ * streams); use one context per concurrently used stream.
+ */
+#ifndef OSS_H
+#define OSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define OSS_OK 0
+#define OSS_E_ARG (-1)      /* invalid argument (null, range, shape, dtype) */
+#define OSS_E_NOMEM (-2)    /* device or pinned host allocation failed */
+#define OSS_E_OVERFLOW (-3) /* an integer table could overflow int64 */
+#define OSS_E_DEVICE (-4)   /* a HIP runtime call failed */
+#define OSS_E_STATE (-5)    /* handle used with the wrong context or shape */
+
+/* pixel types */
+#define OSS_U8 0
+#define OSS_U16 1
+
+/* feature bits */
+#define OSS_F_SUM 1u
+#define OSS_F_SQ 2u
+#define OSS_F_GRAD 4u
+#define OSS_F_ALL 7u
+
+#define OSS_MAX_SCALES 32 /* scale ids 0..31 per template (bits of a uint32) */
+
+typedef struct oss_ctx oss_ctx;
+typedef struct oss_ref oss_ref;
+
+/* An image in memory: H rows of W pixels, rows pitch_bytes apart.
+ * dtype OSS_U8 (bit_depth 1..8) or OSS_U16 (bit_depth 1..16); pixel values
+ * must not exceed 2^bit_depth - 1 (the bound is used to prove the integer
+ * tables cannot overflow). */
+typedef struct oss_image_desc {
+    int32_t H, W;
+    int64_t pitch_bytes;
+    int32_t dtype;
+    int32_t bit_depth;
+} oss_image_desc;
+
+/* Template features: F[0] sum, F[1] sum of squares, F[2] gradient sum of
+ * the radius-rho star at the template centre ((w-1)/2, (h-1)/2) (floors);
+ * entries for features not in feat_mask are 0. */
+typedef struct oss_template_feat {
+    int64_t F[3];
+    int32_t rho;
+    uint32_t feat_mask;
+} oss_template_feat;
+
+/* One probe: template index, scale id (0..31), reference radius r >= 0. */
+typedef struct oss_probe {
+    int32_t template_id, scale_id, r;
+} oss_probe;
+
+/* Relative tolerance P[f]/Q per feature f (0 sum, 1 squares, 2 gradient);
+ * Q > 0, P[f] >= 0. */
+typedef struct oss_tolerance {
+    int32_t P[3];
+    int32_t Q;
+} oss_tolerance;
+
+/* One candidate: template, row, column and the bits of the scales whose
+ * probes pass there.  Lists are in (t, y, x) order. */
+typedef struct oss_candidate {
+    int32_t t, y, x;
+    uint32_t scale_bits;
+} oss_candidate;
+
+/* Create a context on HIP device `device` (makes it current on the calling
+ * thread).  *out receives the handle; destroy it with oss_ctx_destroy after
+ * releasing its references and synchronising the streams it used. */
+int oss_ctx_create(int device, oss_ctx **out);
+int oss_ctx_destroy(oss_ctx *ctx);
+
+/* Static name of a status code ("OSS_OK", "OSS_E_ARG", ...). */
+const char *oss_status_string(int status);
+
+/* Device bytes oss_ref_create would allocate for an image of this shape and
+ * feature set: the three integer tables per feature (below) plus the
+ * builder's carry workspace.  Used for admission by footprint. */
+int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, size_t *out);
+
+/*
+ * Allocate the integral tables of one reference image (Sec. "Patch
+ * Features", Eq. T_1 and the summed triangular table of Sec. "Rotation
+ * Invariance").  For each feature quantity q in feat_mask the library keeps,
+ * for x in [-1, W-1] and y in [-1, H-1]:
+ *   L(x,y)  = sum of q(i,j) over i <= x, j <= y               (Eq. T_1)
+ *   R(x,y)  = sum over j <= y, |i-x| <= y-j     (45-degree table, apex at
+ *             the pixel centre; the paper's triangular sum table)
+ *   R'(x,y) = R with the apex moved to the pixel corner (x+1/2, y+1/2):
+ *             sum over j <= y, x-(y-j) <= i <= x+1+(y-j)
+ * so that square sums take 4 lookups into L (Eq. S_1) and diamond sums 4
+ * lookups into R and R'.  Tables are int64, one entry per (x, y) holding
+ * the quantities in feature-bit order.  Returns OSS_E_OVERFLOW if
+ * H * W * max(q) could exceed 2^62.
+ */
+int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask, oss_ref **out);
+
+/* Build (or rebuild) the tables of `ref` from device pixels laid out as the
+ * descriptor says.  Asynchronous on `stream`; the pixels must stay valid
+ * until the stream reaches this point. */
+int oss_ref_build(oss_ref *ref, const void *dev_pixels, void *stream);
+
+/* Release the tables (the caller synchronises the streams using them). */
+int oss_ref_release(oss_ref *ref);
+
+/*
+ * Read-only device view of the tables: entry (x, y) of table T for
+ * quantity slot q is T[((y+1) * pitch_entries + (x+1)) * nq + q], with
+ * x in [-1, W-1], y in [-1, H-1]; nq = number of bits in the feature mask.
+ */
+int oss_ref_tables(const oss_ref *ref, const int64_t **L, const int64_t **R, const int64_t **Rp,
+                   int64_t *pitch_entries, int32_t *nq);
+
+/* Template features (host, synchronous): the radius-rho star at the centre
+ * of a host image, G taken on the template itself.  rho < 0 picks the
+ * largest radius whose star fits, less one when OSS_F_GRAD is requested (the
+ * template's border pixels have a clamped gradient).  Algorithm 1,
+ * "features(Z)" of the template loop. */
+int oss_template_features(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
+                          uint32_t feat_mask, oss_template_feat *out);
+
+/* The exact set of feature sums that pass one feature test: F passes iff
+ * *lo <= F <= *hi (host, synchronous).  feature 0 sum, 1 squares,
+ * 2 gradient; FT the template's feature sum, r the reference radius, rho the
+ * template radius.  The screen uses the same interval (Algorithm 1, patch
+ * loop: the cross-multiplied relative test solved once per probe). */
+int oss_feature_bounds(int32_t feature, int64_t FT, int32_t r, int32_t rho,
+                       const oss_tolerance *tol, int64_t *lo, int64_t *hi);
+
+/*
+ * Screen one reference against n_tmpl templates and n_probes probes
+ * (Algorithm 1, patch loop, for every probed scale).  feat_mask selects the
+ * compared features (a subset of the reference's).  Outputs, all caller
+ * owned device memory written on `stream`:
+ *   dev_mask  [n_tmpl][H][W] uint8, 1 where some probe of template t passes
+ *             (may be NULL)
+ *   dev_list  up to list_cap candidates in (t, y, x) order (may be NULL
+ *             with list_cap 0)
+ *   dev_count int64, the total number of candidates (may exceed list_cap;
+ *             the list then holds the first list_cap)
+ * Each template's probes are screened by one launch of the star kernel.
+ */
+int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+               const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+               uint32_t feat_mask, uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
+               int64_t *dev_count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSS_H */

@@ -30,6 +30,7 @@ def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH) -> str:
     try:
         subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src],
                        check=True, capture_output=True, text=True)
+        os.chmod(tmp, 0o755)
         os.replace(tmp, out)
     finally:
         if os.path.exists(tmp):

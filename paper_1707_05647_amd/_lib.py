@@ -1,0 +1,236 @@
+"""ctypes binding of liboss.so (include/oss.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors (only their data pointers cross the boundary);
+streams are torch streams or raw hipStream_t integers.  Nothing is computed
+in Python: a missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboss.so")
+
+OSS_OK, OSS_E_ARG, OSS_E_NOMEM, OSS_E_OVERFLOW, OSS_E_DEVICE, OSS_E_STATE = 0, -1, -2, -3, -4, -5
+OSS_U8, OSS_U16 = 0, 1
+OSS_F_SUM, OSS_F_SQ, OSS_F_GRAD, OSS_F_ALL = 1, 2, 4, 7
+OSS_MAX_SCALES = 32
+
+EXPORTED = [
+    "oss_ctx_create", "oss_ctx_destroy", "oss_status_string", "oss_ref_bytes", "oss_ref_create",
+    "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
+    "oss_feature_bounds", "oss_screen",
+]
+
+
+class oss_image_desc(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("pitch_bytes", C.c_int64),
+                ("dtype", C.c_int32), ("bit_depth", C.c_int32)]
+
+
+class oss_template_feat(C.Structure):
+    _fields_ = [("F", C.c_int64 * 3), ("rho", C.c_int32), ("feat_mask", C.c_uint32)]
+
+
+class oss_probe(C.Structure):
+    _fields_ = [("template_id", C.c_int32), ("scale_id", C.c_int32), ("r", C.c_int32)]
+
+
+class oss_tolerance(C.Structure):
+    _fields_ = [("P", C.c_int32 * 3), ("Q", C.c_int32)]
+
+
+class oss_candidate(C.Structure):
+    _fields_ = [("t", C.c_int32), ("y", C.c_int32), ("x", C.c_int32), ("scale_bits", C.c_uint32)]
+
+
+class OssError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load liboss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    # torch first: its bundled HIP runtime carries the soname liboss.so needs
+    # (libamdhip64.so.7), so the library binds to the one runtime torch uses
+    import torch  # noqa: F401
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1707_05647_amd.build`")
+    lib = C.CDLL(p)
+    vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    lib.oss_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.oss_ctx_destroy.argtypes = [vp]
+    lib.oss_status_string.argtypes = [C.c_int]
+    lib.oss_status_string.restype = C.c_char_p
+    lib.oss_ref_bytes.argtypes = [C.POINTER(oss_image_desc), u32, C.POINTER(C.c_size_t)]
+    lib.oss_ref_create.argtypes = [vp, C.POINTER(oss_image_desc), u32, C.POINTER(vp)]
+    lib.oss_ref_build.argtypes = [vp, vp, vp]
+    lib.oss_ref_release.argtypes = [vp]
+    lib.oss_ref_tables.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                   C.POINTER(i64), C.POINTER(i32)]
+    lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
+                                          C.POINTER(oss_template_feat)]
+    lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
+                                       C.POINTER(i64), C.POINTER(i64)]
+    lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
+                               C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
+    for name in EXPORTED:
+        if name != "oss_status_string":
+            getattr(lib, name).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().oss_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != OSS_OK:
+        raise OssError(status, what)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def image_desc(H: int, W: int, dtype: int = OSS_U8, bit_depth: int | None = None,
+               pitch_bytes: int | None = None) -> oss_image_desc:
+    px = 1 if dtype == OSS_U8 else 2
+    return oss_image_desc(int(H), int(W), int(pitch_bytes if pitch_bytes is not None else W * px),
+                          int(dtype), int(bit_depth if bit_depth is not None else 8 * px))
+
+
+def device_image(arr, device):
+    """Copy a 2-D uint8/uint16 numpy image to a torch device tensor (16-bit
+    pixels travel as int16 storage, the same bytes)."""
+    import torch
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.uint16:
+        a = a.view(np.int16)
+    return torch.from_numpy(a).to(device)
+
+
+def desc_of(arr, bit_depth: int | None = None) -> oss_image_desc:
+    """Descriptor of a 2-D uint8/uint16 numpy array or torch tensor."""
+    import torch
+    if isinstance(arr, torch.Tensor):
+        # int16 tensors are accepted as the storage of 16-bit unsigned pixels
+        if (arr.dtype not in (torch.uint8, torch.uint16, torch.int16) or arr.dim() != 2
+                or arr.stride(1) != 1):
+            raise ValueError("need a 2-D uint8/uint16 tensor with unit column stride")
+        dt = OSS_U8 if arr.dtype == torch.uint8 else OSS_U16
+        return image_desc(arr.shape[0], arr.shape[1], dt, bit_depth,
+                          arr.stride(0) * arr.element_size())
+    a = np.asarray(arr)
+    if a.dtype not in (np.uint8, np.uint16) or a.ndim != 2 or a.strides[1] != a.itemsize:
+        raise ValueError("need a 2-D uint8/uint16 array with unit column stride")
+    dt = OSS_U8 if a.dtype == np.uint8 else OSS_U16
+    return image_desc(a.shape[0], a.shape[1], dt, bit_depth, a.strides[0])
+
+
+def oss_ctx_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(load().oss_ctx_create(int(device), C.byref(h)), "oss_ctx_create")
+    return h.value
+
+
+def oss_ctx_destroy(ctx: int):
+    _check(load().oss_ctx_destroy(ctx), "oss_ctx_destroy")
+
+
+def oss_ref_bytes(desc: oss_image_desc, feat_mask: int) -> int:
+    out = C.c_size_t()
+    _check(load().oss_ref_bytes(C.byref(desc), int(feat_mask), C.byref(out)), "oss_ref_bytes")
+    return out.value
+
+
+def oss_ref_create(ctx: int, desc: oss_image_desc, feat_mask: int) -> int:
+    h = C.c_void_p()
+    _check(load().oss_ref_create(ctx, C.byref(desc), int(feat_mask), C.byref(h)),
+           "oss_ref_create")
+    return h.value
+
+
+def oss_ref_build(ref: int, pixels, stream=None):
+    _check(load().oss_ref_build(ref, _ptr(pixels), _stream(stream)), "oss_ref_build")
+
+
+def oss_ref_release(ref: int):
+    _check(load().oss_ref_release(ref), "oss_ref_release")
+
+
+def oss_ref_tables(ref: int):
+    """(L, R, Rp) device pointers, pitch in entries, number of quantities."""
+    L, R, Rp = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    pitch, nq = C.c_int64(), C.c_int32()
+    _check(load().oss_ref_tables(ref, C.byref(L), C.byref(R), C.byref(Rp), C.byref(pitch),
+                                 C.byref(nq)), "oss_ref_tables")
+    return L.value, R.value, Rp.value, pitch.value, nq.value
+
+
+def oss_template_features(pixels, rho: int, feat_mask: int,
+                          bit_depth: int | None = None) -> oss_template_feat:
+    a = np.ascontiguousarray(pixels)
+    out = oss_template_feat()
+    d = desc_of(a, bit_depth)
+    _check(load().oss_template_features(a.ctypes.data, C.byref(d), int(rho), int(feat_mask),
+                                        C.byref(out)), "oss_template_features")
+    return out
+
+
+def tolerance(P, Q: int) -> oss_tolerance:
+    P = list(P) + [0] * (3 - len(P))
+    return oss_tolerance((C.c_int32 * 3)(*[int(v) for v in P[:3]]), int(Q))
+
+
+def oss_feature_bounds(feature: int, FT: int, r: int, rho: int, P, Q: int):
+    """(lo, hi): the feature sums F that pass are exactly lo <= F <= hi."""
+    lo, hi = C.c_int64(), C.c_int64()
+    _check(load().oss_feature_bounds(int(feature), int(FT), int(r), int(rho),
+                                     C.byref(tolerance(P, Q)), C.byref(lo), C.byref(hi)),
+           "oss_feature_bounds")
+    return lo.value, hi.value
+
+
+def oss_screen(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None, cand_list=None,
+               list_cap: int = 0, count=None, stream=None):
+    """tmpl: sequence of oss_template_feat; probes: sequence of (t, k, r);
+    tol: (P0, P1, P2, Q) or oss_tolerance; mask/cand_list/count: torch
+    device tensors (uint8 [T,H,W], int32 [cap,4], int64 [1])."""
+    nt = len(tmpl)
+    ta = (oss_template_feat * nt)(*tmpl)
+    npb = len(probes)
+    pa = (oss_probe * max(1, npb))(*[oss_probe(int(t), int(k), int(r)) for t, k, r in probes])
+    if not isinstance(tol, oss_tolerance):
+        P0, P1, P2, Q = tol
+        tol = oss_tolerance((C.c_int32 * 3)(int(P0), int(P1), int(P2)), int(Q))
+    if count is None:
+        raise ValueError("count tensor required")
+    _check(load().oss_screen(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask), _ptr(mask),
+                             _ptr(cand_list), int(list_cap), _ptr(count), _stream(stream)),
+           "oss_screen")

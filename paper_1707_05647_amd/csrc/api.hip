@@ -1,0 +1,534 @@
+// C ABI of the octagonal-star screening library (include/oss.h).
+#include "oss_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+using namespace oss;
+
+namespace {
+
+struct PlanSlot {
+    void *host = nullptr;  // pinned staging
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+constexpr int NSLOTS = 4;
+
+}  // namespace
+
+struct oss_ctx {
+    int device = 0;
+    uint32_t *bits = nullptr;  // scale-bit words, n_tmpl * H * W
+    size_t bits_cap = 0;       // bytes
+    void *cws = nullptr;       // compaction workspace
+    size_t cws_cap = 0;        // bytes
+    PlanSlot slots[NSLOTS];
+    int next_slot = 0;
+};
+
+struct oss_ref {
+    oss_ctx *ctx = nullptr;
+    oss_image_desc desc{};
+    uint32_t feat_mask = 0;
+    BuildGeom geom{};
+    void *mem = nullptr;  // one allocation for everything below
+    size_t bytes = 0;
+    BuildBuffers bb{};
+};
+
+namespace oss {
+
+int square_half(int r)
+{
+    int s = 0;
+    while ((int64_t)(2 * s + 1) * (2 * s + 1) < 2LL * r * r)
+        ++s;
+    return s;
+}
+
+int64_t star_area(int r)
+{
+    const int64_t s = square_half(r);
+    return (2 * s + 1) * (2 * s + 1) + 2LL * r * r + 2LL * r + 1;
+}
+
+static __int128 floor_div(__int128 a, __int128 b)  // b > 0
+{
+    __int128 q = a / b;
+    if ((a % b != 0) && (a < 0))
+        --q;
+    return q;
+}
+
+static int64_t clamp64(__int128 v)
+{
+    if (v > (__int128)INT64_MAX)
+        return INT64_MAX;
+    if (v < (__int128)INT64_MIN)
+        return INT64_MIN;
+    return (int64_t)v;
+}
+
+// (Q-P) X_T <= Q X_ref <= (Q+P) X_T with X_ref = F A(rho) c_ref and
+// X_T = FT A(r) c_T, solved for the integer F: F in [lo, hi].
+void feature_bounds(int f, int64_t FT, int r, int rho, int P, int Q, int64_t *lo, int64_t *hi)
+{
+    const __int128 c_ref = (f == 2) ? r : 1;
+    const __int128 c_t = (f == 2) ? rho : 1;
+    const __int128 xt = (__int128)FT * star_area(r) * c_t;
+    const __int128 k = (__int128)Q * star_area(rho) * c_ref;
+    const __int128 lo_num = (__int128)(Q - P) * xt;
+    const __int128 hi_num = (__int128)(Q + P) * xt;
+    if (k == 0) {
+        // X_ref is 0 whatever F is
+        const bool ok = lo_num <= 0 && 0 <= hi_num;
+        *lo = ok ? INT64_MIN : 1;
+        *hi = ok ? INT64_MAX : 0;
+        return;
+    }
+    *lo = clamp64(-floor_div(-lo_num, k));
+    *hi = clamp64(floor_div(hi_num, k));
+}
+
+}  // namespace oss
+
+static int popc(uint32_t m) { return __builtin_popcount(m); }
+
+static bool desc_ok(const oss_image_desc *d)
+{
+    if (!d || d->H <= 0 || d->W <= 0)
+        return false;
+    if (d->dtype == OSS_U8) {
+        if (d->bit_depth < 1 || d->bit_depth > 8)
+            return false;
+    } else if (d->dtype == OSS_U16) {
+        if (d->bit_depth < 1 || d->bit_depth > 16)
+            return false;
+    } else {
+        return false;
+    }
+    const int64_t px = d->dtype == OSS_U8 ? 1 : 2;
+    if (d->pitch_bytes < (int64_t)d->W * px || d->pitch_bytes % px != 0)
+        return false;
+    return true;
+}
+
+static int hip_status(hipError_t e) { return e == hipSuccess ? OSS_OK : OSS_E_DEVICE; }
+
+extern "C" {
+
+const char *oss_status_string(int status)
+{
+    switch (status) {
+    case OSS_OK: return "OSS_OK";
+    case OSS_E_ARG: return "OSS_E_ARG";
+    case OSS_E_NOMEM: return "OSS_E_NOMEM";
+    case OSS_E_OVERFLOW: return "OSS_E_OVERFLOW";
+    case OSS_E_DEVICE: return "OSS_E_DEVICE";
+    case OSS_E_STATE: return "OSS_E_STATE";
+    default: return "OSS_E_UNKNOWN";
+    }
+}
+
+int oss_ctx_create(int device, oss_ctx **out)
+{
+    if (!out)
+        return OSS_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (device < 0 || device >= n)
+        return OSS_E_ARG;
+    if (hipSetDevice(device) != hipSuccess)
+        return OSS_E_DEVICE;
+    oss_ctx *c = new (std::nothrow) oss_ctx();
+    if (!c)
+        return OSS_E_NOMEM;
+    c->device = device;
+    for (auto &s : c->slots) {
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+            oss_ctx_destroy(c);
+            return OSS_E_DEVICE;
+        }
+    }
+    *out = c;
+    return OSS_OK;
+}
+
+int oss_ctx_destroy(oss_ctx *ctx)
+{
+    if (!ctx)
+        return OSS_E_ARG;
+    (void)hipSetDevice(ctx->device);
+    for (auto &s : ctx->slots) {
+        if (s.ev) {
+            if (s.used)
+                (void)hipEventSynchronize(s.ev);
+            (void)hipEventDestroy(s.ev);
+        }
+        if (s.host)
+            (void)hipHostFree(s.host);
+        if (s.dev)
+            (void)hipFree(s.dev);
+    }
+    if (ctx->bits)
+        (void)hipFree(ctx->bits);
+    if (ctx->cws)
+        (void)hipFree(ctx->cws);
+    delete ctx;
+    return OSS_OK;
+}
+
+// Device layout of a reference: 3 tables, 2 row-base arrays, 3 band
+// contribution arrays and 3 carry arrays, each 256-byte aligned.
+enum { A_L, A_R, A_RP, A_BPA, A_BPF, A_AGL, A_AGAD, A_AGD, A_CL, A_CAD, A_CD, A_COUNT };
+
+static size_t ref_layout(const BuildGeom &g, size_t off[A_COUNT])
+{
+    const size_t e = sizeof(int64_t) * (size_t)g.nq;
+    const size_t table = (size_t)(g.H + 1) * (size_t)g.pitch_e * e;
+    const size_t bpa = (size_t)g.H * g.nch_agg * e;
+    const size_t bpf = (size_t)g.H * g.nch_fin * e;
+    const size_t car = (size_t)g.nb * g.cw * e;
+    const size_t sizes[A_COUNT] = {table, table, table, bpa, bpf, car, car, car, car, car, car};
+    size_t acc = 0;
+    for (int i = 0; i < A_COUNT; ++i) {
+        off[i] = acc;
+        acc += (sizes[i] + 255) / 256 * 256;
+    }
+    return acc;
+}
+
+static bool overflow_ok(const oss_image_desc *d, uint32_t fm)
+{
+    const __int128 maxv = ((__int128)1 << d->bit_depth) - 1;
+    __int128 maxq = 0;
+    if (fm & OSS_F_SUM)
+        maxq = std::max(maxq, maxv);
+    if (fm & OSS_F_SQ)
+        maxq = std::max(maxq, maxv * maxv);
+    if (fm & OSS_F_GRAD)
+        maxq = std::max(maxq, 2 * maxv);
+    return (__int128)d->H * d->W * maxq < ((__int128)1 << 62);
+}
+
+int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, size_t *out)
+{
+    if (!out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+        return OSS_E_ARG;
+    const BuildGeom g = make_geom(desc->H, desc->W, popc(feat_mask));
+    size_t off[A_COUNT];
+    *out = ref_layout(g, off);
+    return OSS_OK;
+}
+
+int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask, oss_ref **out)
+{
+    if (!ctx || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+        return OSS_E_ARG;
+    *out = nullptr;
+    if (!overflow_ok(desc, feat_mask))
+        return OSS_E_OVERFLOW;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    oss_ref *r = new (std::nothrow) oss_ref();
+    if (!r)
+        return OSS_E_NOMEM;
+    r->ctx = ctx;
+    r->desc = *desc;
+    r->feat_mask = feat_mask;
+    r->geom = make_geom(desc->H, desc->W, popc(feat_mask));
+    size_t off[A_COUNT];
+    r->bytes = ref_layout(r->geom, off);
+    if (hipMalloc(&r->mem, r->bytes) != hipSuccess) {
+        delete r;
+        return OSS_E_NOMEM;
+    }
+    char *m = static_cast<char *>(r->mem);
+    auto at = [&](int i) { return reinterpret_cast<int64_t *>(m + off[i]); };
+    r->bb.L = at(A_L);
+    r->bb.R = at(A_R);
+    r->bb.Rp = at(A_RP);
+    r->bb.bp_agg = at(A_BPA);
+    r->bb.bp_fin = at(A_BPF);
+    r->bb.agg_L = at(A_AGL);
+    r->bb.agg_AD = at(A_AGAD);
+    r->bb.agg_D = at(A_AGD);
+    r->bb.c_L = at(A_CL);
+    r->bb.c_AD = at(A_CAD);
+    r->bb.c_D = at(A_CD);
+    *out = r;
+    return OSS_OK;
+}
+
+int oss_ref_build(oss_ref *ref, const void *dev_pixels, void *stream)
+{
+    if (!ref || !dev_pixels)
+        return OSS_E_ARG;
+    if (hipSetDevice(ref->ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    return hip_status(launch_build(ref->geom, dev_pixels, ref->desc.pitch_bytes, ref->desc.dtype,
+                                   ref->feat_mask, ref->bb, static_cast<hipStream_t>(stream)));
+}
+
+int oss_ref_release(oss_ref *ref)
+{
+    if (!ref)
+        return OSS_E_ARG;
+    (void)hipSetDevice(ref->ctx->device);
+    if (ref->mem)
+        (void)hipFree(ref->mem);
+    delete ref;
+    return OSS_OK;
+}
+
+int oss_ref_tables(const oss_ref *ref, const int64_t **L, const int64_t **R, const int64_t **Rp,
+                   int64_t *pitch_entries, int32_t *nq)
+{
+    if (!ref)
+        return OSS_E_ARG;
+    if (L)
+        *L = ref->bb.L;
+    if (R)
+        *R = ref->bb.R;
+    if (Rp)
+        *Rp = ref->bb.Rp;
+    if (pitch_entries)
+        *pitch_entries = ref->geom.pitch_e;
+    if (nq)
+        *nq = ref->geom.nq;
+    return OSS_OK;
+}
+
+// Template features on the host: star sums at the template centre, summed
+// row by row over the square's and the diamond's spans.
+int oss_template_features(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
+                          uint32_t feat_mask, oss_template_feat *out)
+{
+    if (!host_pixels || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+        return OSS_E_ARG;
+    const int H = desc->H, W = desc->W;
+    const int cx = (W - 1) / 2, cy = (H - 1) / 2;
+    const int rmax = std::min(std::min(cx, W - 1 - cx), std::min(cy, H - 1 - cy));
+    if (rho < 0)
+        rho = rmax - ((feat_mask & OSS_F_GRAD) ? 1 : 0);
+    if (rho < 0 || rho > rmax)
+        return OSS_E_ARG;
+    const unsigned char *base = static_cast<const unsigned char *>(host_pixels);
+    auto pix = [&](int x, int y) -> int64_t {
+        const unsigned char *row = base + (int64_t)y * desc->pitch_bytes;
+        if (desc->dtype == OSS_U8)
+            return row[x];
+        uint16_t v;
+        std::memcpy(&v, row + 2 * (int64_t)x, 2);
+        return v;
+    };
+    auto grad = [&](int x, int y) -> int64_t {
+        const int xr = std::min(x + 1, W - 1), xl = std::max(x - 1, 0);
+        const int yd = std::min(y + 1, H - 1), yu = std::max(y - 1, 0);
+        const int64_t gx = pix(xr, y) - pix(xl, y), gy = pix(x, yd) - pix(x, yu);
+        return (gx < 0 ? -gx : gx) + (gy < 0 ? -gy : gy);
+    };
+    int64_t f1 = 0, f2 = 0, fg = 0;
+    auto span = [&](int y, int x0, int x1) {
+        for (int x = x0; x <= x1; ++x) {
+            const int64_t v = pix(x, y);
+            f1 += v;
+            f2 += v * v;
+            if (feat_mask & OSS_F_GRAD)
+                fg += grad(x, y);
+        }
+    };
+    const int s = square_half(rho);
+    for (int dy = -s; dy <= s; ++dy)
+        span(cy + dy, cx - s, cx + s);
+    for (int dy = -rho; dy <= rho; ++dy) {
+        const int h = rho - (dy < 0 ? -dy : dy);
+        span(cy + dy, cx - h, cx + h);
+    }
+    out->F[0] = (feat_mask & OSS_F_SUM) ? f1 : 0;
+    out->F[1] = (feat_mask & OSS_F_SQ) ? f2 : 0;
+    out->F[2] = (feat_mask & OSS_F_GRAD) ? fg : 0;
+    out->rho = rho;
+    out->feat_mask = feat_mask;
+    return OSS_OK;
+}
+
+int oss_feature_bounds(int32_t feature, int64_t FT, int32_t r, int32_t rho,
+                       const oss_tolerance *tol, int64_t *lo, int64_t *hi)
+{
+    if (!tol || !lo || !hi || feature < 0 || feature > 2 || r < 0 || rho < 0 || tol->Q <= 0 ||
+        tol->P[feature] < 0)
+        return OSS_E_ARG;
+    feature_bounds(feature, FT, r, rho, tol->P[feature], tol->Q, lo, hi);
+    return OSS_OK;
+}
+
+}  // extern "C"
+
+// grow a device buffer (synchronising the device before freeing the old one)
+static int grow(void **p, size_t *cap, size_t need)
+{
+    if (*cap >= need)
+        return OSS_OK;
+    if (*p) {
+        if (hipDeviceSynchronize() != hipSuccess)
+            return OSS_E_DEVICE;
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    if (hipMalloc(p, need) != hipSuccess) {
+        *p = nullptr;
+        return OSS_E_NOMEM;
+    }
+    *cap = need;
+    return OSS_OK;
+}
+
+// copy `bytes` of host data to a device plan buffer through a pinned slot
+static int upload_plan(oss_ctx *ctx, const void *src, size_t bytes, hipStream_t st, PlanSlot **used)
+{
+    PlanSlot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % NSLOTS;
+    if (s.used && hipEventSynchronize(s.ev) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (s.cap < bytes) {
+        if (s.host)
+            (void)hipHostFree(s.host);
+        if (s.dev)
+            (void)hipFree(s.dev);
+        s.host = s.dev = nullptr;
+        s.cap = 0;
+        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess)
+            return OSS_E_NOMEM;
+        if (hipMalloc(&s.dev, bytes) != hipSuccess)
+            return OSS_E_NOMEM;
+        s.cap = bytes;
+    }
+    std::memcpy(s.host, src, bytes);
+    if (hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    *used = &s;
+    return OSS_OK;
+}
+
+// Build the per-template plans: distinct radii in increasing order, and for
+// each the probes with their exact feature-sum bounds in table slot order.
+static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                      const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+                      uint32_t fm, std::vector<DevTemplatePlan> &plans)
+{
+    plans.assign(n_tmpl, DevTemplatePlan{});
+    std::vector<std::vector<oss_probe>> per(n_tmpl);
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0)
+            return OSS_E_ARG;
+        per[p.template_id].push_back(p);
+        if ((int)per[p.template_id].size() > OSS_MAX_SCALES)
+            return OSS_E_ARG;
+    }
+    // feature f -> table slot (the reference's quantities in bit order)
+    int slot_of[3], slot = 0;
+    for (int f = 0; f < 3; ++f)
+        slot_of[f] = (ref->feat_mask & (1u << f)) ? slot++ : -1;
+    for (int t = 0; t < n_tmpl; ++t) {
+        auto &v = per[t];
+        std::stable_sort(v.begin(), v.end(),
+                         [](const oss_probe &a, const oss_probe &b) { return a.r < b.r; });
+        DevTemplatePlan &pl = plans[t];
+        int nr = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (nr == 0 || pl.radii[nr - 1].r != v[i].r) {
+                pl.radii[nr].r = v[i].r;
+                pl.radii[nr].s = square_half(v[i].r);
+                pl.radii[nr].first = (int32_t)i;
+                pl.radii[nr].count = 0;
+                ++nr;
+            }
+            pl.radii[nr - 1].count++;
+            DevProbe &dp = pl.probes[i];
+            dp.k = v[i].scale_id;
+            for (int q = 0; q < 3; ++q) {
+                dp.lo[q] = INT64_MIN;
+                dp.hi[q] = INT64_MAX;
+            }
+            for (int f = 0; f < 3; ++f) {
+                if (!(fm & (1u << f)))
+                    continue;
+                feature_bounds(f, tmpl[t].F[f], v[i].r, tmpl[t].rho, tol->P[f], tol->Q,
+                               &dp.lo[slot_of[f]], &dp.hi[slot_of[f]]);
+            }
+        }
+        pl.n_radii = nr;
+    }
+    return OSS_OK;
+}
+
+extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                          int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                          const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                          oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                          void *stream)
+{
+    if (!ctx || !ref || !tmpl || n_tmpl <= 0 || (n_probes > 0 && !probes) || n_probes < 0 || !tol ||
+        !dev_count || list_cap < 0 || (list_cap > 0 && !dev_list))
+        return OSS_E_ARG;
+    if (ref->ctx != ctx)
+        return OSS_E_STATE;
+    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask))
+        return OSS_E_ARG;
+    if (tol->Q <= 0)
+        return OSS_E_ARG;
+    for (int f = 0; f < 3; ++f)
+        if ((feat_mask & (1u << f)) && tol->P[f] < 0)
+            return OSS_E_ARG;
+    for (int t = 0; t < n_tmpl; ++t)
+        if ((tmpl[t].feat_mask & feat_mask) != feat_mask || tmpl[t].rho < 0)
+            return OSS_E_ARG;
+    std::vector<DevTemplatePlan> plans;
+    int rc = make_plans(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, plans);
+    if (rc != OSS_OK)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    const int64_t hw = (int64_t)g.H * g.W;
+    const int64_t n = hw * n_tmpl;
+    rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap, (size_t)n * sizeof(uint32_t));
+    if (rc != OSS_OK)
+        return rc;
+    rc = grow(&ctx->cws, &ctx->cws_cap, compact_workspace_bytes(n));
+    if (rc != OSS_OK)
+        return rc;
+    PlanSlot *slot = nullptr;
+    rc = upload_plan(ctx, plans.data(), plans.size() * sizeof(DevTemplatePlan), st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    const DevTemplatePlan *dplan = static_cast<const DevTemplatePlan *>(slot->dev);
+    for (int t = 0; t < n_tmpl; ++t) {
+        hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
+                                         ctx->bits + hw * t, st);
+        if (e != hipSuccess)
+            return OSS_E_DEVICE;
+    }
+    hipError_t e = launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap,
+                                  dev_count, ctx->cws, st);
+    if (e != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
+    return OSS_OK;
+}

@@ -1,0 +1,125 @@
+"""Convenience layer over the C ABI: owns the handles and the torch output
+tensors.  All computation happens in liboss.so."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class ScreenResult:
+    mask: "object"        # torch uint8 [T, H, W] on the device
+    cands: "object"       # torch int32 [cap, 4] (t, y, x, scale_bits as int32)
+    count: "object"       # torch int64 [1] on the device
+
+    def host(self):
+        """(mask ndarray, candidate ndarray [n, 4] int64, total count)."""
+        n = int(self.count.item())
+        c = self.cands[:min(n, self.cands.shape[0])].cpu().numpy().astype(np.int64)
+        if len(c):
+            c[:, 3] &= 0xFFFFFFFF
+        return self.mask.cpu().numpy(), c, n
+
+
+class Reference:
+    """Integral tables of one device-resident reference image."""
+
+    def __init__(self, ctx: "Context", image, feat_mask: int, bit_depth: int | None = None,
+                 stream=None, build: bool = True):
+        self.ctx = ctx
+        self.image = image
+        self.desc = L.desc_of(image, bit_depth)
+        self.feat_mask = int(feat_mask)
+        self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask)
+        if build:
+            self.build(stream)
+
+    @property
+    def H(self):
+        return self.desc.H
+
+    @property
+    def W(self):
+        return self.desc.W
+
+    def build(self, stream=None, image=None):
+        if image is not None:
+            self.image = image
+        L.oss_ref_build(self.handle, self.image, stream)
+
+    def release(self):
+        if self.handle:
+            L.oss_ref_release(self.handle)
+            self.handle = None
+
+    def tables_host(self):
+        """Copy (L, R, R') to host int64 arrays [H+1, W+1, nq] (synchronous;
+        for tests and inspection)."""
+        Lp, Rp_, Rpp, pitch, nq = L.oss_ref_tables(self.handle)
+        out = []
+        for p in (Lp, Rp_, Rpp):
+            a = np.empty((self.H + 1, pitch, nq), np.int64)
+            _hip_memcpy_d2h(a, p)
+            out.append(np.ascontiguousarray(a[:, :self.W + 1, :]))
+        return out
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = L.oss_ctx_create(device)
+
+    def reference(self, image, feat_mask: int = L.OSS_F_ALL, bit_depth: int | None = None,
+                  stream=None) -> Reference:
+        return Reference(self, image, feat_mask, bit_depth, stream)
+
+    def template_features(self, pixels, rho: int, feat_mask: int, bit_depth: int | None = None):
+        return L.oss_template_features(pixels, rho, feat_mask, bit_depth)
+
+    def screen(self, ref: Reference, templates, probes, tol, feat_mask: int,
+               list_cap: int | None = None, stream=None, out: ScreenResult | None = None,
+               with_mask: bool = True) -> ScreenResult:
+        """templates: list of oss_template_feat; probes: (t, k, r) triples;
+        tol: (P0, P1, P2, Q)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        T = len(templates)
+        if out is None:
+            cap = list_cap if list_cap is not None else max(1024, T * ref.H * ref.W // 50)
+            mask = (torch.empty((T, ref.H, ref.W), dtype=torch.uint8, device=dev)
+                    if with_mask else None)
+            cands = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=dev)
+            count = torch.zeros(1, dtype=torch.int64, device=dev)
+            out = ScreenResult(mask, cands, count)
+        cap = out.cands.shape[0] if list_cap is None else list_cap
+        L.oss_screen(self.handle, ref.handle, templates, probes, tol, feat_mask, out.mask,
+                     out.cands, cap, out.count, stream)
+        return out
+
+    def close(self):
+        if self.handle:
+            L.oss_ctx_destroy(self.handle)
+            self.handle = None
+
+
+_hip = None
+
+
+def _hip_memcpy_d2h(dst: np.ndarray, src_ptr: int):
+    """hipMemcpy device -> host of dst.nbytes bytes (blocking)."""
+    global _hip
+    import ctypes as C
+    if _hip is None:
+        import torch  # noqa: F401  (binds to torch's runtime by soname)
+        _hip = C.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipDeviceSynchronize.restype = C.c_int
+    if _hip.hipDeviceSynchronize() != 0:
+        raise RuntimeError("hipDeviceSynchronize failed")
+    rc = _hip.hipMemcpy(dst.ctypes.data, src_ptr, dst.nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")

@@ -1,0 +1,121 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+and its host-only calls (status names, footprints, template features, exact
+feature bounds, argument errors) agree with the oracle.  No GPU call is made."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle.core as oc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1707_05647_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1707_05647_amd import build
+        build.build()
+    return L
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "oss.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int)\s*(oss_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 11, names
+    raw = C.CDLL(lib.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(lib.EXPORTED)
+
+
+def test_status_strings(lib):
+    assert lib.status_string(0) == "OSS_OK"
+    assert lib.status_string(-1) == "OSS_E_ARG"
+    assert lib.status_string(-3) == "OSS_E_OVERFLOW"
+
+
+def test_ref_bytes(lib):
+    d = lib.image_desc(4096, 4096)
+    b3 = lib.oss_ref_bytes(d, 7)
+    b1 = lib.oss_ref_bytes(d, 1)
+    tables = 3 * 4097 * 4112 * 8
+    assert b1 >= tables and b3 >= 3 * tables
+    assert b3 < 3 * tables * 1.2
+    with pytest.raises(lib.OssError):
+        lib.oss_ref_bytes(lib.image_desc(0, 10), 7)
+    with pytest.raises(lib.OssError):
+        lib.oss_ref_bytes(d, 8)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_template_features_match_oracle(lib, seed):
+    rng = np.random.default_rng(seed)
+    h, w = int(rng.integers(3, 40)), int(rng.integers(3, 40))
+    depth = 8 if seed % 2 == 0 else 12
+    img = rng.integers(0, 2 ** depth, (h, w)).astype(np.uint8 if depth == 8 else np.uint16)
+    rmax = min((w - 1) // 2, w - 1 - (w - 1) // 2, (h - 1) // 2, h - 1 - (h - 1) // 2)
+    for rho in range(0, rmax + 1):
+        want = oc.template_features(img, rho)
+        for fm in (1, 2, 3, 4, 7):
+            got = lib.oss_template_features(img, rho, fm, bit_depth=depth)
+            for f in range(3):
+                assert got.F[f] == (want[f] if fm & (1 << f) else 0), (rho, fm, f)
+            assert got.rho == rho
+    # rho < 0 picks the largest fitting radius, one less with the gradient
+    assert lib.oss_template_features(img, -1, 3).rho == rmax
+    if rmax >= 1:
+        assert lib.oss_template_features(img, -1, 7).rho == rmax - 1
+    with pytest.raises(lib.OssError):
+        lib.oss_template_features(img, rmax + 1, 7)
+
+
+def test_template_features_strided(lib):
+    rng = np.random.default_rng(3)
+    big = rng.integers(0, 256, (40, 64)).astype(np.uint8)
+    view = big[3:36, 5:38]  # non-contiguous rows
+    got = lib.oss_template_features(np.ascontiguousarray(view), 16, 7)
+    want = oc.template_features(view, 16)
+    assert list(got.F) == list(want)
+
+
+def test_feature_bounds_match_cross_multiplied_compare(lib):
+    """lo <= F <= hi holds exactly when the oracle's cross-multiplied test passes."""
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        f = int(rng.integers(0, 3))
+        r, rho = int(rng.integers(0, 200)), int(rng.integers(0, 200))
+        FT = int(rng.integers(0, 10 ** int(rng.integers(1, 12))))
+        P, Q = int(rng.integers(0, 150)), int(rng.integers(1, 101))
+        Pv = [0, 0, 0]
+        Pv[f] = P
+        lo, hi = lib.oss_feature_bounds(f, FT, r, rho, Pv, Q)
+        cands = {lo - 1, lo, lo + 1, hi - 1, hi, hi + 1, 0, FT}
+        for F in cands:
+            if F < 0 or F >= 2 ** 62:
+                continue
+            want = oc.feature_pass(f, F, FT, r, rho, P, Q)
+            assert (lo <= F <= hi) == want, (f, F, FT, r, rho, P, Q, lo, hi)
+
+
+def test_screen_argument_errors_before_any_launch(lib):
+    L = lib.load()
+    tol = lib.tolerance((1, 1, 1), 20)
+    tm = (lib.oss_template_feat * 1)()
+    pr = (lib.oss_probe * 1)(lib.oss_probe(0, 0, 4))
+    # null context / reference / count
+    assert L.oss_screen(None, None, tm, 1, pr, 1, C.byref(tol), 7, None, None, 0, None,
+                        None) == lib.OSS_E_ARG
+    bad = lib.tolerance((1, 1, 1), 0)
+    assert L.oss_screen(None, None, tm, 1, pr, 1, C.byref(bad), 7, None, None, 0, None,
+                        None) == lib.OSS_E_ARG
+    assert L.oss_ref_create(None, None, 7, None) == lib.OSS_E_ARG
+    assert L.oss_ref_build(None, None, None) == lib.OSS_E_ARG

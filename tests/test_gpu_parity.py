@@ -1,0 +1,168 @@
+"""GPU parity: the HIP tables and the screen, bit for bit against the numpy
+definitions and the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle.core as oc
+from gpu_util import Runner, bits_from_list, say, tables_numpy
+from synth import blob_image, cut_patch, make_rng, make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def runner():
+    r = Runner()
+    yield r
+    r.close()
+
+
+TABLE_CASES = [
+    # (H, W, depth, feature mask, pitch padding)
+    (37, 53, 8, 7, 0),
+    (1, 1, 8, 7, 0),
+    (5, 700, 8, 3, 0),       # two final-pass tiles across
+    (129, 100, 12, 7, 0),    # a partial last band
+    (33, 1000, 8, 5, 13),    # three tiles across, pitch > width
+    (70, 450, 8, 4, 0),
+    (64, 64, 16, 2, 0),      # full 16-bit squares
+]
+
+
+@pytest.mark.parametrize("case", TABLE_CASES, ids=lambda c: "x".join(map(str, c)))
+def test_tables_match_definitions(runner, case):
+    H, W, depth, fm, pad = case
+    rng = np.random.default_rng(H * 1000 + W)
+    dt = np.uint8 if depth == 8 else np.uint16
+    img = rng.integers(0, 2 ** depth, (H, W)).astype(dt)
+    torch = runner.torch
+    say(f"tables {case}")
+    if pad:
+        wide = np.zeros((H, W + pad), dt)
+        wide[:, :W] = img
+        t_img = runner.L.device_image(wide, runner.dev)[:, :W]
+    else:
+        t_img = runner.L.device_image(img, runner.dev)
+    ref = runner.ctx.reference(t_img, fm, depth)
+    torch.cuda.synchronize()
+    got = ref.tables_host()
+    ref.release()
+    want = tables_numpy(img, fm)
+    for name, g, w in zip(("L", "R", "R'"), got, want):
+        assert np.array_equal(g, w), (name, np.argwhere(g != w)[:5])
+
+
+def _screen_and_compare(runner, w, **kw):
+    tm = [(t.pixels, t.rho) for t in w.templates]
+    P, Q = w.tol_P, w.tol_Q
+    say(f"screen workload {w.cfg_id} {w.H}x{w.W} T={len(tm)} probes={len(w.probes)} {kw}")
+    mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, P, Q,
+                                   bit_depth=w.depth, **kw)
+    want = oc.screen_full(w.ref, tm, w.probes, w.feat_mask, P, Q)
+    wmask, wlist = oc.mask_and_list(want)
+    assert n == len(wlist)
+    assert np.array_equal(mask, wmask)
+    assert np.array_equal(cands, wlist)
+    return want
+
+
+def test_cfg1_full(runner):
+    w = make_workload(1, 0)
+    want = _screen_and_compare(runner, w)
+    t = w.templates[0]
+    assert want[0, t.cy, t.cx] == 1  # exact cut: always survives
+
+
+def test_cfg2_small_full(runner):
+    w = make_workload(2, 0, H=256, blobs_per_512sq=800, sig_hi=24)
+    _screen_and_compare(runner, w)
+
+
+def test_cfg2_ragged_pitch(runner):
+    w = make_workload(2, 1, H=211, W=333, blobs_per_512sq=800, sig_hi=24)
+    _screen_and_compare(runner, w, pitch_pad=7)
+
+
+def test_cfg3_small_full(runner):
+    w = make_workload(3, 0, H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20)
+    _screen_and_compare(runner, w)
+
+
+def test_cfg5_small_full(runner):
+    w = make_workload(5, 0, H=224, W=240, n_templates=3, blobs_per_512sq=1200, sig_hi=20)
+    _screen_and_compare(runner, w)
+
+
+def test_single_valid_position_and_empty(runner):
+    rng = make_rng(7, 0)
+    img = blob_image(21, 21, rng, blobs_per_512sq=4000, sig_hi=6)
+    tm = [(cut_patch(img, 10, 10, 10), 9)]
+    probes = [(0, 0, 10), (0, 1, 11), (0, 2, 3)]
+    mask, cands, n = runner.screen(img, tm, probes, 7, (100, 100, 100), 100)
+    want = oc.screen_full(img, tm, probes, 7, (100, 100, 100), 100)
+    assert np.array_equal(cands, oc.mask_and_list(want)[1])
+    assert not (want & 2).any()
+    # no valid position at all
+    mask, cands, n = runner.screen(img, tm, [(0, 0, 11)], 7, (100, 100, 100), 100)
+    assert n == 0 and not mask.any()
+
+
+def test_list_truncation(runner):
+    w = make_workload(2, 2, H=128, blobs_per_512sq=800, sig_hi=24)
+    tm = [(t.pixels, t.rho) for t in w.templates]
+    P = (100, 100, 100)
+    mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, P, 100)
+    assert n > 100
+    m2, c2, n2 = runner.screen(w.ref, tm, w.probes, w.feat_mask, P, 100, list_cap=100)
+    assert n2 == n and np.array_equal(c2, cands[:100]) and np.array_equal(m2, mask)
+
+
+@pytest.mark.parametrize("depth", [8, 12, 16])
+def test_overflow_edge_constant_max(runner, depth):
+    """All pixels at the maximum value, largest radius: exact sums c*A(r),
+    c^2*A(r), 0 pass at P = 0 everywhere the star fits."""
+    H = W = 129
+    c = 2 ** depth - 1
+    img = np.full((H, W), c, np.uint8 if depth == 8 else np.uint16)
+    tm = [(np.full((131, 131), c, img.dtype), 64)]
+    probes = [(0, 0, 64), (0, 1, 63)]
+    mask, cands, n = runner.screen(img, tm, probes, 7, (0, 0, 0), 1, bit_depth=depth)
+    want = oc.screen_full(img, tm, probes, 7, (0, 0, 0), 1)
+    assert np.array_equal(cands, oc.mask_and_list(want)[1])
+    assert want[0, 64, 64] == 3 and n == 9
+
+
+def test_deterministic(runner):
+    w = make_workload(3, 3, H=160, n_templates=3, blobs_per_512sq=1200, sig_hi=20)
+    tm = [(t.pixels, t.rho) for t in w.templates]
+    a = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q)
+    b = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q)
+    assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_cfg2_full_size_sampled(runner):
+    """The benchmark workload at full size (4096^2, 7 radii): every sampled
+    position bit-exact against the oracle; properties that hold everywhere."""
+    w = make_workload(2, 0)
+    tm = [(t.pixels, t.rho) for t in w.templates]
+    say("cfg2 full size: screening 4096^2")
+    mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q,
+                                   list_cap=4 << 20)
+    assert n == len(cands) == int(mask.sum())
+    key = (cands[:, 0] * w.H + cands[:, 1]) * w.W + cands[:, 2]
+    assert (np.diff(key) > 0).all()
+    assert (mask[0, cands[:, 1], cands[:, 2]] == 1).all() and (cands[:, 3] != 0).all()
+    bits = bits_from_list(cands, 1, w.H, w.W)
+    rng = np.random.default_rng(0)
+    t = w.templates[0]
+    xs = np.concatenate([rng.integers(0, w.W, 3000), [t.cx, 16, w.W - 17, 64, w.W - 65, 0]])
+    ys = np.concatenate([rng.integers(0, w.H, 3000), [t.cy, 16, w.H - 17, 64, w.H - 65, 0]])
+    # plus a band of candidates
+    sel = cands[:: max(1, len(cands) // 500)]
+    xs = np.concatenate([xs, sel[:, 2]]).astype(np.int32)
+    ys = np.concatenate([ys, sel[:, 1]]).astype(np.int32)
+    say(f"cfg2 full size: oracle on {len(xs)} sampled positions")
+    want = oc.screen_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q, xs, ys)
+    assert np.array_equal(bits[0, ys, xs], want[0])
+    # the planted template survives at its true radius (32 = scale id 2)
+    assert bits[0, t.cy, t.cx] & (1 << 2)
