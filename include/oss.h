@@ -123,6 +123,24 @@ typedef struct oss_candidate {
 int oss_ctx_create(int device, oss_ctx **out);
 int oss_ctx_destroy(oss_ctx *ctx);
 
+/* Timing of one kernel over the launches recorded since profiling was
+ * (re)enabled. */
+typedef struct oss_kernel_stat {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double max_ms;
+} oss_kernel_stat;
+
+/* enable != 0: clear the statistics and record a HIP event pair around every
+ * kernel this context (or a reference created on it) launches, on the
+ * launch stream.  enable == 0: stop recording (statistics are kept). */
+int oss_ctx_profile(oss_ctx *ctx, int enable);
+
+/* Wait for the recorded events and return one entry per kernel that ran:
+ * up to `cap` entries in out, the number written in *n. */
+int oss_ctx_profile_read(oss_ctx *ctx, oss_kernel_stat *out, int32_t cap, int32_t *n);
+
 /* Static name of a status code ("OSS_OK", "OSS_E_ARG", ...). */
 const char *oss_status_string(int status);
 

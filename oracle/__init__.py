@@ -13,6 +13,7 @@ the star's pixel sets, used on tiny inputs to pin the C code.
 """
 from .core import (  # noqa: F401
     build,
+    threads,
     square_half,
     star_weight,
     star_area,

@@ -43,6 +43,8 @@ def _declare(lib):
     i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
     u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
     u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = C.c_int
     lib.oracle_square_half.argtypes = [C.c_int]
     lib.oracle_square_half.restype = C.c_int
     lib.oracle_star_weight.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -79,6 +81,11 @@ def _img16(img) -> np.ndarray:
     if a.ndim != 2 or a.dtype not in (np.uint8, np.uint16):
         raise ValueError("image must be a 2-D uint8 or uint16 array")
     return np.ascontiguousarray(a, dtype=np.uint16)
+
+
+def threads(lib=None) -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int((lib or load()).oracle_threads())
 
 
 def square_half(r: int, lib=None) -> int:

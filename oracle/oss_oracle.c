@@ -33,8 +33,21 @@
  */
 #include <stdint.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef __int128 i128;
+
+/* Number of threads the parallel loops below use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Square half-width congruent with the radius-r diamond. */
 int oracle_square_half(int r)

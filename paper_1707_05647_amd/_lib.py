@@ -23,7 +23,7 @@ OSS_MAX_SCALES = 32
 EXPORTED = [
     "oss_ctx_create", "oss_ctx_destroy", "oss_status_string", "oss_ref_bytes", "oss_ref_create",
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
-    "oss_feature_bounds", "oss_screen",
+    "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
 ]
 
 
@@ -46,6 +46,11 @@ class oss_tolerance(C.Structure):
 
 class oss_candidate(C.Structure):
     _fields_ = [("t", C.c_int32), ("y", C.c_int32), ("x", C.c_int32), ("scale_bits", C.c_uint32)]
+
+
+class oss_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("max_ms", C.c_double)]
 
 
 class OssError(RuntimeError):
@@ -84,6 +89,8 @@ def load(path: str | None = None):
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
                                        C.POINTER(i64), C.POINTER(i64)]
+    lib.oss_ctx_profile.argtypes = [vp, C.c_int]
+    lib.oss_ctx_profile_read.argtypes = [vp, C.POINTER(oss_kernel_stat), i32, C.POINTER(i32)]
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
     for name in EXPORTED:
@@ -161,6 +168,19 @@ def oss_ctx_create(device: int = 0) -> int:
 
 def oss_ctx_destroy(ctx: int):
     _check(load().oss_ctx_destroy(ctx), "oss_ctx_destroy")
+
+
+def oss_ctx_profile(ctx: int, enable: bool):
+    _check(load().oss_ctx_profile(ctx, 1 if enable else 0), "oss_ctx_profile")
+
+
+def oss_ctx_profile_read(ctx: int) -> dict:
+    """{kernel name: (launches, total_ms, max_ms)} (waits for the events)."""
+    arr = (oss_kernel_stat * 32)()
+    n = C.c_int32()
+    _check(load().oss_ctx_profile_read(ctx, arr, 32, C.byref(n)), "oss_ctx_profile_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].max_ms)
+            for i in range(n.value)}
 
 
 def oss_ref_bytes(desc: oss_image_desc, feat_mask: int) -> int:

@@ -31,6 +31,7 @@ struct oss_ctx {
     size_t cws_cap = 0;        // bytes
     PlanSlot slots[NSLOTS];
     int next_slot = 0;
+    Profiler prof;
 };
 
 struct oss_ref {
@@ -168,6 +169,8 @@ int oss_ctx_destroy(oss_ctx *ctx)
     if (!ctx)
         return OSS_E_ARG;
     (void)hipSetDevice(ctx->device);
+    ctx->prof.on = false;
+    (void)ctx->prof.resolve();
     for (auto &s : ctx->slots) {
         if (s.ev) {
             if (s.used)
@@ -276,7 +279,8 @@ int oss_ref_build(oss_ref *ref, const void *dev_pixels, void *stream)
     if (hipSetDevice(ref->ctx->device) != hipSuccess)
         return OSS_E_DEVICE;
     return hip_status(launch_build(ref->geom, dev_pixels, ref->desc.pitch_bytes, ref->desc.dtype,
-                                   ref->feat_mask, ref->bb, static_cast<hipStream_t>(stream)));
+                                   ref->feat_mask, ref->bb, static_cast<hipStream_t>(stream),
+                                   &ref->ctx->prof));
 }
 
 int oss_ref_release(oss_ref *ref)
@@ -359,6 +363,46 @@ int oss_template_features(const void *host_pixels, const oss_image_desc *desc, i
     out->F[2] = (feat_mask & OSS_F_GRAD) ? fg : 0;
     out->rho = rho;
     out->feat_mask = feat_mask;
+    return OSS_OK;
+}
+
+int oss_ctx_profile(oss_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return OSS_E_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (enable) {
+        ctx->prof.clear();
+        ctx->prof.on = true;
+    } else {
+        ctx->prof.on = false;
+    }
+    return OSS_OK;
+}
+
+int oss_ctx_profile_read(oss_ctx *ctx, oss_kernel_stat *out, int32_t cap, int32_t *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !out))
+        return OSS_E_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (ctx->prof.resolve() != hipSuccess)
+        return OSS_E_DEVICE;
+    int32_t k = 0;
+    for (int i = 0; i < K_COUNT; ++i) {
+        if (ctx->prof.launches[i] == 0)
+            continue;
+        if (k < cap) {
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, kKernelNames[i], sizeof(out[k].name) - 1);
+            out[k].launches = ctx->prof.launches[i];
+            out[k].total_ms = ctx->prof.total_ms[i];
+            out[k].max_ms = ctx->prof.max_ms[i];
+        }
+        ++k;
+    }
+    *n = k < cap ? k : cap;
     return OSS_OK;
 }
 
@@ -519,12 +563,12 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     const DevTemplatePlan *dplan = static_cast<const DevTemplatePlan *>(slot->dev);
     for (int t = 0; t < n_tmpl; ++t) {
         hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
-                                         ctx->bits + hw * t, st);
+                                         ctx->bits + hw * t, st, &ctx->prof);
         if (e != hipSuccess)
             return OSS_E_DEVICE;
     }
     hipError_t e = launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap,
-                                  dev_count, ctx->cws, st);
+                                  dev_count, ctx->cws, st, &ctx->prof);
     if (e != hipSuccess)
         return OSS_E_DEVICE;
     if (hipEventRecord(slot->ev, st) != hipSuccess)

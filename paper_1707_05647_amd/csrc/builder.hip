@@ -396,47 +396,61 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const int64_t *
 
 template <typename Pix, unsigned FM>
 static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_bytes,
-                          const BuildBuffers &bb, hipStream_t st)
+                          const BuildBuffers &bb, hipStream_t st, Profiler *prof)
 {
     constexpr int NQ = Feat<FM>::NQ;
     const Pix *img = static_cast<const Pix *>(pixels);
     const int64_t pitch = pitch_bytes / (int64_t)sizeof(Pix);
-    hipLaunchKernelGGL((row_base_kernel<Pix, FM>), dim3(g.H), dim3(ROWBASE_THREADS), 0, st, img,
-                       pitch, g, bb.bp_agg, bb.bp_fin);
-    hipLaunchKernelGGL((band_kernel<Pix, FM, false>), dim3(g.nch_agg, g.nb), dim3(BAND_THREADS), 0,
-                       st, img, pitch, g, bb.bp_agg, nullptr, nullptr, nullptr, bb.agg_L,
-                       bb.agg_AD, bb.agg_D);
-    const int span = (g.nb - 1) * KBAND;
-    const int lines = g.cw + span;
-    hipLaunchKernelGGL((carry_kernel<NQ>), dim3((lines + 255) / 256, 3), dim3(256), 0, st, g,
-                       bb.agg_L, bb.agg_AD, bb.agg_D, bb.c_L, bb.c_AD, bb.c_D);
-    hipLaunchKernelGGL((band_kernel<Pix, FM, true>), dim3(g.nch_fin, g.nb), dim3(BAND_THREADS), 0,
-                       st, img, pitch, g, bb.bp_fin, bb.c_L, bb.c_AD, bb.c_D, bb.L, bb.R, bb.Rp);
+    {
+        ProfScope ps(prof, K_ROW_BASE, st);
+        hipLaunchKernelGGL((row_base_kernel<Pix, FM>), dim3(g.H), dim3(ROWBASE_THREADS), 0, st,
+                           img, pitch, g, bb.bp_agg, bb.bp_fin);
+    }
+    {
+        ProfScope ps(prof, K_BAND_AGG, st);
+        hipLaunchKernelGGL((band_kernel<Pix, FM, false>), dim3(g.nch_agg, g.nb),
+                           dim3(BAND_THREADS), 0, st, img, pitch, g, bb.bp_agg, nullptr, nullptr,
+                           nullptr, bb.agg_L, bb.agg_AD, bb.agg_D);
+    }
+    {
+        ProfScope ps(prof, K_CARRY, st);
+        const int span = (g.nb - 1) * KBAND;
+        const int lines = g.cw + span;
+        hipLaunchKernelGGL((carry_kernel<NQ>), dim3((lines + 255) / 256, 3), dim3(256), 0, st, g,
+                           bb.agg_L, bb.agg_AD, bb.agg_D, bb.c_L, bb.c_AD, bb.c_D);
+    }
+    {
+        ProfScope ps(prof, K_BAND_FINAL, st);
+        hipLaunchKernelGGL((band_kernel<Pix, FM, true>), dim3(g.nch_fin, g.nb), dim3(BAND_THREADS),
+                           0, st, img, pitch, g, bb.bp_fin, bb.c_L, bb.c_AD, bb.c_D, bb.L, bb.R,
+                           bb.Rp);
+    }
     return hipGetLastError();
 }
 
 template <typename Pix>
 static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint32_t fm,
-                            const BuildBuffers &bb, hipStream_t st)
+                            const BuildBuffers &bb, hipStream_t st, Profiler *pr)
 {
     switch (fm) {
-    case 1: return build_t<Pix, 1>(g, px, pb, bb, st);
-    case 2: return build_t<Pix, 2>(g, px, pb, bb, st);
-    case 3: return build_t<Pix, 3>(g, px, pb, bb, st);
-    case 4: return build_t<Pix, 4>(g, px, pb, bb, st);
-    case 5: return build_t<Pix, 5>(g, px, pb, bb, st);
-    case 6: return build_t<Pix, 6>(g, px, pb, bb, st);
-    case 7: return build_t<Pix, 7>(g, px, pb, bb, st);
+    case 1: return build_t<Pix, 1>(g, px, pb, bb, st, pr);
+    case 2: return build_t<Pix, 2>(g, px, pb, bb, st, pr);
+    case 3: return build_t<Pix, 3>(g, px, pb, bb, st, pr);
+    case 4: return build_t<Pix, 4>(g, px, pb, bb, st, pr);
+    case 5: return build_t<Pix, 5>(g, px, pb, bb, st, pr);
+    case 6: return build_t<Pix, 6>(g, px, pb, bb, st, pr);
+    case 7: return build_t<Pix, 7>(g, px, pb, bb, st, pr);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_bytes, int dtype,
-                        uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream)
+                        uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
+                        Profiler *prof)
 {
     if (dtype == OSS_U8)
-        return build_pix<uint8_t>(g, pixels, pitch_bytes, feat_mask, bb, stream);
-    return build_pix<uint16_t>(g, pixels, pitch_bytes, feat_mask, bb, stream);
+        return build_pix<uint8_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
+    return build_pix<uint16_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
 }
 
 }  // namespace oss

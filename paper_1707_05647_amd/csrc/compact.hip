@@ -140,19 +140,28 @@ size_t compact_workspace_bytes(int64_t n)
 
 hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
                           oss_candidate *list, int64_t list_cap, int64_t *count, void *workspace,
-                          hipStream_t stream)
+                          hipStream_t stream, Profiler *prof)
 {
     const int64_t hw = (int64_t)H * W;
     const int64_t n = n_tmpl * hw;
     const int64_t nseg = (n + CSEG - 1) / CSEG;
     int64_t *seg_count = static_cast<int64_t *>(workspace);
     int64_t *seg_off = seg_count + nseg;
-    hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)nseg), dim3(CTHREADS), 0, stream, bits,
-                       n, seg_count);
-    hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(SCAN_THREADS), 0, stream, seg_count,
-                       nseg, seg_off, count);
-    hipLaunchKernelGGL(compact_write_kernel, dim3((unsigned)nseg), dim3(CTHREADS), 0, stream, bits,
-                       n, hw, W, seg_off, mask, list, list ? list_cap : 0);
+    {
+        ProfScope ps(prof, K_COMPACT_COUNT, stream);
+        hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)nseg), dim3(CTHREADS), 0, stream,
+                           bits, n, seg_count);
+    }
+    {
+        ProfScope ps(prof, K_COMPACT_SCAN, stream);
+        hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(SCAN_THREADS), 0, stream, seg_count,
+                           nseg, seg_off, count);
+    }
+    {
+        ProfScope ps(prof, K_COMPACT_WRITE, stream);
+        hipLaunchKernelGGL(compact_write_kernel, dim3((unsigned)nseg), dim3(CTHREADS), 0, stream,
+                           bits, n, hw, W, seg_off, mask, list, list ? list_cap : 0);
+    }
     return hipGetLastError();
 }
 

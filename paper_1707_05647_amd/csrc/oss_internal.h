@@ -72,6 +72,49 @@ int square_half(int r);
 int64_t star_area(int r);
 
 // ---------------------------------------------------------------------------
+// Per-kernel timing with HIP events recorded on the launch stream.
+// ---------------------------------------------------------------------------
+enum KernelId {
+    K_ROW_BASE,
+    K_BAND_AGG,
+    K_CARRY,
+    K_BAND_FINAL,
+    K_STAR,
+    K_COMPACT_COUNT,
+    K_COMPACT_SCAN,
+    K_COMPACT_WRITE,
+    K_COUNT
+};
+extern const char *const kKernelNames[K_COUNT];
+
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[K_COUNT] = {};
+    double total_ms[K_COUNT] = {};
+    double max_ms[K_COUNT] = {};
+    void clear();
+    hipError_t resolve();  // waits for the recorded events and accumulates
+    ~Profiler();
+};
+
+// Records a start event on construction and a stop event on destruction
+// when profiling is on.
+struct ProfScope {
+    Profiler *p;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    int id;
+    ProfScope(Profiler *p_, int id_, hipStream_t st_);
+    ~ProfScope();
+};
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (asynchronous, on `stream`).
 // ---------------------------------------------------------------------------
 struct BuildBuffers {
@@ -82,16 +125,17 @@ struct BuildBuffers {
 };
 
 hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_bytes, int dtype,
-                        uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream);
+                        uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
+                        Profiler *prof);
 
 hipError_t launch_star_plain(const BuildGeom &g, const int64_t *L, const int64_t *R,
                              const int64_t *Rp, const DevTemplatePlan *plan, uint32_t *bits,
-                             hipStream_t stream);
+                             hipStream_t stream, Profiler *prof);
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);
 hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
                           oss_candidate *list, int64_t list_cap, int64_t *count, void *workspace,
-                          hipStream_t stream);
+                          hipStream_t stream, Profiler *prof);
 
 }  // namespace oss

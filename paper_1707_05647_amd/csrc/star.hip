@@ -95,8 +95,9 @@ __global__ __launch_bounds__(STAR_THREADS) void star_plain_kernel(
 
 hipError_t launch_star_plain(const BuildGeom &g, const int64_t *L, const int64_t *R,
                              const int64_t *Rp, const DevTemplatePlan *plan, uint32_t *bits,
-                             hipStream_t stream)
+                             hipStream_t stream, Profiler *prof)
 {
+    ProfScope ps(prof, K_STAR, stream);
     const int tiles_x = (g.W + STAR_THREADS - 1) / STAR_THREADS;
     const int n_tiles = tiles_x * g.H;
     const int nblk = (n_tiles + 7) / 8 * 8;

@@ -73,8 +73,8 @@ class Context:
         self.handle = L.oss_ctx_create(device)
 
     def reference(self, image, feat_mask: int = L.OSS_F_ALL, bit_depth: int | None = None,
-                  stream=None) -> Reference:
-        return Reference(self, image, feat_mask, bit_depth, stream)
+                  stream=None, build: bool = True) -> Reference:
+        return Reference(self, image, feat_mask, bit_depth, stream, build)
 
     def template_features(self, pixels, rho: int, feat_mask: int, bit_depth: int | None = None):
         return L.oss_template_features(pixels, rho, feat_mask, bit_depth)
