@@ -55,9 +55,9 @@ def pixel_scales(H, W, probes):
     return sum(max(0, H - 2 * r) * max(0, W - 2 * r) for _, _, r in probes)
 
 
-def algorithmic_bytes(H, W, nq, n_tmpl, px_bytes):
+def algorithmic_bytes(H, W, nq, n_tmpl, px_bytes, value_bytes):
     """Minimum HBM bytes per launch of each kernel."""
-    table = 3 * (H + 1) * (W + 1) * nq * 8
+    table = 3 * (H + 1) * (W + 1) * nq * value_bytes
     hw = H * W
     return {
         # writes every table entry once, reads the image once
@@ -160,7 +160,7 @@ def main():
     stream = torch.cuda.current_stream()
     img = L.device_image(w.ref, dev)
     ctx = Context(0)
-    ref = ctx.reference(img, w.feat_mask, 8, build=False)
+    ref = ctx.reference(img, w.feat_mask, 8, build=False, max_radius=max(w.radii()))
     T = len(w.templates)
     cap = 1 << 22
     mask = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
@@ -191,7 +191,7 @@ def main():
     ps = pixel_scales(w.H, w.W, w.probes)
     value = ps * args.steps / elapsed / 1e9
     n = int(count.item())
-    abytes = algorithmic_bytes(w.H, w.W, 3, T, 1)
+    abytes = algorithmic_bytes(w.H, w.W, 3, T, 1, ref.value_bits // 8)
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
             for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
@@ -230,6 +230,7 @@ def main():
             "H": w.H, "W": w.W, "radii": w.radii(), "templates": T,
             "tolerance_P_over_Q": [p / w.tol_Q for p in w.tol_P], "seed": args.seed,
             "pixel_scales_per_step": ps,
+            "table_value_bits": ref.value_bits,
         },
         "roofline": roof,
         "kernels": kern,

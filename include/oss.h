@@ -144,10 +144,12 @@ int oss_ctx_profile_read(oss_ctx *ctx, oss_kernel_stat *out, int32_t cap, int32_
 /* Static name of a status code ("OSS_OK", "OSS_E_ARG", ...). */
 const char *oss_status_string(int status);
 
-/* Device bytes oss_ref_create would allocate for an image of this shape and
- * feature set: the three integer tables per feature (below) plus the
- * builder's carry workspace.  Used for admission by footprint. */
-int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, size_t *out);
+/* Device bytes oss_ref_create would allocate for an image of this shape,
+ * feature set and maximum radius: the three integral tables per feature
+ * (below) plus the builder's carry workspace.  Used for admission by
+ * footprint. */
+int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_radius,
+                  size_t *out);
 
 /*
  * Allocate the integral tables of one reference image (Sec. "Patch
@@ -160,11 +162,20 @@ int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, size_t *out);
  *   R'(x,y) = R with the apex moved to the pixel corner (x+1/2, y+1/2):
  *             sum over j <= y, x-(y-j) <= i <= x+1+(y-j)
  * so that square sums take 4 lookups into L (Eq. S_1) and diamond sums 4
- * lookups into R and R'.  Tables are int64, one entry per (x, y) holding
- * the quantities in feature-bit order.  Returns OSS_E_OVERFLOW if
- * H * W * max(q) could exceed 2^62.
+ * lookups into R and R'.  One table entry holds the quantities of (x, y) in
+ * feature-bit order.
+ *
+ * max_radius is the largest probe radius this reference will be screened
+ * with (< 0: the largest star that fits the image); screens with a larger
+ * radius are rejected.  It fixes the value width: when every square and
+ * every diamond sum of every quantity up to max_radius is provably below
+ * 2^32 (from bit_depth), the tables are stored modulo 2^32 in 32-bit
+ * words and each region sum is still exact; otherwise they are int64.
+ * Feature sums and comparisons are int64 either way.  Returns
+ * OSS_E_OVERFLOW if H * W * max(q) could exceed 2^62.
  */
-int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask, oss_ref **out);
+int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
+                   int32_t max_radius, oss_ref **out);
 
 /* Build (or rebuild) the tables of `ref` from device pixels laid out as the
  * descriptor says.  Asynchronous on `stream`; the pixels must stay valid
@@ -177,10 +188,13 @@ int oss_ref_release(oss_ref *ref);
 /*
  * Read-only device view of the tables: entry (x, y) of table T for
  * quantity slot q is T[((y+1) * pitch_entries + (x+1)) * nq + q], with
- * x in [-1, W-1], y in [-1, H-1]; nq = number of bits in the feature mask.
+ * x in [-1, W-1], y in [-1, H-1]; nq = number of bits in the feature mask;
+ * values are value_bits (32: the sums modulo 2^32, or 64) wide unsigned
+ * words.  Any output pointer may be NULL.
  */
-int oss_ref_tables(const oss_ref *ref, const int64_t **L, const int64_t **R, const int64_t **Rp,
-                   int64_t *pitch_entries, int32_t *nq);
+int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const void **Rp,
+                   int64_t *pitch_entries, int32_t *nq, int32_t *value_bits,
+                   int32_t *max_radius);
 
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the

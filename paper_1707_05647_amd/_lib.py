@@ -79,12 +79,13 @@ def load(path: str | None = None):
     lib.oss_ctx_destroy.argtypes = [vp]
     lib.oss_status_string.argtypes = [C.c_int]
     lib.oss_status_string.restype = C.c_char_p
-    lib.oss_ref_bytes.argtypes = [C.POINTER(oss_image_desc), u32, C.POINTER(C.c_size_t)]
-    lib.oss_ref_create.argtypes = [vp, C.POINTER(oss_image_desc), u32, C.POINTER(vp)]
+    lib.oss_ref_bytes.argtypes = [C.POINTER(oss_image_desc), u32, i32, C.POINTER(C.c_size_t)]
+    lib.oss_ref_create.argtypes = [vp, C.POINTER(oss_image_desc), u32, i32, C.POINTER(vp)]
     lib.oss_ref_build.argtypes = [vp, vp, vp]
     lib.oss_ref_release.argtypes = [vp]
     lib.oss_ref_tables.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
-                                   C.POINTER(i64), C.POINTER(i32)]
+                                   C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                   C.POINTER(i32)]
     lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
@@ -183,16 +184,17 @@ def oss_ctx_profile_read(ctx: int) -> dict:
             for i in range(n.value)}
 
 
-def oss_ref_bytes(desc: oss_image_desc, feat_mask: int) -> int:
+def oss_ref_bytes(desc: oss_image_desc, feat_mask: int, max_radius: int = -1) -> int:
     out = C.c_size_t()
-    _check(load().oss_ref_bytes(C.byref(desc), int(feat_mask), C.byref(out)), "oss_ref_bytes")
+    _check(load().oss_ref_bytes(C.byref(desc), int(feat_mask), int(max_radius), C.byref(out)),
+           "oss_ref_bytes")
     return out.value
 
 
-def oss_ref_create(ctx: int, desc: oss_image_desc, feat_mask: int) -> int:
+def oss_ref_create(ctx: int, desc: oss_image_desc, feat_mask: int, max_radius: int = -1) -> int:
     h = C.c_void_p()
-    _check(load().oss_ref_create(ctx, C.byref(desc), int(feat_mask), C.byref(h)),
-           "oss_ref_create")
+    _check(load().oss_ref_create(ctx, C.byref(desc), int(feat_mask), int(max_radius),
+                                 C.byref(h)), "oss_ref_create")
     return h.value
 
 
@@ -205,12 +207,13 @@ def oss_ref_release(ref: int):
 
 
 def oss_ref_tables(ref: int):
-    """(L, R, Rp) device pointers, pitch in entries, number of quantities."""
+    """(L, R, Rp) device pointers, pitch in entries, number of quantities,
+    value width in bits (32: sums modulo 2^32, or 64), maximum radius."""
     L, R, Rp = C.c_void_p(), C.c_void_p(), C.c_void_p()
-    pitch, nq = C.c_int64(), C.c_int32()
+    pitch, nq, vb, mr = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
     _check(load().oss_ref_tables(ref, C.byref(L), C.byref(R), C.byref(Rp), C.byref(pitch),
-                                 C.byref(nq)), "oss_ref_tables")
-    return L.value, R.value, Rp.value, pitch.value, nq.value
+                                 C.byref(nq), C.byref(vb), C.byref(mr)), "oss_ref_tables")
+    return L.value, R.value, Rp.value, pitch.value, nq.value, vb.value, mr.value
 
 
 def oss_template_features(pixels, rho: int, feat_mask: int,

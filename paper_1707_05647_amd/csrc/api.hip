@@ -38,6 +38,7 @@ struct oss_ref {
     oss_ctx *ctx = nullptr;
     oss_image_desc desc{};
     uint32_t feat_mask = 0;
+    int32_t max_radius = 0;
     BuildGeom geom{};
     void *mem = nullptr;  // one allocation for everything below
     size_t bytes = 0;
@@ -190,18 +191,17 @@ int oss_ctx_destroy(oss_ctx *ctx)
     return OSS_OK;
 }
 
-// Device layout of a reference: 3 tables, 2 row-base arrays, 3 band
+// Device layout of a reference: 3 tables, the row-prefix bases, 3 band
 // contribution arrays and 3 carry arrays, each 256-byte aligned.
-enum { A_L, A_R, A_RP, A_BPA, A_BPF, A_AGL, A_AGAD, A_AGD, A_CL, A_CAD, A_CD, A_COUNT };
+enum { A_L, A_R, A_RP, A_BP, A_AGL, A_AGAD, A_AGD, A_CL, A_CAD, A_CD, A_COUNT };
 
 static size_t ref_layout(const BuildGeom &g, size_t off[A_COUNT])
 {
-    const size_t e = sizeof(int64_t) * (size_t)g.nq;
+    const size_t e = (size_t)g.ebytes * (size_t)g.nq;
     const size_t table = (size_t)(g.H + 1) * (size_t)g.pitch_e * e;
-    const size_t bpa = (size_t)g.H * g.nch_agg * e;
-    const size_t bpf = (size_t)g.H * g.nch_fin * e;
+    const size_t bp = (size_t)g.H * g.nbp * e;
     const size_t car = (size_t)g.nb * g.cw * e;
-    const size_t sizes[A_COUNT] = {table, table, table, bpa, bpf, car, car, car, car, car, car};
+    const size_t sizes[A_COUNT] = {table, table, table, bp, car, car, car, car, car, car};
     size_t acc = 0;
     for (int i = 0; i < A_COUNT; ++i) {
         off[i] = acc;
@@ -210,7 +210,7 @@ static size_t ref_layout(const BuildGeom &g, size_t off[A_COUNT])
     return acc;
 }
 
-static bool overflow_ok(const oss_image_desc *d, uint32_t fm)
+static __int128 max_quantity(const oss_image_desc *d, uint32_t fm)
 {
     const __int128 maxv = ((__int128)1 << d->bit_depth) - 1;
     __int128 maxq = 0;
@@ -220,20 +220,47 @@ static bool overflow_ok(const oss_image_desc *d, uint32_t fm)
         maxq = std::max(maxq, maxv * maxv);
     if (fm & OSS_F_GRAD)
         maxq = std::max(maxq, 2 * maxv);
-    return (__int128)d->H * d->W * maxq < ((__int128)1 << 62);
+    return maxq;
 }
 
-int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, size_t *out)
+static bool overflow_ok(const oss_image_desc *d, uint32_t fm)
+{
+    return (__int128)d->H * d->W * max_quantity(d, fm) < ((__int128)1 << 62);
+}
+
+static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
+{
+    const int32_t fit = (std::min(d->H, d->W) - 1) / 2;
+    return max_radius < 0 ? fit : max_radius;
+}
+
+// 32-bit storage is exact when every square and every diamond sum up to the
+// maximum radius stays below 2^32 for every stored quantity.
+static int storage_bytes(const oss_image_desc *d, uint32_t fm, int32_t R)
+{
+    const __int128 s = square_half(R);
+    const __int128 area = std::max((2 * s + 1) * (2 * s + 1),
+                                   (__int128)2 * R * R + 2 * (__int128)R + 1);
+    return max_quantity(d, fm) * area < ((__int128)1 << 32) ? 4 : 8;
+}
+
+static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R)
+{
+    return make_geom(d->H, d->W, popc(fm), storage_bytes(d, fm, R));
+}
+
+int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_radius, size_t *out)
 {
     if (!out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
         return OSS_E_ARG;
-    const BuildGeom g = make_geom(desc->H, desc->W, popc(feat_mask));
+    const BuildGeom g = ref_geom(desc, feat_mask, resolve_max_radius(desc, max_radius));
     size_t off[A_COUNT];
     *out = ref_layout(g, off);
     return OSS_OK;
 }
 
-int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask, oss_ref **out)
+int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
+                   int32_t max_radius, oss_ref **out)
 {
     if (!ctx || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
         return OSS_E_ARG;
@@ -248,7 +275,8 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
     r->ctx = ctx;
     r->desc = *desc;
     r->feat_mask = feat_mask;
-    r->geom = make_geom(desc->H, desc->W, popc(feat_mask));
+    r->max_radius = resolve_max_radius(desc, max_radius);
+    r->geom = ref_geom(desc, feat_mask, r->max_radius);
     size_t off[A_COUNT];
     r->bytes = ref_layout(r->geom, off);
     if (hipMalloc(&r->mem, r->bytes) != hipSuccess) {
@@ -256,12 +284,11 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
         return OSS_E_NOMEM;
     }
     char *m = static_cast<char *>(r->mem);
-    auto at = [&](int i) { return reinterpret_cast<int64_t *>(m + off[i]); };
+    auto at = [&](int i) { return static_cast<void *>(m + off[i]); };
     r->bb.L = at(A_L);
     r->bb.R = at(A_R);
     r->bb.Rp = at(A_RP);
-    r->bb.bp_agg = at(A_BPA);
-    r->bb.bp_fin = at(A_BPF);
+    r->bb.bp = at(A_BP);
     r->bb.agg_L = at(A_AGL);
     r->bb.agg_AD = at(A_AGAD);
     r->bb.agg_D = at(A_AGD);
@@ -294,8 +321,9 @@ int oss_ref_release(oss_ref *ref)
     return OSS_OK;
 }
 
-int oss_ref_tables(const oss_ref *ref, const int64_t **L, const int64_t **R, const int64_t **Rp,
-                   int64_t *pitch_entries, int32_t *nq)
+int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const void **Rp,
+                   int64_t *pitch_entries, int32_t *nq, int32_t *value_bits,
+                   int32_t *max_radius)
 {
     if (!ref)
         return OSS_E_ARG;
@@ -309,6 +337,10 @@ int oss_ref_tables(const oss_ref *ref, const int64_t **L, const int64_t **R, con
         *pitch_entries = ref->geom.pitch_e;
     if (nq)
         *nq = ref->geom.nq;
+    if (value_bits)
+        *value_bits = 8 * ref->geom.ebytes;
+    if (max_radius)
+        *max_radius = ref->max_radius;
     return OSS_OK;
 }
 
@@ -476,7 +508,7 @@ static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t
     for (int i = 0; i < n_probes; ++i) {
         const oss_probe &p = probes[i];
         if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
-            p.scale_id >= OSS_MAX_SCALES || p.r < 0)
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
             return OSS_E_ARG;
         per[p.template_id].push_back(p);
         if ((int)per[p.template_id].size() > OSS_MAX_SCALES)

@@ -5,47 +5,50 @@
 //
 // The paper builds its tables by one horizontal and one vertical cumulative
 // pass (Sec. "Patch Features") and "two diagonal passes" for the triangular
-// one.  Here every table is written exactly once, in row bands of KBAND
-// rows, from the row prefix P_y(x) of the band's own rows plus a carry row
-// (the three tables at the row above the band):
+// one.  Here every table entry is written exactly once, in row bands of
+// KBAND rows, from the band's own row prefixes plus the carry row above it:
 //
-//   K0 row_base   per image row, P_y at the left edge of every band tile
-//                 (one block per row: segment sums + block scan)
-//   K1 band<agg>  per band tile, the band's own contribution with zero
-//                 carries, kept only at the band's last row
-//   K2 carry      per line across bands, the carry rows: a running sum of
-//                 the band contributions along columns (L), anti-diagonals
-//                 (T_ad) and diagonals (T_d)
-//   K3 band<fin>  per band tile, the final tables from the carry row, one
-//                 coalesced store per entry
+//   row_base   per image row, the row prefix at every 64th column
+//              (wavefront reductions of 64-column chunks + a block scan)
+//   band_agg   per band tile, the band's own contribution to the carries
+//              from its column, anti-diagonal and diagonal projections
+//              (LDS atomics) and three block scans, not a row-by-row walk
+//   carry      per line across bands, the carry rows: running sums of the
+//              band contributions along columns (L), anti-diagonals (T_ad)
+//              and diagonals (T_d)
+//   band_final per band tile, the tables from the carry row: each row one
+//              wavefront scan (DPP), one barrier, and one coalesced store
+//              per entry (the row's R/R' are stored one row late, once the
+//              neighbouring waves' diagonal carries are visible)
 //
-// Inside a band a tile of 512 threads owns 512 consecutive columns (one
-// column per thread): each row it computes q, the row prefix by an
-// LDS-staged block scan (64-lane wavefront scans combined through LDS), and
-// advances the three recurrences, exchanging the shifted diagonal carries
-// with its neighbours through LDS.  A tile writes only its core columns;
-// the 33-column halos on both sides absorb the diagonal dependencies
-// (a diagonal carry moves one column per row).
+// Arithmetic is unsigned and wraps: with 32-bit storage every table is the
+// exact sum modulo 2^32, which keeps every square and diamond sum exact as
+// long as it is below 2^32 (the host checks that bound for the declared
+// maximum radius before choosing 32-bit storage).
 #include "oss_internal.h"
 
 namespace oss {
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-BuildGeom make_geom(int H, int W, int nq)
+BuildGeom make_geom(int H, int W, int nq, int ebytes)
 {
     BuildGeom g;
     g.H = H;
     g.W = W;
     g.nq = nq;
+    g.ebytes = ebytes;
     g.pitch_e = ((int64_t)W + 1 + 15) / 16 * 16;
     g.nb = cdiv(H + 1, KBAND);
-    g.cx0 = -2 - KBAND;
-    g.cw = W + 2 * KBAND + 3;
-    g.nch_agg = cdiv(g.cw, BAND_CORE_MAX);
-    g.wc_agg = cdiv(g.cw, g.nch_agg);
-    g.nch_fin = cdiv(W + 1, BAND_CORE_MAX);
-    g.wc_fin = cdiv(W + 1, g.nch_fin);
+    // final tiles: cores cover [-1, W-1]; the first core starts at -64+HALO <= -1
+    g.fin_x0 = -64;
+    g.nfin = cdiv((W - 1) - (g.fin_x0 + BAND_HALO) + 1, BAND_STRIDE);
+    g.cx0 = g.fin_x0;
+    g.cw = (g.nfin - 1) * BAND_STRIDE + BAND_THREADS;
+    // projection tiles: cores cover the carry range
+    g.agg_x0 = -128;
+    g.nagg = cdiv((g.cx0 + g.cw - 1) - (g.agg_x0 + BAND_HALO) + 1, BAND_STRIDE);
+    g.nbp = cdiv(W, 64) + 1;
     return g;
 }
 
@@ -54,392 +57,631 @@ struct Feat {
     static constexpr int NQ = ((FM >> 0) & 1) + ((FM >> 1) & 1) + ((FM >> 2) & 1);
 };
 
-// q values of pixel (x, y) (inside the image) in feature-bit order.
-template <typename Pix, unsigned FM>
-__device__ __forceinline__ void load_q(const Pix *__restrict__ img, int64_t pitch, int H, int W,
-                                       int x, int y, int64_t *q)
+// ---------------------------------------------------------------------------
+// Wavefront primitives (DPP; 64-bit values move as two 32-bit halves).
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
 {
-    const Pix *row = img + (int64_t)y * pitch;
-    const int v = row[x];
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, BOUND);
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint64_t dpp(uint64_t v)
+{
+    const uint32_t lo = dpp<CTRL, ROW_MASK, BOUND>((uint32_t)v);
+    const uint32_t hi = dpp<CTRL, ROW_MASK, BOUND>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// inclusive scan across the 64 lanes of a wavefront
+template <typename T>
+__device__ __forceinline__ T wave_scan(T v)
+{
+    v += dpp<0x111, 0xf, true>(v);  // row_shr:1
+    v += dpp<0x112, 0xf, true>(v);  // row_shr:2
+    v += dpp<0x114, 0xf, true>(v);  // row_shr:4
+    v += dpp<0x118, 0xf, true>(v);  // row_shr:8
+    v += dpp<0x142, 0xa, false>(v); // row_bcast:15 into rows 1, 3
+    v += dpp<0x143, 0xc, false>(v); // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// value of lane - 1 (lane 0: 0) / of lane + 1 (lane 63: 0)
+template <typename T>
+__device__ __forceinline__ T from_left(T v)
+{
+    return dpp<0x138, 0xf, false>(v);  // wave_shr:1
+}
+template <typename T>
+__device__ __forceinline__ T from_right(T v)
+{
+    return dpp<0x130, 0xf, false>(v);  // wave_shl:1
+}
+
+template <typename T>
+__device__ __forceinline__ T lane63(T v)
+{
+    return (T)__builtin_amdgcn_readlane((int)v, 63);
+}
+template <>
+__device__ __forceinline__ uint64_t lane63<uint64_t>(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// q values of a pixel inside the image, in feature-bit order, from the
+// pixel c, its left / right neighbours l, r and the pixels above / below u,
+// d (neighbour indices clamped to the image).
+template <unsigned FM, typename T>
+__device__ __forceinline__ void quantities(int c, int l, int r, int u, int d, T *q)
+{
     int slot = 0;
     if (FM & OSS_F_SUM)
-        q[slot++] = v;
+        q[slot++] = (T)c;
     if (FM & OSS_F_SQ)
-        q[slot++] = (int64_t)v * v;
+        q[slot++] = (T)((uint64_t)c * (uint64_t)c);
     if (FM & OSS_F_GRAD) {
-        const int xr = x + 1 < W ? x + 1 : W - 1;
-        const int xl = x > 0 ? x - 1 : 0;
-        const int yd = y + 1 < H ? y + 1 : H - 1;
-        const int yu = y > 0 ? y - 1 : 0;
-        const int gx = (int)row[xr] - (int)row[xl];
-        const int gy = (int)img[(int64_t)yd * pitch + x] - (int)img[(int64_t)yu * pitch + x];
-        q[slot++] = (gx < 0 ? -gx : gx) + (gy < 0 ? -gy : gy);
+        const int gx = r - l, gy = d - u;
+        q[slot++] = (T)((gx < 0 ? -gx : gx) + (gy < 0 ? -gy : gy));
     }
 }
 
-// Inclusive scan of NQ int64 values over the block (NWAVES waves of 64).
-// s_w holds NWAVES*NQ partial sums; the caller must separate two uses of
-// s_w by a barrier.
-template <int NQ, int NWAVES>
-__device__ __forceinline__ void block_incl_scan(int64_t *v, int64_t *s_w, int64_t *total)
+template <typename Pix, unsigned FM, typename T>
+__device__ __forceinline__ void load_q(const Pix *__restrict__ img, int64_t pitch, int H, int W,
+                                       int x, int y, T *q)
 {
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int64_t t = __shfl_up(v[q], d, 64);
-            if (lane >= d)
-                v[q] += t;
-        }
+    const Pix *row = img + (int64_t)y * pitch;
+    const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < W ? x + 1 : W - 1;
+    const int yu = y > 0 ? y - 1 : 0, yd = y + 1 < H ? y + 1 : H - 1;
+    int u = 0, d = 0, l = 0, r = 0;
+    const int c = row[x];
+    if (FM & OSS_F_GRAD) {
+        l = row[xl];
+        r = row[xr];
+        u = img[(int64_t)yu * pitch + x];
+        d = img[(int64_t)yd * pitch + x];
     }
-    if (lane == 63) {
+    quantities<FM, T>(c, l, r, u, d, q);
+}
+
+// base P_y(X0 - 1) of a tile whose threads start at column X0 (a multiple of 64)
+template <typename T>
+__device__ __forceinline__ const T *tile_base(const T *__restrict__ bp, const BuildGeom &g, int y,
+                                              int X0, int NQ)
+{
+    int j = X0 / 64;
+    j = j < 0 ? 0 : (j > g.nbp - 1 ? g.nbp - 1 : j);
+    return bp + ((int64_t)y * g.nbp + j) * NQ;
+}
+
+// ---------------------------------------------------------------------------
+// row_base: bp[y][j] = P_y(64 j - 1) for j in [0, nbp); the last entry is
+// the row total.  One block per row; a wave reduces 64-column chunks.
+// ---------------------------------------------------------------------------
+constexpr int RB_THREADS = 256;
+
+template <typename Pix, unsigned FM, typename T>
+__global__ __launch_bounds__(RB_THREADS) void row_base_kernel(const Pix *__restrict__ img,
+                                                              int64_t pitch, BuildGeom g,
+                                                              T *__restrict__ bp)
+{
+    constexpr int NQ = Feat<FM>::NQ;
+    __shared__ T s_chunk[NQ][RB_THREADS];
+    __shared__ T s_w[RB_THREADS / 64][NQ];
+    const int y = blockIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nch = g.nbp - 1;  // 64-column chunks
+    T carry[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        carry[q] = 0;
+    T *out = bp + (int64_t)y * g.nbp * NQ;
+    if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            s_w[wid * NQ + q] = v[q];
+            out[q] = 0;
+    }
+    for (int m0 = 0; m0 < nch; m0 += RB_THREADS) {
+        // chunk sums for chunks m0 .. m0 + 255
+        for (int m = m0 + wid; m < min(m0 + RB_THREADS, nch); m += RB_THREADS / 64) {
+            const int x = m * 64 + lane;
+            T q[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k)
+                q[k] = 0;
+            if (x < g.W)
+                load_q<Pix, FM, T>(img, pitch, g.H, g.W, x, y, q);
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const T s = lane63(wave_scan(q[k]));
+                if (lane == 0)
+                    s_chunk[k][m - m0] = s;
+            }
+        }
+        __syncthreads();
+        // block scan of the chunk sums
+        const int m = m0 + threadIdx.x;
+        T v[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            v[k] = m < nch ? s_chunk[k][threadIdx.x] : (T)0;
+            v[k] = wave_scan(v[k]);
+            if (lane == 63)
+                s_w[wid][k] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            T off = carry[k], tot = carry[k];
+            for (int w = 0; w < RB_THREADS / 64; ++w) {
+                off += (w < wid) ? s_w[w][k] : (T)0;
+                tot += s_w[w][k];
+            }
+            if (m < nch)
+                out[(int64_t)(m + 1) * NQ + k] = off + v[k];
+            carry[k] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// band_agg: the band's contribution to the carry rows, for the core columns
+// x of the tile (threads from X0 = agg_x0 + c * STRIDE, band rows y_s..y_e):
+//   agg_L[x]  = sum_y P_y(x)             = B + sum_{X0 <= i <= x} colsum(i)
+//   agg_AD[x] = sum_y P_y(x + y_e - y)   = B + sum over the tile's pixels with
+//                                          (i - X0) + (y - y_s) <= (x - X0) + (y_e - y_s)
+//   agg_D[x]  = sum_y P_y(x - (y_e - y)) = B + sum over the tile's pixels with
+//                                          (i - X0) - (y - y_s) <= (x - X0) - (y_e - y_s)
+// with B = sum_y P_y(X0 - 1).  The pixels are projected onto columns,
+// anti-diagonals and diagonals (LDS atomic adds) and each projection is
+// scanned once.
+// ---------------------------------------------------------------------------
+constexpr int PROJ = BAND_THREADS + KBAND;  // projection slots per tile
+
+template <typename T, int NQ>
+__device__ __forceinline__ void block_scan_lds(T (*arr)[PROJ], T (*s_w)[NQ])
+{
+    // inclusive scan of arr[q][0..PROJ) in place; thread t owns slots 2t, 2t+1
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int i0 = 2 * threadIdx.x;
+    T a[NQ], b[NQ], s[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        a[q] = i0 < PROJ ? arr[q][i0] : (T)0;
+        b[q] = i0 + 1 < PROJ ? arr[q][i0 + 1] : (T)0;
+        s[q] = wave_scan((T)(a[q] + b[q]));
+        if (lane == 63)
+            s_w[wid][q] = s[q];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int64_t off = 0, tot = 0;
-        for (int w = 0; w < NWAVES; ++w) {
-            const int64_t s = s_w[w * NQ + q];
-            off += (w < wid) ? s : 0;
-            tot += s;
-        }
-        v[q] += off;
-        if (total)
-            total[q] = tot;
+        T off = 0;
+        for (int w = 0; w < BAND_THREADS / 64; ++w)
+            off += (w < wid) ? s_w[w][q] : (T)0;
+        const T incl = off + s[q];
+        if (i0 < PROJ)
+            arr[q][i0] = incl - b[q];
+        if (i0 + 1 < PROJ)
+            arr[q][i0 + 1] = incl;
     }
+    __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// K0: bases of the row prefix.  For image row y and each tile c of each pass,
-// writes P_y(x_start(c) - 1), x_start = first column of the tile's threads.
-// ---------------------------------------------------------------------------
-constexpr int ROWBASE_THREADS = 256;
-
-template <typename Pix, unsigned FM>
-__global__ __launch_bounds__(ROWBASE_THREADS) void row_base_kernel(
-    const Pix *__restrict__ img, int64_t pitch, BuildGeom g, int64_t *__restrict__ bp_agg,
-    int64_t *__restrict__ bp_fin)
-{
-    constexpr int NQ = Feat<FM>::NQ;
-    __shared__ int64_t s_w[(ROWBASE_THREADS / 64) * NQ];
-    const int y = blockIdx.x;
-    const int W = g.W;
-    const int seg = (W + ROWBASE_THREADS - 1) / ROWBASE_THREADS;
-    const int x0 = threadIdx.x * seg;
-    const int x1 = min(x0 + seg, W);
-    int64_t sum[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        sum[q] = 0;
-    for (int x = x0; x < x1; ++x) {
-        int64_t qv[NQ];
-        load_q<Pix, FM>(img, pitch, g.H, W, x, y, qv);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            sum[q] += qv[q];
-    }
-    int64_t incl[NQ], tot[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        incl[q] = sum[q];
-    block_incl_scan<NQ, ROWBASE_THREADS / 64>(incl, s_w, tot);
-    // exclusive prefix at x0
-    int64_t excl[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        excl[q] = incl[q] - sum[q];
-
-    for (int pass = 0; pass < 2; ++pass) {
-        const int nch = pass == 0 ? g.nch_agg : g.nch_fin;
-        const int wc = pass == 0 ? g.wc_agg : g.wc_fin;
-        const int core0 = pass == 0 ? g.cx0 : -1;
-        int64_t *out = pass == 0 ? bp_agg : bp_fin;
-        for (int c = 0; c < nch; ++c) {
-            const int col = core0 + c * wc - BAND_HALO - 1;
-            int64_t *dst = out + ((int64_t)y * nch + c) * NQ;
-            if (col < 0 || col >= W - 1) {
-                if (threadIdx.x == 0) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        dst[q] = col < 0 ? 0 : tot[q];
-                }
-            } else if (col >= x0 && col < x1) {
-                int64_t acc[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    acc[q] = excl[q];
-                for (int x = x0; x <= col; ++x) {
-                    int64_t qv[NQ];
-                    load_q<Pix, FM>(img, pitch, g.H, W, x, y, qv);
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        acc[q] += qv[q];
-                }
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    dst[q] = acc[q];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K1 / K3: one band tile.  FINAL = false: zero carries, store the band's own
-// contribution at its last row into (outA, outB, outC) = (agg_L, agg_AD,
-// agg_D) over the carry range.  FINAL = true: start from the carry row and
-// store L, R, R' for every row of the band.
-// ---------------------------------------------------------------------------
-template <typename Pix, unsigned FM, bool FINAL>
-__global__ __launch_bounds__(BAND_THREADS) void band_kernel(
-    const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const int64_t *__restrict__ bp,
-    const int64_t *__restrict__ cL, const int64_t *__restrict__ cAD,
-    const int64_t *__restrict__ cD, int64_t *__restrict__ outA, int64_t *__restrict__ outB,
-    int64_t *__restrict__ outC)
+template <typename Pix, unsigned FM, typename T>
+__global__ __launch_bounds__(BAND_THREADS) void band_agg_kernel(
+    const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const T *__restrict__ bp,
+    T *__restrict__ aL, T *__restrict__ aAD, T *__restrict__ aD)
 {
     constexpr int NQ = Feat<FM>::NQ;
     constexpr int NW = BAND_THREADS / 64;
-    __shared__ int64_t s_w[NW * NQ];
-    __shared__ int64_t s_ta[2][NQ][BAND_THREADS];
-    __shared__ int64_t s_td[2][NQ][BAND_THREADS];
-
-    const int c = blockIdx.x;
-    const int b = blockIdx.y;
+    __shared__ T s_ad[NQ][PROJ];
+    __shared__ T s_d[NQ][PROJ];
+    __shared__ T s_col[NQ][PROJ];
+    __shared__ T s_w[NW][NQ];
     const int tid = threadIdx.x;
-    const int nch = FINAL ? g.nch_fin : g.nch_agg;
-    const int wc = FINAL ? g.wc_fin : g.wc_agg;
-    const int core0 = FINAL ? -1 : g.cx0;
-    const int core_last = FINAL ? g.W - 1 : g.cx0 + g.cw - 1;
-    const int xs = core0 + c * wc;
-    const int xe = min(xs + wc - 1, core_last);
-    const int x = xs - BAND_HALO + tid;
-    const bool in_core = x >= xs && x <= xe;
+    const int X0 = g.agg_x0 + blockIdx.x * BAND_STRIDE;
+    const int b = blockIdx.y;
+    const int x = X0 + tid;
     const int ys = -1 + b * KBAND;
     const int rows = min(KBAND, g.H - ys);
-    const int W = g.W, H = g.H;
-
-    // L(x, y-1), T_ad(x+1, y-1), T_d(x-1, y-1)
-    int64_t Lc[NQ], ta_r[NQ], td_l[NQ], TA[NQ], TD[NQ];
+    for (int i = tid; i < PROJ; i += BAND_THREADS) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            s_ad[q][i] = 0;
+            s_d[q][i] = 0;
+            s_col[q][i] = 0;
+        }
+    }
+    __syncthreads();
+    T col[NQ], B[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        Lc[q] = 0;
-        ta_r[q] = 0;
-        td_l[q] = 0;
-        TA[q] = 0;
-        TD[q] = 0;
+        col[q] = 0;
+        B[q] = 0;
     }
-    if (FINAL) {
-        const int64_t row = (int64_t)b * g.cw;
-        const int ci = x - g.cx0;
-        if (ci >= 0 && ci < g.cw) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                Lc[q] = cL[(row + ci) * NQ + q];
-        }
-        if (ci + 1 >= 0 && ci + 1 < g.cw) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                ta_r[q] = cAD[(row + ci + 1) * NQ + q];
-        }
-        if (ci - 1 >= 0 && ci - 1 < g.cw) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                td_l[q] = cD[(row + ci - 1) * NQ + q];
-        }
-    }
-
+    const bool inside = x >= 0 && x < g.W;
     for (int k = 0; k < rows; ++k) {
         const int y = ys + k;
-        int64_t P[NQ];
+        if (y < 0)
+            continue;
+        const T *base = tile_base(bp, g, y, X0, NQ);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            P[q] = 0;
-        if (y >= 0 && x >= 0 && x < W)
-            load_q<Pix, FM>(img, pitch, H, W, x, y, P);
-        block_incl_scan<NQ, NW>(P, s_w, nullptr);
-        if (y >= 0) {
-            const int64_t *base = bp + ((int64_t)y * nch + c) * NQ;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                P[q] += base[q];
-        }
-        const int buf = k & 1;
+            B[q] += base[q];
+        if (!inside)
+            continue;
+        T qv[NQ];
+        load_q<Pix, FM, T>(img, pitch, g.H, g.W, x, y, qv);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            Lc[q] += P[q];
-            TA[q] = ta_r[q] + P[q];
-            TD[q] = td_l[q] + P[q];
-            s_ta[buf][q][tid] = TA[q];
-            s_td[buf][q][tid] = TD[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            ta_r[q] = tid + 1 < BAND_THREADS ? s_ta[buf][q][tid + 1] : 0;
-            td_l[q] = tid > 0 ? s_td[buf][q][tid - 1] : 0;
-        }
-        if (FINAL && in_core) {
-            const int64_t e = ((int64_t)(y + 1) * g.pitch_e + (x + 1)) * NQ;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                outA[e + q] = Lc[q];
-                outB[e + q] = TA[q] - td_l[q];
-                outC[e + q] = ta_r[q] - td_l[q];
-            }
+            col[q] += qv[q];
+            atomicAdd(&s_ad[q][tid + k], qv[q]);
+            atomicAdd(&s_d[q][tid - k + KBAND - 1], qv[q]);
         }
     }
-    if (!FINAL && in_core) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        s_col[q][tid] = col[q];
+    __syncthreads();
+    block_scan_lds<T, NQ>(s_col, s_w);
+    block_scan_lds<T, NQ>(s_ad, s_w);
+    block_scan_lds<T, NQ>(s_d, s_w);
+    const int core0 = X0 + BAND_HALO;
+    if (x >= core0 && x < core0 + BAND_STRIDE && x >= g.cx0 && x < g.cx0 + g.cw) {
         const int64_t e = ((int64_t)b * g.cw + (x - g.cx0)) * NQ;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            outA[e + q] = Lc[q];
-            outB[e + q] = TA[q];
-            outC[e + q] = TD[q];
+            aL[e + q] = B[q] + s_col[q][tid];
+            aAD[e + q] = B[q] + s_ad[q][tid + rows - 1];
+            aD[e + q] = B[q] + s_d[q][tid - rows + KBAND];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// K2: carry rows.  C^0 = 0 and, for band b with KBAND rows,
-//   C_L^{b+1}[x]  = C_L^b[x]           + agg_L^b[x]
-//   C_AD^{b+1}[x] = C_AD^b[x + KBAND]  + agg_AD^b[x]
-//   C_D^{b+1}[x]  = C_D^b[x - KBAND]   + agg_D^b[x]
-// walked by one thread per line.  Beyond the right end of the carry range
-// the anti-diagonal table equals the full row total L(W-1, .); left of it
-// the diagonal table is zero.
+// carry: C^0 = 0 and, for a band of KBAND rows,
+//   C_L^{b+1}[x]  = C_L^b[x]          + agg_L^b[x]
+//   C_AD^{b+1}[x] = C_AD^b[x + KBAND] + agg_AD^b[x]
+//   C_D^{b+1}[x]  = C_D^b[x - KBAND]  + agg_D^b[x]
+// one thread per line; right of the carry range the anti-diagonal table
+// equals the full row total L(W-1, .), left of it the diagonal table is 0.
+// The loads of a group of bands are issued before the dependent sums.
 // ---------------------------------------------------------------------------
-template <int NQ>
-__global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const int64_t *__restrict__ aL,
-                                                    const int64_t *__restrict__ aAD,
-                                                    const int64_t *__restrict__ aD,
-                                                    int64_t *__restrict__ cL,
-                                                    int64_t *__restrict__ cAD,
-                                                    int64_t *__restrict__ cD)
+constexpr int CW_UNROLL = 8;
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__restrict__ aL,
+                                                    const T *__restrict__ aAD,
+                                                    const T *__restrict__ aD,
+                                                    T *__restrict__ cL, T *__restrict__ cAD,
+                                                    T *__restrict__ cD)
 {
     const int kind = blockIdx.y;
     const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int cw = g.cw, nb = g.nb;
-    const int span = (nb - 1) * KBAND;
-    const int ci_tot = (g.W - 1) - g.cx0;  // index of x = W-1
-    int64_t v[NQ];
+    const int64_t cw = g.cw;
+    const int nb = g.nb;
+    const int64_t span = (int64_t)(nb - 1) * KBAND;
+    const int64_t ci_tot = (g.W - 1) - g.cx0;  // carry index of x = W-1
+    T v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         v[q] = 0;
     if (kind == 0) {
         if (line >= cw)
             return;
-        for (int b = 0; b < nb; ++b) {
-            const int64_t e = ((int64_t)b * cw + line) * NQ;
+        for (int b0 = 0; b0 < nb; b0 += CW_UNROLL) {
+            T a[CW_UNROLL][NQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                cL[e + q] = v[q];
-                v[q] += aL[e + q];
+            for (int u = 0; u < CW_UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    a[u][q] = b0 + u < nb ? aL[(((int64_t)(b0 + u)) * cw + line) * NQ + q] : (T)0;
+#pragma unroll
+            for (int u = 0; u < CW_UNROLL; ++u) {
+                if (b0 + u >= nb)
+                    break;
+                const int64_t e = (((int64_t)(b0 + u)) * cw + line) * NQ;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    cL[e + q] = v[q];
+                    v[q] += a[u][q];
+                }
             }
         }
     } else if (kind == 1) {
-        // lines lambda in [0, cw + span): index of x at band b is lambda - b*K
+        // line lambda: carry index lambda - b*K at band b
         if (line >= cw + span)
             return;
-        for (int b = 0; b < nb; ++b) {
-            const int64_t xb = line - (int64_t)b * KBAND;
-            if (xb < 0)
+        for (int b0 = 0; b0 < nb; b0 += CW_UNROLL) {
+            if (line - (int64_t)b0 * KBAND < 0)
                 break;
-            if (xb < cw) {
-                const int64_t e = ((int64_t)b * cw + xb) * NQ;
+            T a[CW_UNROLL][NQ];
+#pragma unroll
+            for (int u = 0; u < CW_UNROLL; ++u) {
+                const int b = b0 + u;
+                const int64_t xn = line - (int64_t)(b + 1) * KBAND;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    T val = 0;
+                    if (b < nb) {
+                        if (xn >= cw)
+                            val = aL[((int64_t)b * cw + ci_tot) * NQ + q];
+                        else if (xn >= 0)
+                            val = aAD[((int64_t)b * cw + xn) * NQ + q];
+                    }
+                    a[u][q] = val;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CW_UNROLL; ++u) {
+                const int b = b0 + u;
+                if (b >= nb)
+                    break;
+                const int64_t xb = line - (int64_t)b * KBAND;
+                if (xb >= 0 && xb < cw) {
+                    const int64_t e = ((int64_t)b * cw + xb) * NQ;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        cAD[e + q] = v[q];
+                }
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
-                    cAD[e + q] = v[q];
-            }
-            const int64_t xn = xb - KBAND;
-            const int64_t et = ((int64_t)b * cw + ci_tot) * NQ;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int64_t bt = aL[et + q];
-                int64_t a;
-                if (xn >= cw)
-                    a = bt;
-                else if (xn >= 0)
-                    a = aAD[((int64_t)b * cw + xn) * NQ + q];
-                else
-                    a = 0;
-                v[q] += a;
+                    v[q] += a[u][q];
             }
         }
     } else {
-        // lines lambda in [-span, cw): index of x at band b is lambda + b*K
+        // line lambda - span: carry index lambda - span + b*K at band b
         if (line >= cw + span)
             return;
         const int64_t lam = line - span;
-        for (int b = 0; b < nb; ++b) {
-            const int64_t xb = lam + (int64_t)b * KBAND;
-            if (xb >= cw)
+        for (int b0 = 0; b0 < nb; b0 += CW_UNROLL) {
+            if (lam + (int64_t)b0 * KBAND >= cw)
                 break;
-            if (xb >= 0) {
-                const int64_t e = ((int64_t)b * cw + xb) * NQ;
+            T a[CW_UNROLL][NQ];
+#pragma unroll
+            for (int u = 0; u < CW_UNROLL; ++u) {
+                const int b = b0 + u;
+                const int64_t xn = lam + (int64_t)(b + 1) * KBAND;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
-                    cD[e + q] = v[q];
+                    a[u][q] = (b < nb && xn >= 0 && xn < cw)
+                                  ? aD[((int64_t)b * cw + xn) * NQ + q]
+                                  : (T)0;
             }
-            const int64_t xn = xb + KBAND;
-            if (xn >= 0 && xn < cw) {
+#pragma unroll
+            for (int u = 0; u < CW_UNROLL; ++u) {
+                const int b = b0 + u;
+                if (b >= nb)
+                    break;
+                const int64_t xb = lam + (int64_t)b * KBAND;
+                if (xb >= 0 && xb < cw) {
+                    const int64_t e = ((int64_t)b * cw + xb) * NQ;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        cD[e + q] = v[q];
+                }
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
-                    v[q] += aD[((int64_t)b * cw + xn) * NQ + q];
+                    v[q] += a[u][q];
             }
         }
     }
 }
 
-template <typename Pix, unsigned FM>
+// ---------------------------------------------------------------------------
+// band_final: one tile of one band.  Thread state after row k-1: L, T_ad and
+// T_d at its column.  Row k: q, wavefront scan, one barrier (which also
+// publishes the previous row's T_ad of lane 0 and T_d of lane 63 of every
+// wave), then
+//   ta_r = T_ad(x+1, y-1), td_l = T_d(x-1, y-1)   (DPP, or the wave edges)
+//   store row y-1:  L, R = T_ad(x) - td_l, R' = ta_r - td_l
+//   advance:        L += P, T_ad = ta_r + P, T_d = td_l + P
+// The last row is stored after one more barrier.
+// ---------------------------------------------------------------------------
+template <typename T, int NQ>
+__device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v)
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        tab[e * NQ + q] = v[q];
+}
+
+template <typename Pix, unsigned FM, typename T>
+__global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
+    const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const T *__restrict__ bp,
+    const T *__restrict__ cL, const T *__restrict__ cAD, const T *__restrict__ cD,
+    T *__restrict__ tL, T *__restrict__ tR, T *__restrict__ tRp)
+{
+    constexpr int NQ = Feat<FM>::NQ;
+    constexpr int NW = BAND_THREADS / 64;
+    __shared__ T s_wt[2][NW][NQ];
+    __shared__ T s_eta[2][NW][NQ];
+    __shared__ T s_etd[2][NW][NQ];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int X0 = g.fin_x0 + blockIdx.x * BAND_STRIDE;
+    const int b = blockIdx.y;
+    const int x = X0 + tid;
+    const int ys = -1 + b * KBAND;
+    const int rows = min(KBAND, g.H - ys);
+    const int W = g.W, H = g.H;
+    const int core0 = X0 + BAND_HALO;
+    const bool store = x >= core0 && x < core0 + BAND_STRIDE && x >= -1 && x <= W - 1;
+    const bool inside = x >= 0 && x < W;
+
+    T Lc[NQ], TA[NQ], TD[NQ];
+    {
+        const int64_t e = ((int64_t)b * g.cw + (x - g.cx0)) * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            Lc[q] = cL[e + q];
+            TA[q] = cAD[e + q];
+            TD[q] = cD[e + q];
+        }
+    }
+    // pixels: rolling window of the current row (left, centre, right) and
+    // the centre of the row above
+    const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < W ? x + 1 : W - 1;
+    int pl = 0, pc = 0, pr = 0, pu = 0;
+    if (inside) {
+        const int y0 = ys < 0 ? 0 : ys;
+        const int yu0 = y0 > 0 ? y0 - 1 : 0;
+        const Pix *row = img + (int64_t)y0 * pitch;
+        pl = row[xl];
+        pc = row[x];
+        pr = row[xr];
+        pu = img[(int64_t)yu0 * pitch + x];
+    }
+
+    for (int k = 0; k < rows; ++k) {
+        const int y = ys + k;
+        T s[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            s[q] = 0;
+        if (y >= 0 && inside) {
+            const int yd = y + 1 < H ? y + 1 : H - 1;
+            const Pix *nrow = img + (int64_t)yd * pitch;
+            const int nl = nrow[xl], nc = nrow[x], nr = nrow[xr];
+            quantities<FM, T>(pc, pl, pr, pu, nc, s);
+            pu = pc;
+            pl = nl;
+            pc = nc;
+            pr = nr;
+        }
+        const int buf = k & 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            s[q] = wave_scan(s[q]);
+            if (lane == 63) {
+                s_wt[buf][wid][q] = s[q];
+                s_etd[buf][wid][q] = TD[q];
+            }
+            if (lane == 0)
+                s_eta[buf][wid][q] = TA[q];
+        }
+        __syncthreads();
+        const T *base = y >= 0 ? tile_base(bp, g, y, X0, NQ) : nullptr;
+        T ta_r[NQ], td_l[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T off = base ? base[q] : (T)0;
+            for (int w = 0; w < NW; ++w)
+                off += (w < wid) ? s_wt[buf][w][q] : (T)0;
+            const T P = off + s[q];
+            ta_r[q] = from_right(TA[q]);
+            td_l[q] = from_left(TD[q]);
+            if (lane == 63)
+                ta_r[q] = wid + 1 < NW ? s_eta[buf][wid + 1][q] : (T)0;
+            if (lane == 0)
+                td_l[q] = wid > 0 ? s_etd[buf][wid - 1][q] : (T)0;
+            s[q] = P;
+        }
+        if (k > 0 && store) {
+            const int64_t e = (int64_t)y * g.pitch_e + (x + 1);  // row y-1
+            T r[NQ], rp[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                r[q] = TA[q] - td_l[q];
+                rp[q] = ta_r[q] - td_l[q];
+            }
+            store_entry<T, NQ>(tL, e, Lc);
+            store_entry<T, NQ>(tR, e, r);
+            store_entry<T, NQ>(tRp, e, rp);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            Lc[q] += s[q];
+            TA[q] = ta_r[q] + s[q];
+            TD[q] = td_l[q] + s[q];
+        }
+    }
+    // the band's last row
+    const int buf = rows & 1;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (lane == 63)
+            s_etd[buf][wid][q] = TD[q];
+        if (lane == 0)
+            s_eta[buf][wid][q] = TA[q];
+    }
+    __syncthreads();
+    // neighbour values first, with every lane active (DPP reads from lanes
+    // that are switched off return 0)
+    T r[NQ], rp[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        T ta_r = from_right(TA[q]);
+        T td_l = from_left(TD[q]);
+        if (lane == 63)
+            ta_r = wid + 1 < NW ? s_eta[buf][wid + 1][q] : (T)0;
+        if (lane == 0)
+            td_l = wid > 0 ? s_etd[buf][wid - 1][q] : (T)0;
+        r[q] = TA[q] - td_l;
+        rp[q] = ta_r - td_l;
+    }
+    if (store) {
+        const int64_t e = (int64_t)(ys + rows) * g.pitch_e + (x + 1);
+        store_entry<T, NQ>(tL, e, Lc);
+        store_entry<T, NQ>(tR, e, r);
+        store_entry<T, NQ>(tRp, e, rp);
+    }
+}
+
+template <typename Pix, unsigned FM, typename T>
 static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_bytes,
                           const BuildBuffers &bb, hipStream_t st, Profiler *prof)
 {
     constexpr int NQ = Feat<FM>::NQ;
     const Pix *img = static_cast<const Pix *>(pixels);
     const int64_t pitch = pitch_bytes / (int64_t)sizeof(Pix);
+    T *bp = static_cast<T *>(bb.bp);
+    T *aL = static_cast<T *>(bb.agg_L), *aAD = static_cast<T *>(bb.agg_AD),
+      *aD = static_cast<T *>(bb.agg_D);
+    T *cL = static_cast<T *>(bb.c_L), *cAD = static_cast<T *>(bb.c_AD),
+      *cD = static_cast<T *>(bb.c_D);
     {
         ProfScope ps(prof, K_ROW_BASE, st);
-        hipLaunchKernelGGL((row_base_kernel<Pix, FM>), dim3(g.H), dim3(ROWBASE_THREADS), 0, st,
-                           img, pitch, g, bb.bp_agg, bb.bp_fin);
+        hipLaunchKernelGGL((row_base_kernel<Pix, FM, T>), dim3(g.H), dim3(RB_THREADS), 0, st, img,
+                           pitch, g, bp);
     }
     {
         ProfScope ps(prof, K_BAND_AGG, st);
-        hipLaunchKernelGGL((band_kernel<Pix, FM, false>), dim3(g.nch_agg, g.nb),
-                           dim3(BAND_THREADS), 0, st, img, pitch, g, bb.bp_agg, nullptr, nullptr,
-                           nullptr, bb.agg_L, bb.agg_AD, bb.agg_D);
+        hipLaunchKernelGGL((band_agg_kernel<Pix, FM, T>), dim3(g.nagg, g.nb), dim3(BAND_THREADS),
+                           0, st, img, pitch, g, bp, aL, aAD, aD);
     }
     {
         ProfScope ps(prof, K_CARRY, st);
-        const int span = (g.nb - 1) * KBAND;
-        const int lines = g.cw + span;
-        hipLaunchKernelGGL((carry_kernel<NQ>), dim3((lines + 255) / 256, 3), dim3(256), 0, st, g,
-                           bb.agg_L, bb.agg_AD, bb.agg_D, bb.c_L, bb.c_AD, bb.c_D);
+        const int lines = g.cw + (g.nb - 1) * KBAND;
+        hipLaunchKernelGGL((carry_kernel<T, NQ>), dim3((lines + 255) / 256, 3), dim3(256), 0, st,
+                           g, aL, aAD, aD, cL, cAD, cD);
     }
     {
         ProfScope ps(prof, K_BAND_FINAL, st);
-        hipLaunchKernelGGL((band_kernel<Pix, FM, true>), dim3(g.nch_fin, g.nb), dim3(BAND_THREADS),
-                           0, st, img, pitch, g, bb.bp_fin, bb.c_L, bb.c_AD, bb.c_D, bb.L, bb.R,
-                           bb.Rp);
+        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T>), dim3(g.nfin, g.nb),
+                           dim3(BAND_THREADS), 0, st, img, pitch, g, bp, cL, cAD, cD,
+                           static_cast<T *>(bb.L), static_cast<T *>(bb.R),
+                           static_cast<T *>(bb.Rp));
     }
     return hipGetLastError();
 }
 
-template <typename Pix>
+template <typename Pix, typename T>
 static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint32_t fm,
                             const BuildBuffers &bb, hipStream_t st, Profiler *pr)
 {
     switch (fm) {
-    case 1: return build_t<Pix, 1>(g, px, pb, bb, st, pr);
-    case 2: return build_t<Pix, 2>(g, px, pb, bb, st, pr);
-    case 3: return build_t<Pix, 3>(g, px, pb, bb, st, pr);
-    case 4: return build_t<Pix, 4>(g, px, pb, bb, st, pr);
-    case 5: return build_t<Pix, 5>(g, px, pb, bb, st, pr);
-    case 6: return build_t<Pix, 6>(g, px, pb, bb, st, pr);
-    case 7: return build_t<Pix, 7>(g, px, pb, bb, st, pr);
+    case 1: return build_t<Pix, 1, T>(g, px, pb, bb, st, pr);
+    case 2: return build_t<Pix, 2, T>(g, px, pb, bb, st, pr);
+    case 3: return build_t<Pix, 3, T>(g, px, pb, bb, st, pr);
+    case 4: return build_t<Pix, 4, T>(g, px, pb, bb, st, pr);
+    case 5: return build_t<Pix, 5, T>(g, px, pb, bb, st, pr);
+    case 6: return build_t<Pix, 6, T>(g, px, pb, bb, st, pr);
+    case 7: return build_t<Pix, 7, T>(g, px, pb, bb, st, pr);
     default: return hipErrorInvalidValue;
     }
 }
@@ -448,9 +690,15 @@ hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_by
                         uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
                         Profiler *prof)
 {
+    if (g.ebytes == 4) {
+        if (dtype == OSS_U8)
+            return build_pix<uint8_t, uint32_t>(g, pixels, pitch_bytes, feat_mask, bb, stream,
+                                                prof);
+        return build_pix<uint16_t, uint32_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
+    }
     if (dtype == OSS_U8)
-        return build_pix<uint8_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
-    return build_pix<uint16_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
+        return build_pix<uint8_t, uint64_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
+    return build_pix<uint16_t, uint64_t>(g, pixels, pitch_bytes, feat_mask, bb, stream, prof);
 }
 
 }  // namespace oss

@@ -22,26 +22,36 @@ namespace oss {
 //     T_ad(x,y) = T_ad(x+1, y-1) + P_y(x)      (anti-diagonal carry)
 //     T_d(x,y)  = T_d(x-1, y-1)  + P_y(x)      (diagonal carry)
 //     R(x,y)    = T_ad(x,y) - T_d(x-1,y),   R'(x,y) = T_ad(x+1,y) - T_d(x-1,y)
-// The carries entering a band (the three tables at row y_s - 1) are found in
-// three steps: a zero-carry pass gives each band's own contribution, a line
-// walk across bands accumulates them, and the final pass starts from them.
-// Carry arrays span x in [CX0, CX1] = [-2-KBAND, W+KBAND].
+// The carries entering a band (the three tables at row y_s - 1) come from a
+// projection pass (each band's own contribution), a line walk across bands
+// and are consumed by the final pass.
+//
+// Band tiles are 512 threads wide, one column per thread; a tile whose
+// threads start at column X0 (a multiple of 64) owns the core columns
+// [X0 + BAND_HALO, X0 + BAND_HALO + BAND_STRIDE - 1]; consecutive tiles are
+// BAND_STRIDE apart.  The halos absorb the one-column-per-row drift of the
+// diagonal carries.  Row prefixes enter a tile through its base
+// P_y(X0 - 1), taken from the per-row prefix at every 64th column.
 // ---------------------------------------------------------------------------
-constexpr int KBAND = 32;          // rows per band
+constexpr int KBAND = 30;          // rows per band
 constexpr int BAND_THREADS = 512;  // threads (= columns) per band tile
 constexpr int BAND_HALO = KBAND + 1;
-constexpr int BAND_CORE_MAX = BAND_THREADS - 2 * BAND_HALO;  // 446 columns
+constexpr int BAND_STRIDE = 448;   // core width, a multiple of 64
+static_assert(BAND_HALO + BAND_STRIDE + BAND_HALO <= BAND_THREADS, "tile too narrow");
+static_assert(BAND_STRIDE % 64 == 0, "tile starts must stay 64-aligned");
 
 struct BuildGeom {
     int H, W, nq;
+    int ebytes;        // bytes per table quantity: 4 (stored mod 2^32) or 8
     int64_t pitch_e;   // table entries per row (>= W+1)
     int nb;            // bands
-    int cx0, cw;       // carry range start (-2-K) and width (W+2K+3)
-    int nch_agg, wc_agg;   // zero-carry pass: chunk count and core width over [cx0, cx0+cw)
-    int nch_fin, wc_fin;   // final pass: chunk count and core width over [-1, W-1]
+    int nfin, fin_x0;  // final tiles: first thread column of tile c is fin_x0 + c*BAND_STRIDE
+    int nagg, agg_x0;  // projection tiles
+    int cx0, cw;       // carry range [cx0, cx0 + cw): the union of the final tiles' columns
+    int nbp;           // row-prefix bases per row: P_y(64 j - 1), j in [0, nbp)
 };
 
-BuildGeom make_geom(int H, int W, int nq);
+BuildGeom make_geom(int H, int W, int nq, int ebytes);
 
 // ---------------------------------------------------------------------------
 // Screening plan uploaded per call.
@@ -117,20 +127,21 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // Kernel launchers (asynchronous, on `stream`).
 // ---------------------------------------------------------------------------
+// All arrays hold `ebytes`-wide unsigned integers (mod 2^32 or 2^64).
 struct BuildBuffers {
-    int64_t *L, *R, *Rp;          // tables
-    int64_t *bp_agg, *bp_fin;     // [H][nch][nq] row-prefix bases
-    int64_t *agg_L, *agg_AD, *agg_D;  // [nb][cw][nq]
-    int64_t *c_L, *c_AD, *c_D;        // [nb][cw][nq]
+    void *L, *R, *Rp;             // tables [H+1][pitch_e][nq]
+    void *bp;                     // [H][nbp][nq] row-prefix bases
+    void *agg_L, *agg_AD, *agg_D; // [nb][cw][nq] band contributions
+    void *c_L, *c_AD, *c_D;       // [nb][cw][nq] carry rows
 };
 
 hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_bytes, int dtype,
                         uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
                         Profiler *prof);
 
-hipError_t launch_star_plain(const BuildGeom &g, const int64_t *L, const int64_t *R,
-                             const int64_t *Rp, const DevTemplatePlan *plan, uint32_t *bits,
-                             hipStream_t stream, Profiler *prof);
+hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                             const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream,
+                             Profiler *prof);
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);

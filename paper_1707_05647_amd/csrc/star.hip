@@ -15,8 +15,10 @@
 // therefore does two int64 compares per feature and probe.
 //
 // One thread per position; a wave covers 64 consecutive columns of one row,
-// so each lookup is a coalesced, wave-uniform-offset read of the int64
-// tables (the feature quantities of one entry sit next to each other).  A
+// so each lookup is a coalesced, wave-uniform-offset read of the tables
+// (the feature quantities of one entry sit next to each other).  With
+// 32-bit tables the square and the diamond sums are formed modulo 2^32
+// (each is below 2^32, so exact) and widened before they are added.  A
 // thread walks all radii of its template (up to 32) and ORs the passing
 // scales' bits.  Blocks are assigned XCD-major: the blocks that one XCD
 // receives (every 8th block id) cover a contiguous run of rows, so the rows
@@ -28,19 +30,24 @@ namespace oss {
 
 constexpr int STAR_THREADS = 256;
 
-template <int NQ>
-__device__ __forceinline__ void ld(const int64_t *__restrict__ T, int64_t e, int64_t *v)
+template <typename T, int NQ>
+__device__ __forceinline__ void ld(const T *__restrict__ tab, int64_t e, T *v)
 {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-        v[q] = T[e * NQ + q];
+        v[q] = tab[e * NQ + q];
 }
 
-template <int NQ>
+// Sum of two region sums that were formed in T: with 32-bit tables each
+// region sum is exact modulo 2^32 and below 2^32, so it zero-extends.
+__device__ __forceinline__ int64_t widen(uint32_t v) { return (int64_t)v; }
+__device__ __forceinline__ int64_t widen(uint64_t v) { return (int64_t)v; }
+
+template <typename T, int NQ>
 __global__ __launch_bounds__(STAR_THREADS) void star_plain_kernel(
-    const int64_t *__restrict__ L, const int64_t *__restrict__ R, const int64_t *__restrict__ Rp,
-    int64_t pitch_e, int H, int W, const DevTemplatePlan *__restrict__ plan,
-    uint32_t *__restrict__ bits, int tiles_x, int n_tiles)
+    const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
+    int H, int W, const DevTemplatePlan *__restrict__ plan, uint32_t *__restrict__ bits,
+    int tiles_x, int n_tiles)
 {
     const int per_xcd = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -63,21 +70,22 @@ __global__ __launch_bounds__(STAR_THREADS) void star_plain_kernel(
         const int64_t dys1 = (int64_t)(s + 1) * pitch_e;
         const int64_t dyr = (int64_t)r * pitch_e;
         const int64_t dyr1 = (int64_t)(r + 1) * pitch_e;
-        int64_t a[NQ], b[NQ], c[NQ], d[NQ], F[NQ];
-        ld<NQ>(L, e0 + dys + s, a);
-        ld<NQ>(L, e0 + dys - s - 1, b);
-        ld<NQ>(L, e0 - dys1 + s, c);
-        ld<NQ>(L, e0 - dys1 - s - 1, d);
+        T a[NQ], b[NQ], c[NQ], d[NQ];
+        int64_t F[NQ];
+        ld<T, NQ>(L, e0 + dys + s, a);
+        ld<T, NQ>(L, e0 + dys - s - 1, b);
+        ld<T, NQ>(L, e0 - dys1 + s, c);
+        ld<T, NQ>(L, e0 - dys1 - s - 1, d);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            F[q] = a[q] - b[q] - c[q] + d[q];
-        ld<NQ>(R, e0 + dyr, a);
-        ld<NQ>(Rp, e0 - pitch_e - r - 1, b);
-        ld<NQ>(Rp, e0 - pitch_e + r, c);
-        ld<NQ>(R, e0 - dyr1, d);
+            F[q] = widen((T)(a[q] - b[q] - c[q] + d[q]));
+        ld<T, NQ>(R, e0 + dyr, a);
+        ld<T, NQ>(Rp, e0 - pitch_e - r - 1, b);
+        ld<T, NQ>(Rp, e0 - pitch_e + r, c);
+        ld<T, NQ>(R, e0 - dyr1, d);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            F[q] += a[q] - b[q] - c[q] + d[q];
+            F[q] += widen((T)(a[q] - b[q] - c[q] + d[q]));
         const int p0 = plan->radii[j].first;
         const int p1 = p0 + plan->radii[j].count;
         for (int p = p0; p < p1; ++p) {
@@ -93,31 +101,42 @@ __global__ __launch_bounds__(STAR_THREADS) void star_plain_kernel(
         bits[(int64_t)y * W + x] = acc;
 }
 
-hipError_t launch_star_plain(const BuildGeom &g, const int64_t *L, const int64_t *R,
-                             const int64_t *Rp, const DevTemplatePlan *plan, uint32_t *bits,
-                             hipStream_t stream, Profiler *prof)
+template <typename T>
+static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                         const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream)
 {
-    ProfScope ps(prof, K_STAR, stream);
     const int tiles_x = (g.W + STAR_THREADS - 1) / STAR_THREADS;
     const int n_tiles = tiles_x * g.H;
     const int nblk = (n_tiles + 7) / 8 * 8;
+    const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
+            *rp = static_cast<const T *>(Rp);
     switch (g.nq) {
     case 1:
-        hipLaunchKernelGGL(star_plain_kernel<1>, dim3(nblk), dim3(STAR_THREADS), 0, stream, L, R,
-                           Rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 1>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
+                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
         break;
     case 2:
-        hipLaunchKernelGGL(star_plain_kernel<2>, dim3(nblk), dim3(STAR_THREADS), 0, stream, L, R,
-                           Rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 2>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
+                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
         break;
     case 3:
-        hipLaunchKernelGGL(star_plain_kernel<3>, dim3(nblk), dim3(STAR_THREADS), 0, stream, L, R,
-                           Rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 3>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
+                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                             const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream,
+                             Profiler *prof)
+{
+    ProfScope ps(prof, K_STAR, stream);
+    if (g.ebytes == 4)
+        return star_t<uint32_t>(g, L, R, Rp, plan, bits, stream);
+    return star_t<uint64_t>(g, L, R, Rp, plan, bits, stream);
 }
 
 }  // namespace oss

@@ -28,12 +28,14 @@ class Reference:
     """Integral tables of one device-resident reference image."""
 
     def __init__(self, ctx: "Context", image, feat_mask: int, bit_depth: int | None = None,
-                 stream=None, build: bool = True):
+                 stream=None, build: bool = True, max_radius: int = -1):
         self.ctx = ctx
         self.image = image
         self.desc = L.desc_of(image, bit_depth)
         self.feat_mask = int(feat_mask)
-        self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask)
+        self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask, max_radius)
+        info = L.oss_ref_tables(self.handle)
+        self.value_bits, self.max_radius = info[5], info[6]
         if build:
             self.build(stream)
 
@@ -56,12 +58,13 @@ class Reference:
             self.handle = None
 
     def tables_host(self):
-        """Copy (L, R, R') to host int64 arrays [H+1, W+1, nq] (synchronous;
-        for tests and inspection)."""
-        Lp, Rp_, Rpp, pitch, nq = L.oss_ref_tables(self.handle)
+        """Copy (L, R, R') to host arrays [H+1, W+1, nq] (uint32 holding the
+        sums modulo 2^32, or int64; synchronous; for tests and inspection)."""
+        Lp, Rp_, Rpp, pitch, nq, vb, _ = L.oss_ref_tables(self.handle)
+        dt = np.uint32 if vb == 32 else np.int64
         out = []
         for p in (Lp, Rp_, Rpp):
-            a = np.empty((self.H + 1, pitch, nq), np.int64)
+            a = np.empty((self.H + 1, pitch, nq), dt)
             _hip_memcpy_d2h(a, p)
             out.append(np.ascontiguousarray(a[:, :self.W + 1, :]))
         return out
@@ -73,8 +76,8 @@ class Context:
         self.handle = L.oss_ctx_create(device)
 
     def reference(self, image, feat_mask: int = L.OSS_F_ALL, bit_depth: int | None = None,
-                  stream=None, build: bool = True) -> Reference:
-        return Reference(self, image, feat_mask, bit_depth, stream, build)
+                  stream=None, build: bool = True, max_radius: int = -1) -> Reference:
+        return Reference(self, image, feat_mask, bit_depth, stream, build, max_radius)
 
     def template_features(self, pixels, rho: int, feat_mask: int, bit_depth: int | None = None):
         return L.oss_template_features(pixels, rho, feat_mask, bit_depth)

@@ -76,7 +76,8 @@ class Runner:
         self.ctx = Context(0)
 
     def screen(self, img: np.ndarray, templates, probes, fm: int, P, Q: int, *,
-               bit_depth=None, list_cap=None, pitch_pad: int = 0, tm_fm=None):
+               bit_depth=None, list_cap=None, pitch_pad: int = 0, tm_fm=None,
+               max_radius: int = -1):
         torch = self.torch
         if pitch_pad:
             wide = np.zeros((img.shape[0], img.shape[1] + pitch_pad), img.dtype)
@@ -86,7 +87,8 @@ class Runner:
             t_img = self.L.device_image(img, self.dev)
         if bit_depth is None:
             bit_depth = 8 if img.dtype == np.uint8 else 16
-        ref = self.ctx.reference(t_img, fm, bit_depth)
+        ref = self.ctx.reference(t_img, fm, bit_depth, max_radius=max_radius)
+        self.last_value_bits = ref.value_bits
         tm = [self.L.oss_template_features(px, rho, tm_fm or fm, bit_depth=bit_depth)
               for px, rho in templates]
         H, W = img.shape

@@ -45,11 +45,16 @@ def test_status_strings(lib):
 
 def test_ref_bytes(lib):
     d = lib.image_desc(4096, 4096)
-    b3 = lib.oss_ref_bytes(d, 7)
-    b1 = lib.oss_ref_bytes(d, 1)
-    tables = 3 * 4097 * 4112 * 8
-    assert b1 >= tables and b3 >= 3 * tables
-    assert b3 < 3 * tables * 1.2
+    b3 = lib.oss_ref_bytes(d, 7)           # any radius: squares need int64
+    b1 = lib.oss_ref_bytes(d, 1)           # 8-bit sums fit 32 bits at any radius
+    b3_64 = lib.oss_ref_bytes(d, 7, 64)    # radius <= 64: every sum below 2^32
+    tables = 3 * 4097 * 4112
+    assert tables * 4 <= b1 < tables * 4 * 1.2 and b3 >= 3 * tables * 8
+    assert b3 < 3 * tables * 8 * 1.2
+    assert 3 * tables * 4 <= b3_64 < 3 * tables * 4 * 1.2
+    # 12-bit squares at radius 96 do not fit 32 bits; sums alone do
+    d12 = lib.image_desc(1024, 1024, lib.OSS_U16, 12)
+    assert lib.oss_ref_bytes(d12, 2, 96) > 1.9 * lib.oss_ref_bytes(d12, 1, 96)
     with pytest.raises(lib.OssError):
         lib.oss_ref_bytes(lib.image_desc(0, 10), 7)
     with pytest.raises(lib.OssError):
@@ -117,5 +122,5 @@ def test_screen_argument_errors_before_any_launch(lib):
     bad = lib.tolerance((1, 1, 1), 0)
     assert L.oss_screen(None, None, tm, 1, pr, 1, C.byref(bad), 7, None, None, 0, None,
                         None) == lib.OSS_E_ARG
-    assert L.oss_ref_create(None, None, 7, None) == lib.OSS_E_ARG
+    assert L.oss_ref_create(None, None, 7, -1, None) == lib.OSS_E_ARG
     assert L.oss_ref_build(None, None, None) == lib.OSS_E_ARG

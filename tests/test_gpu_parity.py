@@ -18,20 +18,24 @@ def runner():
 
 
 TABLE_CASES = [
-    # (H, W, depth, feature mask, pitch padding)
-    (37, 53, 8, 7, 0),
-    (1, 1, 8, 7, 0),
-    (5, 700, 8, 3, 0),       # two final-pass tiles across
-    (129, 100, 12, 7, 0),    # a partial last band
-    (33, 1000, 8, 5, 13),    # three tiles across, pitch > width
-    (70, 450, 8, 4, 0),
-    (64, 64, 16, 2, 0),      # full 16-bit squares
+    # (H, W, depth, feature mask, pitch padding, max radius)
+    (37, 53, 8, 7, 0, -1),
+    (37, 53, 8, 7, 0, 1 << 20),     # forced 64-bit storage
+    (1, 1, 8, 7, 0, -1),
+    (5, 700, 8, 3, 0, -1),          # two final-pass tiles across
+    (129, 100, 12, 7, 0, -1),       # a partial last band
+    (129, 100, 12, 7, 0, 8),        # 32-bit storage, 12-bit squares
+    (33, 1000, 8, 5, 13, -1),       # three tiles across, pitch > width
+    (33, 1000, 8, 5, 13, 1 << 20),
+    (70, 450, 8, 4, 0, -1),
+    (64, 64, 16, 2, 0, -1),         # full 16-bit squares (64-bit storage)
+    (91, 931, 16, 1, 0, 3),         # 16-bit sums, 32-bit storage
 ]
 
 
 @pytest.mark.parametrize("case", TABLE_CASES, ids=lambda c: "x".join(map(str, c)))
 def test_tables_match_definitions(runner, case):
-    H, W, depth, fm, pad = case
+    H, W, depth, fm, pad, max_r = case
     rng = np.random.default_rng(H * 1000 + W)
     dt = np.uint8 if depth == 8 else np.uint16
     img = rng.integers(0, 2 ** depth, (H, W)).astype(dt)
@@ -43,21 +47,35 @@ def test_tables_match_definitions(runner, case):
         t_img = runner.L.device_image(wide, runner.dev)[:, :W]
     else:
         t_img = runner.L.device_image(img, runner.dev)
-    ref = runner.ctx.reference(t_img, fm, depth)
+    ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
     torch.cuda.synchronize()
     got = ref.tables_host()
+    bits = ref.value_bits
     ref.release()
     want = tables_numpy(img, fm)
+    if bits == 32:
+        want = [w_ % (1 << 32) for w_ in want]
+    bad = []
     for name, g, w in zip(("L", "R", "R'"), got, want):
-        assert np.array_equal(g, w), (name, np.argwhere(g != w)[:5])
+        diff = np.argwhere(g.astype(np.int64) != w)
+        if len(diff):
+            bad.append(f"{name}: {len(diff)} wrong entries of {g.size}, first (row, col, q) "
+                       f"{diff[:6].tolist()} (table row = y+1, col = x+1)")
+    assert not bad, f"{bits}-bit tables: " + "; ".join(bad)
 
 
-def _screen_and_compare(runner, w, **kw):
+WIDTHS = pytest.mark.parametrize("max_r", [-2, 1 << 20], ids=["w32", "w64"])
+
+
+def _screen_and_compare(runner, w, max_r=-1, **kw):
+    if max_r == -2:  # the largest probe radius: the narrowest exact storage
+        max_r = max(p[2] for p in w.probes)
     tm = [(t.pixels, t.rho) for t in w.templates]
     P, Q = w.tol_P, w.tol_Q
     say(f"screen workload {w.cfg_id} {w.H}x{w.W} T={len(tm)} probes={len(w.probes)} {kw}")
     mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, P, Q,
-                                   bit_depth=w.depth, **kw)
+                                   bit_depth=w.depth, max_radius=max_r, **kw)
+    say(f"  storage {runner.last_value_bits}-bit, {n} candidates")
     want = oc.screen_full(w.ref, tm, w.probes, w.feat_mask, P, Q)
     wmask, wlist = oc.mask_and_list(want)
     assert n == len(wlist)
@@ -66,31 +84,36 @@ def _screen_and_compare(runner, w, **kw):
     return want
 
 
-def test_cfg1_full(runner):
+@WIDTHS
+def test_cfg1_full(runner, max_r):
     w = make_workload(1, 0)
-    want = _screen_and_compare(runner, w)
+    want = _screen_and_compare(runner, w, max_r)
     t = w.templates[0]
     assert want[0, t.cy, t.cx] == 1  # exact cut: always survives
 
 
-def test_cfg2_small_full(runner):
+@WIDTHS
+def test_cfg2_small_full(runner, max_r):
     w = make_workload(2, 0, H=256, blobs_per_512sq=800, sig_hi=24)
-    _screen_and_compare(runner, w)
+    _screen_and_compare(runner, w, max_r)
 
 
-def test_cfg2_ragged_pitch(runner):
+@WIDTHS
+def test_cfg2_ragged_pitch(runner, max_r):
     w = make_workload(2, 1, H=211, W=333, blobs_per_512sq=800, sig_hi=24)
-    _screen_and_compare(runner, w, pitch_pad=7)
+    _screen_and_compare(runner, w, max_r, pitch_pad=7)
 
 
-def test_cfg3_small_full(runner):
+@WIDTHS
+def test_cfg3_small_full(runner, max_r):
     w = make_workload(3, 0, H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20)
-    _screen_and_compare(runner, w)
+    _screen_and_compare(runner, w, max_r)
 
 
-def test_cfg5_small_full(runner):
+@WIDTHS
+def test_cfg5_small_full(runner, max_r):
     w = make_workload(5, 0, H=224, W=240, n_templates=3, blobs_per_512sq=1200, sig_hi=20)
-    _screen_and_compare(runner, w)
+    _screen_and_compare(runner, w, max_r)
 
 
 def test_single_valid_position_and_empty(runner):
@@ -98,13 +121,17 @@ def test_single_valid_position_and_empty(runner):
     img = blob_image(21, 21, rng, blobs_per_512sq=4000, sig_hi=6)
     tm = [(cut_patch(img, 10, 10, 10), 9)]
     probes = [(0, 0, 10), (0, 1, 11), (0, 2, 3)]
-    mask, cands, n = runner.screen(img, tm, probes, 7, (100, 100, 100), 100)
+    mask, cands, n = runner.screen(img, tm, probes, 7, (100, 100, 100), 100, max_radius=16)
     want = oc.screen_full(img, tm, probes, 7, (100, 100, 100), 100)
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
     assert not (want & 2).any()
     # no valid position at all
-    mask, cands, n = runner.screen(img, tm, [(0, 0, 11)], 7, (100, 100, 100), 100)
+    mask, cands, n = runner.screen(img, tm, [(0, 0, 11)], 7, (100, 100, 100), 100,
+                                   max_radius=16)
     assert n == 0 and not mask.any()
+    # a probe beyond the reference's declared maximum radius is an argument error
+    with pytest.raises(runner.L.OssError):
+        runner.screen(img, tm, [(0, 0, 11)], 7, (100, 100, 100), 100)
 
 
 def test_list_truncation(runner):
@@ -117,8 +144,9 @@ def test_list_truncation(runner):
     assert n2 == n and np.array_equal(c2, cands[:100]) and np.array_equal(m2, mask)
 
 
+@pytest.mark.parametrize("max_r", [64, 1 << 20], ids=["rmax64", "w64"])
 @pytest.mark.parametrize("depth", [8, 12, 16])
-def test_overflow_edge_constant_max(runner, depth):
+def test_overflow_edge_constant_max(runner, depth, max_r):
     """All pixels at the maximum value, largest radius: exact sums c*A(r),
     c^2*A(r), 0 pass at P = 0 everywhere the star fits."""
     H = W = 129
@@ -126,10 +154,29 @@ def test_overflow_edge_constant_max(runner, depth):
     img = np.full((H, W), c, np.uint8 if depth == 8 else np.uint16)
     tm = [(np.full((131, 131), c, img.dtype), 64)]
     probes = [(0, 0, 64), (0, 1, 63)]
-    mask, cands, n = runner.screen(img, tm, probes, 7, (0, 0, 0), 1, bit_depth=depth)
+    mask, cands, n = runner.screen(img, tm, probes, 7, (0, 0, 0), 1, bit_depth=depth,
+                                   max_radius=max_r)
     want = oc.screen_full(img, tm, probes, 7, (0, 0, 0), 1)
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
     assert want[0, 64, 64] == 3 and n == 9
+
+
+def test_32bit_storage_near_its_limit(runner):
+    """12-bit pixels, radius 10: square sums of squares reach 3.77e9 < 2^32,
+    so the reference is stored in 32-bit words; radius 11 would not fit."""
+    rng = np.random.default_rng(4)
+    img = rng.integers(3900, 4096, (64, 80)).astype(np.uint16)
+    img[20:40, 30:50] = 4095
+    tm = [(np.ascontiguousarray(img[20:43, 28:51]), 10)]
+    probes = [(0, 0, 10), (0, 1, 7)]
+    P, Q = (2, 3, 100), 1000
+    mask, cands, n = runner.screen(img, tm, probes, 7, P, Q, bit_depth=12, max_radius=10)
+    assert runner.last_value_bits == 32
+    want = oc.screen_full(img, tm, probes, 7, P, Q)
+    assert np.array_equal(cands, oc.mask_and_list(want)[1]) and n > 0
+    mask, cands, n = runner.screen(img, tm, probes, 7, P, Q, bit_depth=12, max_radius=11)
+    assert runner.last_value_bits == 64
+    assert np.array_equal(cands, oc.mask_and_list(want)[1])
 
 
 def test_deterministic(runner):
@@ -147,7 +194,8 @@ def test_cfg2_full_size_sampled(runner):
     tm = [(t.pixels, t.rho) for t in w.templates]
     say("cfg2 full size: screening 4096^2")
     mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q,
-                                   list_cap=4 << 20)
+                                   list_cap=4 << 20, max_radius=64)
+    assert runner.last_value_bits == 32
     assert n == len(cands) == int(mask.sum())
     key = (cands[:, 0] * w.H + cands[:, 1]) * w.W + cands[:, 2]
     assert (np.diff(key) > 0).all()
