@@ -140,6 +140,15 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--star-strip", type=int, default=0,
+                    help="star kernel strip width (threads per block); 0 = library default")
+    ap.add_argument("--star-blocks", type=int, default=0,
+                    help="star kernel persistent blocks per XCD; 0 = library default")
+    ap.add_argument("--star-lds", type=int, default=-1,
+                    help="1/0: star kernel with / without LDS staging; -1 = library default")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB first "
+                         "(a reference kernel of known size for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the screen shards "
@@ -160,6 +169,12 @@ def main():
     stream = torch.cuda.current_stream()
     img = L.device_image(w.ref, dev)
     ctx = Context(0)
+    if args.star_strip:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, args.star_strip)
+    if args.star_blocks:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, args.star_blocks)
+    if args.star_lds >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_LDS, args.star_lds)
     ref = ctx.reference(img, w.feat_mask, 8, build=False, max_radius=max(w.radii()))
     T = len(w.templates)
     cap = 1 << 22
@@ -174,6 +189,13 @@ def main():
         L.oss_screen(ctx.handle, ref.handle, tm, w.probes, tol, w.feat_mask, mask, cands, cap,
                      count, stream)
 
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -231,6 +253,10 @@ def main():
             "tolerance_P_over_Q": [p / w.tol_Q for p in w.tol_P], "seed": args.seed,
             "pixel_scales_per_step": ps,
             "table_value_bits": ref.value_bits,
+            "star_strip": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STRIP),
+            "star_blocks_per_xcd": L.oss_ctx_get_option(ctx.handle,
+                                                        L.OSS_OPT_STAR_BLOCKS_PER_XCD),
+            "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
         },
         "roofline": roof,
         "kernels": kern,

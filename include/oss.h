@@ -123,6 +123,23 @@ typedef struct oss_candidate {
 int oss_ctx_create(int device, oss_ctx **out);
 int oss_ctx_destroy(oss_ctx *ctx);
 
+/* Launch-shape options of a context (values are validated):
+ *   OSS_OPT_STAR_STRIP           column-strip width of the star kernel's
+ *                                sweep = threads per block (64..512, a
+ *                                multiple of 64; default 512)
+ *   OSS_OPT_STAR_BLOCKS_PER_XCD  persistent star blocks per XCD, about the
+ *                                rows of one strip an XCD has in flight
+ *                                (default 64)
+ *   OSS_OPT_STAR_LDS             1: stage the table rows that several
+ *                                lookups share in LDS; 0: load every lookup
+ *                                directly (default)
+ * They change speed only, never results. */
+#define OSS_OPT_STAR_STRIP 1
+#define OSS_OPT_STAR_BLOCKS_PER_XCD 2
+#define OSS_OPT_STAR_LDS 3
+int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
+int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
+
 /* Timing of one kernel over the launches recorded since profiling was
  * (re)enabled. */
 typedef struct oss_kernel_stat {

@@ -24,7 +24,9 @@ EXPORTED = [
     "oss_ctx_create", "oss_ctx_destroy", "oss_status_string", "oss_ref_bytes", "oss_ref_create",
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
+    "oss_ctx_set_option", "oss_ctx_get_option",
 ]
+OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS = 1, 2, 3
 
 
 class oss_image_desc(C.Structure):
@@ -90,6 +92,8 @@ def load(path: str | None = None):
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
                                        C.POINTER(i64), C.POINTER(i64)]
+    lib.oss_ctx_set_option.argtypes = [vp, i32, i32]
+    lib.oss_ctx_get_option.argtypes = [vp, i32, C.POINTER(i32)]
     lib.oss_ctx_profile.argtypes = [vp, C.c_int]
     lib.oss_ctx_profile_read.argtypes = [vp, C.POINTER(oss_kernel_stat), i32, C.POINTER(i32)]
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
@@ -169,6 +173,16 @@ def oss_ctx_create(device: int = 0) -> int:
 
 def oss_ctx_destroy(ctx: int):
     _check(load().oss_ctx_destroy(ctx), "oss_ctx_destroy")
+
+
+def oss_ctx_set_option(ctx: int, option: int, value: int):
+    _check(load().oss_ctx_set_option(ctx, int(option), int(value)), "oss_ctx_set_option")
+
+
+def oss_ctx_get_option(ctx: int, option: int) -> int:
+    v = C.c_int32()
+    _check(load().oss_ctx_get_option(ctx, int(option), C.byref(v)), "oss_ctx_get_option")
+    return v.value
 
 
 def oss_ctx_profile(ctx: int, enable: bool):

@@ -32,6 +32,9 @@ struct oss_ctx {
     PlanSlot slots[NSLOTS];
     int next_slot = 0;
     Profiler prof;
+    int star_strip = 512;          // OSS_OPT_STAR_STRIP
+    int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
+    int star_lds = 0;              // OSS_OPT_STAR_LDS
 };
 
 struct oss_ref {
@@ -398,6 +401,43 @@ int oss_template_features(const void *host_pixels, const oss_image_desc *desc, i
     return OSS_OK;
 }
 
+int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
+{
+    if (!ctx)
+        return OSS_E_ARG;
+    switch (option) {
+    case OSS_OPT_STAR_STRIP:
+        if (value < 64 || value > 512 || value % 64)
+            return OSS_E_ARG;
+        ctx->star_strip = value;
+        return OSS_OK;
+    case OSS_OPT_STAR_BLOCKS_PER_XCD:
+        if (value < 1 || value > 4096)
+            return OSS_E_ARG;
+        ctx->star_blocks_per_xcd = value;
+        return OSS_OK;
+    case OSS_OPT_STAR_LDS:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->star_lds = value;
+        return OSS_OK;
+    default:
+        return OSS_E_ARG;
+    }
+}
+
+int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
+{
+    if (!ctx || !value)
+        return OSS_E_ARG;
+    switch (option) {
+    case OSS_OPT_STAR_STRIP: *value = ctx->star_strip; return OSS_OK;
+    case OSS_OPT_STAR_BLOCKS_PER_XCD: *value = ctx->star_blocks_per_xcd; return OSS_OK;
+    case OSS_OPT_STAR_LDS: *value = ctx->star_lds; return OSS_OK;
+    default: return OSS_E_ARG;
+    }
+}
+
 int oss_ctx_profile(oss_ctx *ctx, int enable)
 {
     if (!ctx)
@@ -594,8 +634,15 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
         return rc;
     const DevTemplatePlan *dplan = static_cast<const DevTemplatePlan *>(slot->dev);
     for (int t = 0; t < n_tmpl; ++t) {
+        const StarSweep sw = make_sweep(g.H, g.W, ctx->star_strip, ctx->star_blocks_per_xcd);
+        int smax = 0, rmax = 0;
+        for (int j = 0; j < plans[t].n_radii; ++j) {
+            smax = std::max(smax, (int)plans[t].radii[j].s);
+            rmax = std::max(rmax, (int)plans[t].radii[j].r);
+        }
         hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
-                                         ctx->bits + hw * t, st, &ctx->prof);
+                                         ctx->bits + hw * t, sw, smax, rmax, ctx->star_lds != 0,
+                                         st, &ctx->prof);
         if (e != hipSuccess)
             return OSS_E_DEVICE;
     }

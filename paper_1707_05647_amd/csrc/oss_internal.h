@@ -139,9 +139,23 @@ hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_by
                         uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
                         Profiler *prof);
 
+// Persistent strip sweep of the star kernel: strips `strip` columns wide (one
+// block), each split into `parts` row ranges when there are fewer than 8
+// strips; units are dealt to the 8 XCDs round-robin.
+constexpr int STAR_MAX_THREADS = 512;
+struct StarSweep {
+    int strip, n_strips, parts, rows_per_part, n_units, blocks_per_xcd;
+};
+StarSweep make_sweep(int H, int W, int strip, int blocks_per_xcd);
+
+// LDS staging of the shared table rows is used when it needs at most
+// STAR_LDS_MAX bytes per block (smax / rmax: the largest square half-width
+// and radius among the template's probes).
+constexpr size_t STAR_LDS_MAX = 64 * 1024;
+size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax);
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream,
-                             Profiler *prof);
+                             const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                             int smax, int rmax, bool lds, hipStream_t stream, Profiler *prof);
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);

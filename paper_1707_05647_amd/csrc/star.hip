@@ -20,108 +20,269 @@
 // 32-bit tables the square and the diamond sums are formed modulo 2^32
 // (each is below 2^32, so exact) and widened before they are added.  A
 // thread walks all radii of its template (up to 32) and ORs the passing
-// scales' bits.  Blocks are assigned XCD-major: the blocks that one XCD
-// receives (every 8th block id) cover a contiguous run of rows, so the rows
-// a radius' lookups revisit 2r+1 rows later stay in that XCD's L2 / the
-// shared Infinity Cache.
+// scales' bits.
+//
+// Schedule (cache reuse): a table entry serves the positions 2s+1 and 2r+1
+// rows apart, so a row-major sweep re-reads each table row from beyond L2
+// once per use unless the rows in between stay cached.  The image is cut
+// into column strips one block wide; strip units are dealt round-robin to
+// the 8 XCDs (a hardware block id b runs on XCD b mod 8), and the blocks_per_xcd
+// persistent blocks of an XCD walk its strips row by row in lockstep.  An
+// XCD then has about blocks_per_xcd rows of one strip in flight, and its L2
+// holds the strip's table rows from 2 r_max rows above to the rows in
+// flight: (rows in flight + 2 r_max + 2) x (strip + 2 r_max) entries.
 #include "oss_internal.h"
 
 namespace oss {
 
-constexpr int STAR_THREADS = 256;
 
 template <typename T, int NQ>
-__device__ __forceinline__ void ld(const T *__restrict__ tab, int64_t e, T *v)
-{
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        v[q] = tab[e * NQ + q];
-}
+struct Entry {
+    T v[NQ];
+};
 
 // Sum of two region sums that were formed in T: with 32-bit tables each
 // region sum is exact modulo 2^32 and below 2^32, so it zero-extends.
 __device__ __forceinline__ int64_t widen(uint32_t v) { return (int64_t)v; }
 __device__ __forceinline__ int64_t widen(uint64_t v) { return (int64_t)v; }
 
+// Entry at a wave-uniform row base plus this lane's byte offset.
 template <typename T, int NQ>
-__global__ __launch_bounds__(STAR_THREADS) void star_plain_kernel(
+__device__ __forceinline__ Entry<T, NQ> at(const char *row, uint32_t lane_off)
+{
+    return *reinterpret_cast<const Entry<T, NQ> *>(row + lane_off);
+}
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
     int H, int W, const DevTemplatePlan *__restrict__ plan, uint32_t *__restrict__ bits,
-    int tiles_x, int n_tiles)
+    StarSweep sw)
 {
-    const int per_xcd = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (tile >= n_tiles)
-        return;
-    const int y = tile / tiles_x;
-    const int x = (tile - y * tiles_x) * STAR_THREADS + threadIdx.x;
-    uint32_t acc = 0;
+    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;  // bytes per table entry
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int units = (sw.n_units - xcd + 7) / 8;  // units u = xcd + 8 t of this XCD
+    const int items = units * sw.rows_per_part;
+    // byte offset of column x0 + tid + 1 relative to column x0
+    const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
+    const int64_t row_bytes = pitch_e * ES;
     const int nr = plan->n_radii;
-    for (int j = 0; j < nr; ++j) {
-        const int r = plan->radii[j].r;
-        const int s = plan->radii[j].s;
-        if (y < r || y > H - 1 - r)
+    for (int it = j; it < items; it += sw.blocks_per_xcd) {
+        const int t = it / sw.rows_per_part;
+        const int u = xcd + 8 * t;
+        const int strip = u / sw.parts, part = u - strip * sw.parts;
+        const int y = part * sw.rows_per_part + (it - t * sw.rows_per_part);
+        if (y >= H)
             continue;
-        if (x < r || x > W - 1 - r)
-            continue;
-        // entry index of (x, y) is (y+1)*pitch_e + (x+1)
-        const int64_t e0 = (int64_t)(y + 1) * pitch_e + (x + 1);
-        const int64_t dys = (int64_t)s * pitch_e;
-        const int64_t dys1 = (int64_t)(s + 1) * pitch_e;
-        const int64_t dyr = (int64_t)r * pitch_e;
-        const int64_t dyr1 = (int64_t)(r + 1) * pitch_e;
-        T a[NQ], b[NQ], c[NQ], d[NQ];
-        int64_t F[NQ];
-        ld<T, NQ>(L, e0 + dys + s, a);
-        ld<T, NQ>(L, e0 + dys - s - 1, b);
-        ld<T, NQ>(L, e0 - dys1 + s, c);
-        ld<T, NQ>(L, e0 - dys1 - s - 1, d);
+        const int x0 = strip * (int)blockDim.x;
+        const int x = x0 + threadIdx.x;
+        const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
+        const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
+        const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
+        uint32_t acc = 0;
+        for (int jr = 0; jr < nr; ++jr) {
+            const DevRadius rd = plan->radii[jr];
+            const int r = rd.r, s = rd.s;
+            if (y < r || y > H - 1 - r)
+                continue;
+            if (x >= r && x <= W - 1 - r) {
+                // table row of image row y' is y' + 1; table column of x' is x' + 1
+                const char *l_top = Lb + (int64_t)(y - s) * row_bytes;       // row y-s-1
+                const char *l_bot = Lb + (int64_t)(y + s + 1) * row_bytes;   // row y+s
+                const char *r_top = Rb + (int64_t)(y - r) * row_bytes;       // row y-r-1
+                const char *r_bot = Rb + (int64_t)(y + r + 1) * row_bytes;   // row y+r
+                const char *rp_mid = Rpb + (int64_t)y * row_bytes;            // row y-1
+                const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
+                const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
+                const Entry<T, NQ> a = at<T, NQ>(l_bot + ds, lane_off);    // L(x+s,   y+s)
+                const Entry<T, NQ> b = at<T, NQ>(l_bot - ds1, lane_off);   // L(x-s-1, y+s)
+                const Entry<T, NQ> c = at<T, NQ>(l_top + ds, lane_off);    // L(x+s,   y-s-1)
+                const Entry<T, NQ> d = at<T, NQ>(l_top - ds1, lane_off);   // L(x-s-1, y-s-1)
+                const Entry<T, NQ> e = at<T, NQ>(r_bot, lane_off);         // R(x, y+r)
+                const Entry<T, NQ> f = at<T, NQ>(rp_mid - dr1, lane_off);  // R'(x-r-1, y-1)
+                const Entry<T, NQ> h = at<T, NQ>(rp_mid + dr, lane_off);   // R'(x+r, y-1)
+                const Entry<T, NQ> k = at<T, NQ>(r_top, lane_off);         // R(x, y-r-1)
+                int64_t F[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            F[q] = widen((T)(a[q] - b[q] - c[q] + d[q]));
-        ld<T, NQ>(R, e0 + dyr, a);
-        ld<T, NQ>(Rp, e0 - pitch_e - r - 1, b);
-        ld<T, NQ>(Rp, e0 - pitch_e + r, c);
-        ld<T, NQ>(R, e0 - dyr1, d);
+                for (int q = 0; q < NQ; ++q)
+                    F[q] = widen((T)(a.v[q] - b.v[q] - c.v[q] + d.v[q])) +
+                           widen((T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]));
+                for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                    const DevProbe pr = plan->probes[p];
+                    bool pass = true;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            F[q] += widen((T)(a[q] - b[q] - c[q] + d[q]));
-        const int p0 = plan->radii[j].first;
-        const int p1 = p0 + plan->radii[j].count;
-        for (int p = p0; p < p1; ++p) {
-            const DevProbe &pr = plan->probes[p];
-            bool pass = true;
+                    for (int q = 0; q < NQ; ++q)
+                        pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                    acc |= pass ? (1u << pr.k) : 0u;
+                }
+            }
+        }
+        if (x < W)
+            bits[(int64_t)y * W + x] = acc;
+    }
+}
+
+// Same screen with the rows that several lookups share staged in LDS: per
+// block row (strip columns [x0, x0 + strip) of image row y) the R' row y-1
+// is loaded once for all radii over [x0 - r_max - 1, x0 + strip - 1 + r_max],
+// and for each radius the two L rows y+s and y-s-1 are loaded once over
+// [x0 - s - 1, x0 + strip - 1 + s], serving both of their lookups.  The two R
+// lookups have no neighbour to share with and stay direct loads.  LDS is
+// quantity-major (one column of T per quantity) so lanes hit consecutive
+// banks.
+template <typename T, int NQ>
+__device__ __forceinline__ void stage_row(T *__restrict__ dst, int cap, const char *row_base,
+                                          int col0, int n, int pitch_e)
+{
+    // dst[q * cap + i] = entry (column col0 + i) of the table row at row_base
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int c = col0 + i + 1;  // table column
+        if (c >= 0 && c < pitch_e) {
+            const Entry<T, NQ> v =
+                *reinterpret_cast<const Entry<T, NQ> *>(row_base + (int64_t)c * sizeof(T) * NQ);
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                pass = pass && F[q] >= pr.lo[q] && F[q] <= pr.hi[q];
-            acc |= pass ? (1u << pr.k) : 0u;
+                dst[q * cap + i] = v.v[q];
         }
     }
-    if (x < W)
-        bits[(int64_t)y * W + x] = acc;
+}
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(STAR_MAX_THREADS) void star_lds_kernel(
+    const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
+    int H, int W, const DevTemplatePlan *__restrict__ plan, uint32_t *__restrict__ bits,
+    StarSweep sw, int smax, int rmax)
+{
+    extern __shared__ char smem_raw[];
+    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    const int strip = blockDim.x;
+    const int capL = strip + 2 * smax + 1, capR = strip + 2 * rmax + 1;
+    T *lt = reinterpret_cast<T *>(smem_raw);  // L row y-s-1   [NQ][capL]
+    T *lb = lt + NQ * capL;                    // L row y+s     [NQ][capL]
+    T *rw = lb + NQ * capL;                    // R' row y-1    [NQ][capR]
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int units = (sw.n_units - xcd + 7) / 8;
+    const int items = units * sw.rows_per_part;
+    const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
+    const int64_t row_bytes = pitch_e * ES;
+    const int tid = threadIdx.x;
+    const int nr = plan->n_radii;
+    for (int it = j; it < items; it += sw.blocks_per_xcd) {
+        const int t = it / sw.rows_per_part;
+        const int u = xcd + 8 * t;
+        const int strip_i = u / sw.parts, part = u - strip_i * sw.parts;
+        const int y = part * sw.rows_per_part + (it - t * sw.rows_per_part);
+        if (y >= H)
+            continue;
+        const int x0 = strip_i * strip;
+        const int x = x0 + tid;
+        const char *Lb = reinterpret_cast<const char *>(L);
+        const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
+        const char *Rpb = reinterpret_cast<const char *>(Rp);
+        __syncthreads();  // the previous row's readers are done with LDS
+        stage_row<T, NQ>(rw, capR, Rpb + (int64_t)y * row_bytes, x0 - rmax - 1,
+                         strip + 2 * rmax + 1, (int)pitch_e);
+        uint32_t acc = 0;
+        for (int jr = 0; jr < nr; ++jr) {
+            const DevRadius rd = plan->radii[jr];
+            const int r = rd.r, s = rd.s;
+            if (y < r || y > H - 1 - r)
+                continue;
+            const bool valid = x >= r && x <= W - 1 - r;
+            Entry<T, NQ> e, k;
+            if (valid) {
+                e = at<T, NQ>(Rb + (int64_t)(y + r + 1) * row_bytes, lane_off);  // R(x, y+r)
+                k = at<T, NQ>(Rb + (int64_t)(y - r) * row_bytes, lane_off);      // R(x, y-r-1)
+            }
+            __syncthreads();  // the previous radius' L readers are done
+            const int n = strip + 2 * s + 1;
+            stage_row<T, NQ>(lt, capL, Lb + (int64_t)(y - s) * row_bytes, x0 - s - 1, n,
+                             (int)pitch_e);
+            stage_row<T, NQ>(lb, capL, Lb + (int64_t)(y + s + 1) * row_bytes, x0 - s - 1, n,
+                             (int)pitch_e);
+            __syncthreads();
+            if (valid) {
+                int64_t F[NQ];
+                const int ia = tid + 2 * s + 1, ib = tid;          // x+s, x-s-1 in the L window
+                const int jf = tid + rmax - r, jh = tid + rmax + r + 1;  // x-r-1, x+r in the R' window
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const T sq = lb[q * capL + ia] - lb[q * capL + ib] - lt[q * capL + ia] +
+                                 lt[q * capL + ib];
+                    const T dm = e.v[q] - rw[q * capR + jf] - rw[q * capR + jh] + k.v[q];
+                    F[q] = widen(sq) + widen(dm);
+                }
+                for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                    const DevProbe pr = plan->probes[p];
+                    bool pass = true;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                    acc |= pass ? (1u << pr.k) : 0u;
+                }
+            }
+        }
+        if (x < W)
+            bits[(int64_t)y * W + x] = acc;
+    }
+}
+
+size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax)
+{
+    return (size_t)nq * ebytes * (2 * (size_t)(strip + 2 * smax + 1) + (strip + 2 * rmax + 1));
+}
+
+StarSweep make_sweep(int H, int W, int strip, int blocks_per_xcd)
+{
+    StarSweep sw;
+    sw.strip = strip;
+    sw.n_strips = (W + strip - 1) / strip;
+    sw.parts = sw.n_strips >= 8 ? 1 : (8 + sw.n_strips - 1) / sw.n_strips;
+    sw.rows_per_part = (H + sw.parts - 1) / sw.parts;
+    sw.n_units = sw.n_strips * sw.parts;
+    sw.blocks_per_xcd = blocks_per_xcd;
+    return sw;
+}
+
+template <typename T, int NQ>
+static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T *rp,
+                            const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                            int smax, int rmax, hipStream_t stream)
+{
+    const size_t lds = star_lds_bytes(sw.strip, NQ, sizeof(T), smax, rmax);
+    hipLaunchKernelGGL((star_lds_kernel<T, NQ>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), lds,
+                       stream, l, r, rp, g.pitch_e, g.H, g.W, plan, bits, sw, smax, rmax);
 }
 
 template <typename T>
 static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                         const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream)
+                         const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                         int smax, int rmax, bool lds, hipStream_t stream)
 {
-    const int tiles_x = (g.W + STAR_THREADS - 1) / STAR_THREADS;
-    const int n_tiles = tiles_x * g.H;
-    const int nblk = (n_tiles + 7) / 8 * 8;
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
+    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+    if (lds) {
+        switch (g.nq) {
+        case 1: star_lds_launch<T, 1>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
+        case 2: star_lds_launch<T, 2>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
+        case 3: star_lds_launch<T, 3>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (g.nq) {
     case 1:
-        hipLaunchKernelGGL((star_plain_kernel<T, 1>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
-                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 1>), grid, block, 0, stream, l, r, rp,
+                           g.pitch_e, g.H, g.W, plan, bits, sw);
         break;
     case 2:
-        hipLaunchKernelGGL((star_plain_kernel<T, 2>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
-                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 2>), grid, block, 0, stream, l, r, rp,
+                           g.pitch_e, g.H, g.W, plan, bits, sw);
         break;
     case 3:
-        hipLaunchKernelGGL((star_plain_kernel<T, 3>), dim3(nblk), dim3(STAR_THREADS), 0, stream,
-                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, tiles_x, n_tiles);
+        hipLaunchKernelGGL((star_plain_kernel<T, 3>), grid, block, 0, stream, l, r, rp,
+                           g.pitch_e, g.H, g.W, plan, bits, sw);
         break;
     default:
         return hipErrorInvalidValue;
@@ -130,13 +291,17 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
 }
 
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const DevTemplatePlan *plan, uint32_t *bits, hipStream_t stream,
-                             Profiler *prof)
+                             const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                             int smax, int rmax, bool lds, hipStream_t stream, Profiler *prof)
 {
+    if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1)
+        return hipErrorInvalidValue;
+    if (lds && star_lds_bytes(sw.strip, g.nq, g.ebytes, smax, rmax) > STAR_LDS_MAX)
+        lds = false;
     ProfScope ps(prof, K_STAR, stream);
     if (g.ebytes == 4)
-        return star_t<uint32_t>(g, L, R, Rp, plan, bits, stream);
-    return star_t<uint64_t>(g, L, R, Rp, plan, bits, stream);
+        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);
+    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);
 }
 
 }  // namespace oss

@@ -179,6 +179,27 @@ def test_32bit_storage_near_its_limit(runner):
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
 
 
+@pytest.mark.parametrize("strip,blocks,lds", [(64, 1, 1), (512, 3, 1), (128, 500, 1),
+                                               (256, 64, 0), (64, 7, 0)])
+def test_launch_shapes_do_not_change_results(runner, strip, blocks, lds):
+    w = make_workload(2, 3, H=300, W=700, blobs_per_512sq=800, sig_hi=24)
+    tm = [(t.pixels, t.rho) for t in w.templates]
+    base = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q)
+    L = runner.L
+    opts = (L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD, L.OSS_OPT_STAR_LDS)
+    old = [L.oss_ctx_get_option(runner.ctx.handle, o) for o in opts]
+    for o, v in zip(opts, (strip, blocks, lds)):
+        L.oss_ctx_set_option(runner.ctx.handle, o, v)
+    try:
+        got = runner.screen(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q)
+    finally:
+        for o, v in zip(opts, old):
+            L.oss_ctx_set_option(runner.ctx.handle, o, v)
+    assert got[2] == base[2] and np.array_equal(got[1], base[1])
+    with pytest.raises(L.OssError):
+        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_STAR_STRIP, 100)
+
+
 def test_deterministic(runner):
     w = make_workload(3, 3, H=160, n_templates=3, blobs_per_512sq=1200, sig_hi=20)
     tm = [(t.pixels, t.rho) for t in w.templates]
