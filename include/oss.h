@@ -133,10 +133,14 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *   OSS_OPT_STAR_LDS             1: stage the table rows that several
  *                                lookups share in LDS; 0: load every lookup
  *                                directly (default)
+ *   OSS_OPT_BATCH_BUCKET         oss_screen_batched: at most this many distinct
+ *                                radii per pass (0: all radii of a template
+ *                                group in one pass; default 0)
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
 #define OSS_OPT_STAR_LDS 3
+#define OSS_OPT_BATCH_BUCKET 4
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 
@@ -246,6 +250,47 @@ int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl, 
                const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
                uint32_t feat_mask, uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
                int64_t *dev_count, void *stream);
+
+/*
+ * Same contract and outputs as oss_screen, with all templates and probes in
+ * one persistent launch over the reference's tables (Algorithm 1's patch
+ * loop for every template and scale together).  Templates are sorted by
+ * radius and taken in groups of 32; within a group the star features of
+ * each distinct radius are computed once per position and compared with
+ * every probe of the group at that radius.  A group's radii are walked in
+ * passes of at most OSS_OPT_BATCH_BUCKET distinct radii.  Results are
+ * identical to oss_screen's.
+ */
+int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                       int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                       const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                       oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                       void *stream);
+
+#define OSS_TUNE_MAX 64
+/* Autotuner result: the chosen shape, its time, and every candidate tried
+ * (strip, blocks per XCD, bucket) with its time in ms. */
+typedef struct oss_tune_result {
+    int32_t strip, blocks_per_xcd, bucket_radii;
+    float ms;
+    int32_t n_tried;
+    int32_t tried[OSS_TUNE_MAX][3];
+    float tried_ms[OSS_TUNE_MAX];
+} oss_tune_result;
+
+/*
+ * Autotune oss_screen_batched for this reference and probe set: time the
+ * batched star pass (HIP events on `stream`, one warm-up and one timed run
+ * per candidate) over strip widths {256, 512}, blocks per XCD {32, 64, 128}
+ * and radius buckets {all, 16, 8, 4}, keep the fastest in the context's
+ * options (OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD,
+ * OSS_OPT_BATCH_BUCKET) and report every candidate in *out.  Synchronises
+ * `stream`; overwrites the context's screen workspace.
+ */
+int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                         int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                         const oss_tolerance *tol, uint32_t feat_mask, void *stream,
+                         oss_tune_result *out);
 
 #ifdef __cplusplus
 }

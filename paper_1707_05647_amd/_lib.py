@@ -24,9 +24,10 @@ EXPORTED = [
     "oss_ctx_create", "oss_ctx_destroy", "oss_status_string", "oss_ref_bytes", "oss_ref_create",
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
-    "oss_ctx_set_option", "oss_ctx_get_option",
+    "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
 ]
-OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS = 1, 2, 3
+OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
+OSS_TUNE_MAX = 64
 
 
 class oss_image_desc(C.Structure):
@@ -53,6 +54,12 @@ class oss_candidate(C.Structure):
 class oss_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("max_ms", C.c_double)]
+
+
+class oss_tune_result(C.Structure):
+    _fields_ = [("strip", C.c_int32), ("blocks_per_xcd", C.c_int32), ("bucket_radii", C.c_int32),
+                ("ms", C.c_float), ("n_tried", C.c_int32),
+                ("tried", (C.c_int32 * 3) * OSS_TUNE_MAX), ("tried_ms", C.c_float * OSS_TUNE_MAX)]
 
 
 class OssError(RuntimeError):
@@ -98,6 +105,10 @@ def load(path: str | None = None):
     lib.oss_ctx_profile_read.argtypes = [vp, C.POINTER(oss_kernel_stat), i32, C.POINTER(i32)]
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
+    lib.oss_screen_batched.argtypes = lib.oss_screen.argtypes
+    lib.oss_autotune_batched.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32,
+                                         C.POINTER(oss_probe), i32, C.POINTER(oss_tolerance), u32,
+                                         vp, C.POINTER(oss_tune_result)]
     for name in EXPORTED:
         if name != "oss_status_string":
             getattr(lib, name).restype = C.c_int
@@ -254,11 +265,7 @@ def oss_feature_bounds(feature: int, FT: int, r: int, rho: int, P, Q: int):
     return lo.value, hi.value
 
 
-def oss_screen(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None, cand_list=None,
-               list_cap: int = 0, count=None, stream=None):
-    """tmpl: sequence of oss_template_feat; probes: sequence of (t, k, r);
-    tol: (P0, P1, P2, Q) or oss_tolerance; mask/cand_list/count: torch
-    device tensors (uint8 [T,H,W], int32 [cap,4], int64 [1])."""
+def _screen_args(tmpl, probes, tol):
     nt = len(tmpl)
     ta = (oss_template_feat * nt)(*tmpl)
     npb = len(probes)
@@ -266,8 +273,34 @@ def oss_screen(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None,
     if not isinstance(tol, oss_tolerance):
         P0, P1, P2, Q = tol
         tol = oss_tolerance((C.c_int32 * 3)(int(P0), int(P1), int(P2)), int(Q))
+    return ta, nt, pa, npb, tol
+
+
+def oss_screen(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None, cand_list=None,
+               list_cap: int = 0, count=None, stream=None, batched: bool = False):
+    """tmpl: sequence of oss_template_feat; probes: sequence of (t, k, r);
+    tol: (P0, P1, P2, Q) or oss_tolerance; mask/cand_list/count: torch
+    device tensors (uint8 [T,H,W], int32 [cap,4], int64 [1]).  batched=True
+    calls oss_screen_batched."""
+    ta, nt, pa, npb, tol = _screen_args(tmpl, probes, tol)
     if count is None:
         raise ValueError("count tensor required")
-    _check(load().oss_screen(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask), _ptr(mask),
-                             _ptr(cand_list), int(list_cap), _ptr(count), _stream(stream)),
-           "oss_screen")
+    fn = load().oss_screen_batched if batched else load().oss_screen
+    _check(fn(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask), _ptr(mask),
+              _ptr(cand_list), int(list_cap), _ptr(count), _stream(stream)),
+           "oss_screen_batched" if batched else "oss_screen")
+
+
+def oss_screen_batched(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None,
+                       cand_list=None, list_cap: int = 0, count=None, stream=None):
+    oss_screen(ctx, ref, tmpl, probes, tol, feat_mask, mask, cand_list, list_cap, count, stream,
+               batched=True)
+
+
+def oss_autotune_batched(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int,
+                         stream=None) -> oss_tune_result:
+    ta, nt, pa, npb, tol = _screen_args(tmpl, probes, tol)
+    out = oss_tune_result()
+    _check(load().oss_autotune_batched(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask),
+                                       _stream(stream), C.byref(out)), "oss_autotune_batched")
+    return out

@@ -35,6 +35,7 @@ struct oss_ctx {
     int star_strip = 512;          // OSS_OPT_STAR_STRIP
     int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
     int star_lds = 0;              // OSS_OPT_STAR_LDS
+    int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
 };
 
 struct oss_ref {
@@ -421,6 +422,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->star_lds = value;
         return OSS_OK;
+    case OSS_OPT_BATCH_BUCKET:
+        if (value < 0 || value > 4096)
+            return OSS_E_ARG;
+        ctx->batch_bucket = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -434,6 +440,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_STAR_STRIP: *value = ctx->star_strip; return OSS_OK;
     case OSS_OPT_STAR_BLOCKS_PER_XCD: *value = ctx->star_blocks_per_xcd; return OSS_OK;
     case OSS_OPT_STAR_LDS: *value = ctx->star_lds; return OSS_OK;
+    case OSS_OPT_BATCH_BUCKET: *value = ctx->batch_bucket; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }
@@ -591,11 +598,11 @@ static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t
     return OSS_OK;
 }
 
-extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
-                          int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
-                          const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
-                          oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
-                          void *stream)
+// Argument checks shared by the screens (before anything is launched).
+static int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                             int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                             const oss_tolerance *tol, uint32_t feat_mask, int64_t list_cap,
+                             const oss_candidate *dev_list, const int64_t *dev_count)
 {
     if (!ctx || !ref || !tmpl || n_tmpl <= 0 || (n_probes > 0 && !probes) || n_probes < 0 || !tol ||
         !dev_count || list_cap < 0 || (list_cap > 0 && !dev_list))
@@ -612,8 +619,30 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     for (int t = 0; t < n_tmpl; ++t)
         if ((tmpl[t].feat_mask & feat_mask) != feat_mask || tmpl[t].rho < 0)
             return OSS_E_ARG;
+    return OSS_OK;
+}
+
+static int screen_workspace(oss_ctx *ctx, int64_t n)
+{
+    int rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap,
+                  (size_t)n * sizeof(uint32_t));
+    if (rc != OSS_OK)
+        return rc;
+    return grow(&ctx->cws, &ctx->cws_cap, compact_workspace_bytes(n));
+}
+
+extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                          int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                          const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                          oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                          void *stream)
+{
+    int rc = check_screen_args(ctx, ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, list_cap,
+                               dev_list, dev_count);
+    if (rc != OSS_OK)
+        return rc;
     std::vector<DevTemplatePlan> plans;
-    int rc = make_plans(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, plans);
+    rc = make_plans(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, plans);
     if (rc != OSS_OK)
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
@@ -622,10 +651,7 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     const BuildGeom &g = ref->geom;
     const int64_t hw = (int64_t)g.H * g.W;
     const int64_t n = hw * n_tmpl;
-    rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap, (size_t)n * sizeof(uint32_t));
-    if (rc != OSS_OK)
-        return rc;
-    rc = grow(&ctx->cws, &ctx->cws_cap, compact_workspace_bytes(n));
+    rc = screen_workspace(ctx, n);
     if (rc != OSS_OK)
         return rc;
     PlanSlot *slot = nullptr;
@@ -653,5 +679,282 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     if (hipEventRecord(slot->ev, st) != hipSuccess)
         return OSS_E_DEVICE;
     slot->used = true;
+    return OSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched screen.
+// ---------------------------------------------------------------------------
+struct BatchHostPlan {
+    std::vector<DevBatchPass> passes;
+    std::vector<DevBatchGroup> groups;
+    std::vector<DevRadius> radii;
+    std::vector<DevBatchProbe> probes;
+    int max_group = 0;
+};
+
+// Templates sorted by radius and cut into groups of BATCH_GROUP; each group's
+// probes sorted by reference radius; every run of at most `bucket` distinct
+// radii (0: all) becomes one pass.
+static int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                           const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+                           uint32_t fm, int bucket, BatchHostPlan &bp)
+{
+    std::vector<std::vector<oss_probe>> per(n_tmpl);
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
+            return OSS_E_ARG;
+        per[p.template_id].push_back(p);
+        if ((int)per[p.template_id].size() > OSS_MAX_SCALES)
+            return OSS_E_ARG;
+    }
+    int slot_of[3], slot = 0;
+    for (int f = 0; f < 3; ++f)
+        slot_of[f] = (ref->feat_mask & (1u << f)) ? slot++ : -1;
+    std::vector<int> order(n_tmpl);
+    for (int t = 0; t < n_tmpl; ++t)
+        order[t] = t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return tmpl[a].rho < tmpl[b].rho; });
+    for (int g0 = 0; g0 < n_tmpl; g0 += BATCH_GROUP) {
+        const int nt = std::min(BATCH_GROUP, n_tmpl - g0);
+        DevBatchGroup grp{};
+        grp.n_t = nt;
+        struct Item {
+            int r, slot;
+            oss_probe p;
+        };
+        std::vector<Item> items;
+        for (int i = 0; i < nt; ++i) {
+            const int t = order[g0 + i];
+            grp.tmap[i] = t;
+            for (const oss_probe &p : per[t])
+                items.push_back({p.r, i, p});
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const Item &a, const Item &b) { return a.r < b.r; });
+        const int gi = (int)bp.groups.size();
+        bp.groups.push_back(grp);
+        bp.max_group = std::max(bp.max_group, nt);
+        const int rad_begin = (int)bp.radii.size();
+        for (const Item &it : items) {
+            if ((int)bp.radii.size() == rad_begin || bp.radii.back().r != it.r) {
+                DevRadius rd;
+                rd.r = it.r;
+                rd.s = square_half(it.r);
+                rd.first = (int32_t)bp.probes.size();
+                rd.count = 0;
+                bp.radii.push_back(rd);
+            }
+            bp.radii.back().count++;
+            DevBatchProbe dp{};
+            dp.t = it.slot;
+            dp.k = it.p.scale_id;
+            for (int q = 0; q < 3; ++q) {
+                dp.lo[q] = INT64_MIN;
+                dp.hi[q] = INT64_MAX;
+            }
+            const oss_template_feat &tf = tmpl[grp.tmap[it.slot]];
+            for (int f = 0; f < 3; ++f) {
+                if (!(fm & (1u << f)))
+                    continue;
+                feature_bounds(f, tf.F[f], it.r, tf.rho, tol->P[f], tol->Q, &dp.lo[slot_of[f]],
+                               &dp.hi[slot_of[f]]);
+            }
+            bp.probes.push_back(dp);
+        }
+        const int rad_end = (int)bp.radii.size();
+        const int step = bucket > 0 ? bucket : std::max(1, rad_end - rad_begin);
+        int j0 = rad_begin;
+        do {
+            const int j1 = std::min(rad_end, j0 + step);
+            bp.passes.push_back({gi, j0, j1, j0 == rad_begin ? 1 : 0});
+            j0 = j1;
+        } while (j0 < rad_end);
+    }
+    return OSS_OK;
+}
+
+// Pack the plan into one upload; returns device pointers into the slot.
+static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t st,
+                             BatchDevPlan *dev, PlanSlot **slot)
+{
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t o_pass = 0;
+    const size_t o_grp = al(o_pass + bp.passes.size() * sizeof(DevBatchPass));
+    const size_t o_rad = al(o_grp + bp.groups.size() * sizeof(DevBatchGroup));
+    const size_t o_prb = al(o_rad + bp.radii.size() * sizeof(DevRadius));
+    const size_t total = al(o_prb + std::max<size_t>(1, bp.probes.size()) * sizeof(DevBatchProbe));
+    std::vector<char> buf(total, 0);
+    std::memcpy(buf.data() + o_pass, bp.passes.data(), bp.passes.size() * sizeof(DevBatchPass));
+    std::memcpy(buf.data() + o_grp, bp.groups.data(), bp.groups.size() * sizeof(DevBatchGroup));
+    std::memcpy(buf.data() + o_rad, bp.radii.data(), bp.radii.size() * sizeof(DevRadius));
+    std::memcpy(buf.data() + o_prb, bp.probes.data(), bp.probes.size() * sizeof(DevBatchProbe));
+    int rc = upload_plan(ctx, buf.data(), total, st, slot);
+    if (rc != OSS_OK)
+        return rc;
+    const char *d = static_cast<const char *>((*slot)->dev);
+    dev->passes = reinterpret_cast<const DevBatchPass *>(d + o_pass);
+    dev->n_passes = (int)bp.passes.size();
+    dev->groups = reinterpret_cast<const DevBatchGroup *>(d + o_grp);
+    dev->radii = reinterpret_cast<const DevRadius *>(d + o_rad);
+    dev->probes = reinterpret_cast<const DevBatchProbe *>(d + o_prb);
+    dev->max_group = bp.max_group;
+    return OSS_OK;
+}
+
+// The batched star pass alone (scale bits into the context workspace).
+static int batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip,
+                      int blocks, hipStream_t st, PlanSlot **slot)
+{
+    BatchDevPlan dev{};
+    int rc = upload_batch_plan(ctx, bp, st, &dev, slot);
+    if (rc != OSS_OK)
+        return rc;
+    const BuildGeom &g = ref->geom;
+    const StarSweep sw = make_sweep(g.H, g.W, strip, blocks);
+    if (launch_star_batch(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dev, ctx->bits, sw, st,
+                          &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    return OSS_OK;
+}
+
+extern "C" int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref,
+                                  const oss_template_feat *tmpl, int32_t n_tmpl,
+                                  const oss_probe *probes, int32_t n_probes,
+                                  const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                                  oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                                  void *stream)
+{
+    int rc = check_screen_args(ctx, ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, list_cap,
+                               dev_list, dev_count);
+    if (rc != OSS_OK)
+        return rc;
+    BatchHostPlan bp;
+    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, ctx->batch_bucket,
+                         bp);
+    if (rc != OSS_OK)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
+    rc = screen_workspace(ctx, n);
+    if (rc != OSS_OK)
+        return rc;
+    PlanSlot *slot = nullptr;
+    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
+                       ctx->cws, st, &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
+    return OSS_OK;
+}
+
+// Empirical search over the batched launch's shape: each candidate (strip
+// width, blocks per XCD, radius bucket) runs the star pass once to warm up
+// and once timed with HIP events on `stream`; the fastest is kept in the
+// context's options.
+extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
+                                    const oss_template_feat *tmpl, int32_t n_tmpl,
+                                    const oss_probe *probes, int32_t n_probes,
+                                    const oss_tolerance *tol, uint32_t feat_mask, void *stream,
+                                    oss_tune_result *out)
+{
+    const int64_t dummy_count = 0;
+    int rc = check_screen_args(ctx, ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, 0,
+                               nullptr, &dummy_count);
+    if (rc != OSS_OK)
+        return rc;
+    if (!out)
+        return OSS_E_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    rc = screen_workspace(ctx, (int64_t)g.H * g.W * n_tmpl);
+    if (rc != OSS_OK)
+        return rc;
+    // distinct radii per group bound the useful bucket sizes
+    BatchHostPlan whole;
+    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, 0, whole);
+    if (rc != OSS_OK)
+        return rc;
+    int max_radii = 0;
+    for (const DevBatchPass &p : whole.passes)
+        max_radii = std::max(max_radii, p.j1 - p.j0);
+    const int strips[] = {256, 512};
+    const int blocks[] = {32, 64, 128};
+    std::vector<int> buckets = {0};
+    for (int b : {16, 8, 4})
+        if (b < max_radii)
+            buckets.push_back(b);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return OSS_E_DEVICE;
+    std::memset(out, 0, sizeof(*out));
+    float best = 1e30f;
+    int n = 0;
+    rc = OSS_OK;
+    for (int bk : buckets) {
+        BatchHostPlan bp;
+        rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, bk, bp);
+        if (rc != OSS_OK)
+            break;
+        for (int sp : strips) {
+            for (int bl : blocks) {
+                PlanSlot *slot = nullptr;
+                rc = batch_star(ctx, ref, bp, sp, bl, st, &slot);  // warm-up
+                if (rc != OSS_OK)
+                    break;
+                if (hipEventRecord(e0, st) != hipSuccess) {
+                    rc = OSS_E_DEVICE;
+                    break;
+                }
+                rc = batch_star(ctx, ref, bp, sp, bl, st, &slot);
+                if (rc != OSS_OK)
+                    break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = OSS_E_DEVICE;
+                    break;
+                }
+                if (n < OSS_TUNE_MAX) {
+                    out->tried[n][0] = sp;
+                    out->tried[n][1] = bl;
+                    out->tried[n][2] = bk;
+                    out->tried_ms[n] = ms;
+                    ++n;
+                }
+                if (ms < best) {
+                    best = ms;
+                    out->strip = sp;
+                    out->blocks_per_xcd = bl;
+                    out->bucket_radii = bk;
+                }
+            }
+            if (rc != OSS_OK)
+                break;
+        }
+        if (rc != OSS_OK)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != OSS_OK)
+        return rc;
+    out->n_tried = n;
+    out->ms = best;
+    ctx->star_strip = out->strip;
+    ctx->star_blocks_per_xcd = out->blocks_per_xcd;
+    ctx->batch_bucket = out->bucket_radii;
     return OSS_OK;
 }

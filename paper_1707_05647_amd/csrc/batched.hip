@@ -1,0 +1,136 @@
+// Batched screen: every probe of every template in one persistent launch
+// over one reference's tables (Algorithm 1's patch loop for all templates
+// and scales at once).
+//
+// Templates are sorted by radius and cut into groups of at most
+// BATCH_GROUP; within a group the probes are grouped by reference radius, so
+// the star features of a radius are computed once per position and
+// compared against every probe of every template of the group at that
+// radius.  The scale bits of the group's templates live in registers
+// (indexed by the probe's uniform template slot).
+//
+// A group's distinct radii are split into buckets of consecutive radii.
+// A pass = (group, bucket); the launch walks all passes in order, each pass a
+// full sweep of the image with the plain kernel's persistent XCD-aware strip
+// schedule.  A bucket of nearby radii only touches table rows near y +- r
+// for its radii, which keeps an XCD's L2 footprint small when the radius
+// range is wide.  The first pass of a group writes the group's scale-bit
+// words; later passes OR into them.  Every pass assigns the same positions to
+// the same block and thread, so each word is only ever read and written by
+// one thread, in pass order.
+#include "star_common.h"
+
+namespace oss {
+
+template <typename T, int NQ, int MT>
+__global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
+    const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
+    int H, int W, const DevBatchPass *__restrict__ passes, int n_passes,
+    const DevBatchGroup *__restrict__ groups, const DevRadius *__restrict__ radii,
+    const DevBatchProbe *__restrict__ probes, uint32_t *__restrict__ bits, StarSweep sw)
+{
+    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int units = (sw.n_units - xcd + 7) / 8;
+    const int items = units * sw.rows_per_part;
+    const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
+    const int64_t row_bytes = pitch_e * ES;
+    const int64_t hw = (int64_t)H * W;
+    for (int ip = 0; ip < n_passes; ++ip) {
+        const DevBatchPass ps = passes[ip];
+        const DevBatchGroup *grp = groups + ps.group;
+        const int nt = grp->n_t;
+        for (int it = j; it < items; it += sw.blocks_per_xcd) {
+            int y, x0;
+            sweep_item(sw, xcd, it, (int)blockDim.x, &y, &x0);
+            if (y >= H)
+                continue;
+            const int x = x0 + threadIdx.x;
+            const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
+            const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
+            const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
+            uint32_t acc[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t] = 0;
+            for (int jr = ps.j0; jr < ps.j1; ++jr) {
+                const DevRadius rd = radii[jr];
+                const int r = rd.r, s = rd.s;
+                if (y < r || y > H - 1 - r)
+                    continue;
+                if (x >= r && x <= W - 1 - r) {
+                    int64_t F[NQ];
+                    star_sums<T, NQ>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                    for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                        const DevBatchProbe pr = probes[p];
+                        bool pass = true;
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                        acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                    }
+                }
+            }
+            if (x < W) {
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    if (t < nt) {
+                        uint32_t *w = bits + (int64_t)grp->tmap[t] * hw + (int64_t)y * W + x;
+                        *w = ps.first ? acc[t] : (*w | acc[t]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int NQ>
+static void batch_launch_nq(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                            const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                            hipStream_t st)
+{
+    const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
+            *rp = static_cast<const T *>(Rp);
+    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+    if (bp.max_group <= 8)
+        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 8>), grid, block, 0, st, l, r, rp, g.pitch_e,
+                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           bits, sw);
+    else if (bp.max_group <= 16)
+        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 16>), grid, block, 0, st, l, r, rp,
+                           g.pitch_e, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii,
+                           bp.probes, bits, sw);
+    else
+        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 32>), grid, block, 0, st, l, r, rp,
+                           g.pitch_e, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii,
+                           bp.probes, bits, sw);
+}
+
+template <typename T>
+static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                          const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                          hipStream_t st)
+{
+    switch (g.nq) {
+    case 1: batch_launch_nq<T, 1>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 2: batch_launch_nq<T, 2>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 3: batch_launch_nq<T, 3>(g, L, R, Rp, bp, bits, sw, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                             const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                             hipStream_t stream, Profiler *prof)
+{
+    if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
+        bp.max_group > BATCH_GROUP)
+        return hipErrorInvalidValue;
+    ProfScope ps(prof, K_STAR_BATCH, stream);
+    if (g.ebytes == 4)
+        return batch_t<uint32_t>(g, L, R, Rp, bp, bits, sw, stream);
+    return batch_t<uint64_t>(g, L, R, Rp, bp, bits, sw, stream);
+}
+
+}  // namespace oss

@@ -75,6 +75,37 @@ struct DevTemplatePlan {
     DevProbe probes[OSS_MAX_SCALES];
 };
 
+// Batched plan (all templates of a screen in one persistent launch).
+constexpr int BATCH_GROUP = 32;  // templates per group (scale bits kept in registers)
+
+struct DevBatchProbe {
+    int64_t lo[3];
+    int64_t hi[3];
+    int32_t t;   // template slot within its group
+    int32_t k;   // scale bit
+};
+
+struct DevBatchGroup {
+    int32_t n_t;                  // templates in the group
+    int32_t tmap[BATCH_GROUP];    // slot -> template index of the screen
+    int32_t pad;
+};
+
+struct DevBatchPass {
+    int32_t group;
+    int32_t j0, j1;  // radii [j0, j1) of the global radius array
+    int32_t first;   // 1: write the group's scale bits, 0: OR into them
+};
+
+struct BatchDevPlan {
+    const DevBatchPass *passes;
+    int n_passes;
+    const DevBatchGroup *groups;
+    const DevRadius *radii;
+    const DevBatchProbe *probes;
+    int max_group;
+};
+
 // exact bounds: F passes feature f of a probe iff lo <= F <= hi
 void feature_bounds(int f, int64_t FT, int r, int rho, int P, int Q, int64_t *lo, int64_t *hi);
 
@@ -90,6 +121,7 @@ enum KernelId {
     K_CARRY,
     K_BAND_FINAL,
     K_STAR,
+    K_STAR_BATCH,
     K_COMPACT_COUNT,
     K_COMPACT_SCAN,
     K_COMPACT_WRITE,
@@ -156,6 +188,10 @@ size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax);
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
                              int smax, int rmax, bool lds, hipStream_t stream, Profiler *prof);
+
+hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                             const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                             hipStream_t stream, Profiler *prof);
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);

@@ -31,27 +31,9 @@
 // XCD then has about blocks_per_xcd rows of one strip in flight, and its L2
 // holds the strip's table rows from 2 r_max rows above to the rows in
 // flight: (rows in flight + 2 r_max + 2) x (strip + 2 r_max) entries.
-#include "oss_internal.h"
+#include "star_common.h"
 
 namespace oss {
-
-
-template <typename T, int NQ>
-struct Entry {
-    T v[NQ];
-};
-
-// Sum of two region sums that were formed in T: with 32-bit tables each
-// region sum is exact modulo 2^32 and below 2^32, so it zero-extends.
-__device__ __forceinline__ int64_t widen(uint32_t v) { return (int64_t)v; }
-__device__ __forceinline__ int64_t widen(uint64_t v) { return (int64_t)v; }
-
-// Entry at a wave-uniform row base plus this lane's byte offset.
-template <typename T, int NQ>
-__device__ __forceinline__ Entry<T, NQ> at(const char *row, uint32_t lane_off)
-{
-    return *reinterpret_cast<const Entry<T, NQ> *>(row + lane_off);
-}
 
 template <typename T, int NQ>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
@@ -68,13 +50,10 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     const int64_t row_bytes = pitch_e * ES;
     const int nr = plan->n_radii;
     for (int it = j; it < items; it += sw.blocks_per_xcd) {
-        const int t = it / sw.rows_per_part;
-        const int u = xcd + 8 * t;
-        const int strip = u / sw.parts, part = u - strip * sw.parts;
-        const int y = part * sw.rows_per_part + (it - t * sw.rows_per_part);
+        int y, x0;
+        sweep_item(sw, xcd, it, (int)blockDim.x, &y, &x0);
         if (y >= H)
             continue;
-        const int x0 = strip * (int)blockDim.x;
         const int x = x0 + threadIdx.x;
         const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
         const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
@@ -86,27 +65,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
             if (y < r || y > H - 1 - r)
                 continue;
             if (x >= r && x <= W - 1 - r) {
-                // table row of image row y' is y' + 1; table column of x' is x' + 1
-                const char *l_top = Lb + (int64_t)(y - s) * row_bytes;       // row y-s-1
-                const char *l_bot = Lb + (int64_t)(y + s + 1) * row_bytes;   // row y+s
-                const char *r_top = Rb + (int64_t)(y - r) * row_bytes;       // row y-r-1
-                const char *r_bot = Rb + (int64_t)(y + r + 1) * row_bytes;   // row y+r
-                const char *rp_mid = Rpb + (int64_t)y * row_bytes;            // row y-1
-                const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
-                const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
-                const Entry<T, NQ> a = at<T, NQ>(l_bot + ds, lane_off);    // L(x+s,   y+s)
-                const Entry<T, NQ> b = at<T, NQ>(l_bot - ds1, lane_off);   // L(x-s-1, y+s)
-                const Entry<T, NQ> c = at<T, NQ>(l_top + ds, lane_off);    // L(x+s,   y-s-1)
-                const Entry<T, NQ> d = at<T, NQ>(l_top - ds1, lane_off);   // L(x-s-1, y-s-1)
-                const Entry<T, NQ> e = at<T, NQ>(r_bot, lane_off);         // R(x, y+r)
-                const Entry<T, NQ> f = at<T, NQ>(rp_mid - dr1, lane_off);  // R'(x-r-1, y-1)
-                const Entry<T, NQ> h = at<T, NQ>(rp_mid + dr, lane_off);   // R'(x+r, y-1)
-                const Entry<T, NQ> k = at<T, NQ>(r_top, lane_off);         // R(x, y-r-1)
                 int64_t F[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    F[q] = widen((T)(a.v[q] - b.v[q] - c.v[q] + d.v[q])) +
-                           widen((T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]));
+                star_sums<T, NQ>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
                 for (int p = rd.first; p < rd.first + rd.count; ++p) {
                     const DevProbe pr = plan->probes[p];
                     bool pass = true;
@@ -168,13 +128,10 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_lds_kernel(
     const int tid = threadIdx.x;
     const int nr = plan->n_radii;
     for (int it = j; it < items; it += sw.blocks_per_xcd) {
-        const int t = it / sw.rows_per_part;
-        const int u = xcd + 8 * t;
-        const int strip_i = u / sw.parts, part = u - strip_i * sw.parts;
-        const int y = part * sw.rows_per_part + (it - t * sw.rows_per_part);
+        int y, x0;
+        sweep_item(sw, xcd, it, strip, &y, &x0);
         if (y >= H)
             continue;
-        const int x0 = strip_i * strip;
         const int x = x0 + tid;
         const char *Lb = reinterpret_cast<const char *>(L);
         const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;

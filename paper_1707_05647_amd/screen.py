@@ -84,7 +84,7 @@ class Context:
 
     def screen(self, ref: Reference, templates, probes, tol, feat_mask: int,
                list_cap: int | None = None, stream=None, out: ScreenResult | None = None,
-               with_mask: bool = True) -> ScreenResult:
+               with_mask: bool = True, batched: bool = False) -> ScreenResult:
         """templates: list of oss_template_feat; probes: (t, k, r) triples;
         tol: (P0, P1, P2, Q)."""
         import torch
@@ -99,7 +99,7 @@ class Context:
             out = ScreenResult(mask, cands, count)
         cap = out.cands.shape[0] if list_cap is None else list_cap
         L.oss_screen(self.handle, ref.handle, templates, probes, tol, feat_mask, out.mask,
-                     out.cands, cap, out.count, stream)
+                     out.cands, cap, out.count, stream, batched=batched)
         return out
 
     def close(self):

@@ -34,7 +34,7 @@ def _round_clip(v: np.ndarray, hi: int, dtype) -> np.ndarray:
 def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
                blobs_per_512sq: float = 200.0, n_blobs: int | None = None,
                base: float = 128.0, amp: float = 80.0, sig_lo: float = 4.0,
-               sig_hi: float = 64.0, noise: float = 8.0) -> np.ndarray:
+               sig_hi: float = 64.0, noise: float = 8.0, device=None) -> np.ndarray:
     """Base + Gaussian blobs + iid uniform noise, rounded and clipped.
 
     * ``n_blobs`` defaults to ``blobs_per_512sq`` per 512x512 of area.
@@ -44,7 +44,16 @@ def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
     * Noise is real-valued U[-noise, noise].
     * depth 8 -> uint8 ``floor(v+1/2)`` clipped to [0, 255];
       depth 12 -> uint16 ``floor(16 v + 1/2)`` clipped to [0, 4095].
+
+    ``device`` (a torch device) renders the same blob parameters there in
+    float64 (fast for very large images); the noise then comes from a torch
+    generator seeded from ``rng``, so the image is a deterministic function
+    of the seed but not bit-identical to the host rendering.  The result is
+    returned as a host array either way.
     """
+    if device is not None:
+        return _blob_image_torch(H, W, rng, depth, blobs_per_512sq, n_blobs, base, amp, sig_lo,
+                                 sig_hi, noise, device)
     if n_blobs is None:
         n_blobs = max(1, int(round(blobs_per_512sq * H * W / (512.0 * 512.0))))
     img = np.full((H, W), base, dtype=np.float64)
@@ -69,6 +78,43 @@ def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
         return _round_clip(img, 255, np.uint8)
     if depth == 12:
         return _round_clip(16.0 * img, 4095, np.uint16)
+    raise ValueError(f"unsupported depth {depth}")
+
+
+def _blob_image_torch(H, W, rng, depth, blobs_per_512sq, n_blobs, base, amp, sig_lo, sig_hi,
+                      noise, device):
+    import torch
+    if n_blobs is None:
+        n_blobs = max(1, int(round(blobs_per_512sq * H * W / (512.0 * 512.0))))
+    amps = rng.uniform(-amp, amp, n_blobs)
+    sigs = rng.uniform(sig_lo, sig_hi, n_blobs)
+    cxs = rng.uniform(0.0, W, n_blobs)
+    cys = rng.uniform(0.0, H, n_blobs)
+    nseed = int(rng.integers(0, 2 ** 62))
+    img = torch.full((H, W), base, dtype=torch.float64, device=device)
+    xs_all = torch.arange(W, dtype=torch.float64, device=device)
+    ys_all = torch.arange(H, dtype=torch.float64, device=device)
+    for a, sg, cx, cy in zip(amps, sigs, cxs, cys):
+        rad = 4.0 * sg
+        x0 = max(0, int(math.floor(cx - rad)))
+        x1 = min(W, int(math.ceil(cx + rad)) + 1)
+        y0 = max(0, int(math.floor(cy - rad)))
+        y1 = min(H, int(math.ceil(cy + rad)) + 1)
+        if x0 >= x1 or y0 >= y1:
+            continue
+        inv = -0.5 / (sg * sg)
+        gx = torch.exp(inv * (xs_all[x0:x1] - cx) ** 2)
+        gy = torch.exp(inv * (ys_all[y0:y1] - cy) ** 2) * a
+        img[y0:y1, x0:x1] += gy[:, None] * gx[None, :]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(nseed)
+    img += (torch.rand((H, W), dtype=torch.float64, device=device, generator=gen) * 2 - 1) * noise
+    if depth == 8:
+        out = torch.clamp(torch.floor(img + 0.5), 0, 255).to(torch.uint8)
+        return out.cpu().numpy()
+    if depth == 12:
+        out = torch.clamp(torch.floor(16.0 * img + 0.5), 0, 4095).to(torch.int16)
+        return out.cpu().numpy().view(np.uint16)
     raise ValueError(f"unsupported depth {depth}")
 
 

@@ -97,12 +97,13 @@ def _resampled_template(rng, ref, hi, obj_radius_fn, *, std_min, apron, margin_m
 
 def make_workload(cfg_id: int, seed: int = 0, *, H: int | None = None, W: int | None = None,
                   n_templates: int | None = None, blobs_per_512sq: float = 200.0,
-                  sig_hi: float = 64.0) -> Workload:
+                  sig_hi: float = 64.0, device=None) -> Workload:
     """Build workload ``cfg_id`` from ``seed``.  ``H``/``W``/``n_templates``
     shrink it for tests; ``blobs_per_512sq``/``sig_hi`` keep small images
-    textured (the default blob recipe is sized for large images)."""
+    textured (the default blob recipe is sized for large images);
+    ``device`` renders the reference image with torch on that device."""
     rng = make_rng(cfg_id, seed)
-    bkw = {"blobs_per_512sq": blobs_per_512sq, "sig_hi": sig_hi}
+    bkw = {"blobs_per_512sq": blobs_per_512sq, "sig_hi": sig_hi, "device": device}
     if cfg_id == 1:
         H = H or 512
         W = W or H
