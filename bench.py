@@ -41,6 +41,7 @@ KERNEL_SOURCES = {
     "row_base": "paper_1707_05647_amd/csrc/builder.hip",
     "carry": "paper_1707_05647_amd/csrc/builder.hip",
     "star_plain": "paper_1707_05647_amd/csrc/star.hip",
+    "star_batch": "paper_1707_05647_amd/csrc/batched.hip",
     "compact_count": "paper_1707_05647_amd/csrc/compact.hip",
     "compact_scan": "paper_1707_05647_amd/csrc/compact.hip",
     "compact_write": "paper_1707_05647_amd/csrc/compact.hip",
