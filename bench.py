@@ -58,11 +58,17 @@ def pixel_scales(H, W, probes):
     return sum(max(0, H - 2 * r) * max(0, W - 2 * r) for _, _, r in probes)
 
 
-def lookup_pairs(w):
-    """Valid (position, distinct radius) pairs of a plain screen: each costs
-    8 table lookups (the batched screen shares a radius between templates of a
-    group, so this bounds its lookups from above)."""
-    pairs = set((t, r) for t, _, r in w.probes)
+def lookup_pairs(w, batched=False, group=32):
+    """Valid (position, radius) pairs whose star sums a launch evaluates, each
+    8 table lookups per quantity: one per (template, distinct radius) for
+    per-template launches; one per (template group, distinct radius) for the
+    batched launch (templates sorted by radius, groups of 32)."""
+    if batched:
+        order = sorted(range(len(w.templates)), key=lambda t: w.templates[t].rho)
+        gid = {t: i // group for i, t in enumerate(order)}
+        pairs = set((gid[t], r) for t, _, r in w.probes)
+    else:
+        pairs = set((t, r) for t, _, r in w.probes)
     return sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, r in pairs)
 
 
@@ -70,9 +76,10 @@ def ref_nq(feat_mask):
     return bin(feat_mask).count("1")
 
 
-def algorithmic_bytes(H, W, nq, n_tmpl, px_bytes, value_bytes):
-    """Minimum HBM bytes per launch of each kernel."""
-    table = 3 * (H + 1) * (W + 1) * nq * value_bytes
+def algorithmic_bytes(H, W, n_tmpl, px_bytes, entry_bytes):
+    """Minimum HBM bytes per launch of each kernel: the three tables once
+    (entry_bytes per entry), the image once, the scale-bit words once."""
+    table = 3 * (H + 1) * (W + 1) * entry_bytes
     hw = H * W
     return {
         # writes every table entry once, reads the image once
@@ -163,6 +170,9 @@ WORKLOAD_TEXT = {
        "7 scales 0.5..2.0 each, one batched launch",
     5: "large batched: 16384x16384 12-bit reference, one radius-48 template at 16 rotations, "
        "32 radii 24..96, one batched launch",
+    4: "serving: Poisson requests at 80% of the per-request scheme's capacity; square uint8 "
+       "references, side log-uniform 1024..8192, 30% resident reuse, 1..8 templates rho U{8..128}, "
+       "1..9 scales geometric in [0.5, 2]",
 }
 
 
@@ -185,19 +195,28 @@ def sampled_check(w, cands, n, cap, mask_dev, seconds):
     """CPU baseline on a random sample plus the GPU/oracle comparison there,
     from the sorted candidate list (scale bits) and the mask."""
     import numpy as np
+    import torch
     T = len(w.templates)
-    c = cands[:min(n, cap)].cpu().numpy().astype(np.int64)
-    keys = (c[:, 0] * w.H + c[:, 1]) * w.W + c[:, 2] if len(c) else np.zeros(0, np.int64)
-    vals = (c[:, 3] & 0xFFFFFFFF).astype(np.uint32) if len(c) else np.zeros(0, np.uint32)
+    dev = cands.device
+    m = min(n, cap)
+    # list keys (t, y, x) -> t*H*W + y*W + x, sorted because the list is in
+    # canonical order; looked up on the device
+    c = cands[:m]
+    keys = c[:, 0].to(torch.int64) * (w.H * w.W)
+    keys += c[:, 1].to(torch.int64) * w.W
+    keys += c[:, 2].to(torch.int64)
 
     def gpu_bits(ys, xs):
         out = np.zeros((T, len(xs)), np.uint32)
+        if m == 0:
+            return out
+        pos = torch.from_numpy(ys.astype(np.int64) * w.W + xs).to(dev)
         for t in range(T):
-            k = (t * w.H + ys.astype(np.int64)) * w.W + xs
-            i = np.searchsorted(keys, k)
-            hit = (i < len(keys)) & (keys[np.minimum(i, len(keys) - 1)] == k) if len(keys) else \
-                np.zeros(len(k), bool)
-            out[t, hit] = vals[i[hit]]
+            k = pos + t * (w.H * w.W)
+            i = torch.searchsorted(keys, k).clamp_(max=m - 1)
+            hit = keys[i] == k
+            v = torch.where(hit, c[i, 3], torch.zeros_like(c[i, 3]))
+            out[t] = v.cpu().numpy().view(np.uint32)
         return out
 
     def gpu_mask(ys, xs):
@@ -210,15 +229,193 @@ def sampled_check(w, cands, n, cap, mask_dev, seconds):
                         list_complete=n <= cap)
 
 
+SERVE_TOL = (4, 8, 65, 100)
+SERVE_CAP = 1 << 22
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, np.float64), q)) if len(v) else None
+
+
+def run_serving(args):
+    """Workload 4.  The per-request scheme (tables built for every request,
+    one launch per template, one request at a time) is timed back to back to
+    find its capacity; the same Poisson stream, at 80% of that rate, is then
+    served by (a) that scheme, first come first served, and (b) the server
+    (resident tables, merged batched launches, several lanes).  Latency runs
+    from a request's arrival to its result being ready."""
+    import numpy as np
+    import torch
+
+    from paper_1707_05647_amd import _lib as L
+    from paper_1707_05647_amd.screen import Context, Server
+    from synth import serving_requests
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    print(f"serving: generating {args.requests} requests", file=sys.stderr, flush=True)
+    reqs, images = serving_requests(args.requests, 1.0, args.seed, device=dev)
+    imgs = {k: L.device_image(v, dev) for k, v in images.items()}
+    feats = [[L.oss_template_features(t.pixels, t.rho, L.OSS_F_ALL) for t in q.templates]
+             for q in reqs]
+    ctx = Context(0)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cands = torch.empty((SERVE_CAP, 4), dtype=torch.int32, device=dev)
+
+    def digest(mask_t, cands_t, n):
+        m = min(n, SERVE_CAP)
+        return (n, int(mask_t.sum().item()), int(cands_t[:m].to(torch.int64).sum().item()))
+
+    def plain_one(i):
+        q = reqs[i]
+        ref = ctx.reference(imgs[q.ref_key], L.OSS_F_ALL, 8, stream,
+                            max_radius=max([p[2] for p in q.probes] + [0]))
+        mask = torch.empty((len(q.templates), q.side, q.side), dtype=torch.uint8, device=dev)
+        L.oss_screen(ctx.handle, ref.handle, feats[i], q.probes, SERVE_TOL, L.OSS_F_ALL, mask,
+                     cands, SERVE_CAP, count, stream)
+        torch.cuda.synchronize()
+        n = int(count.item())
+        d = digest(mask, cands, n)
+        ref.release()
+        return d
+
+    # warm-up and the per-request scheme's capacity (back to back)
+    plain_one(0)
+    t0 = time.perf_counter()
+    plain_digest = [plain_one(i) for i in range(len(reqs))]
+    plain_busy = time.perf_counter() - t0
+    capacity = len(reqs) / plain_busy
+    rate = 0.8 * capacity
+    arrivals = [q.arrival_s / rate for q in reqs]  # the stream was drawn at rate 1
+    print(f"serving: plain capacity {capacity:.1f} req/s, offered {rate:.1f} req/s",
+          file=sys.stderr, flush=True)
+
+    # (a) the per-request scheme under the Poisson stream
+    lat_plain = []
+    start = time.perf_counter()
+    for i in range(len(reqs)):
+        now = time.perf_counter() - start
+        if now < arrivals[i]:
+            time.sleep(arrivals[i] - now)
+        plain_one(i)
+        lat_plain.append((time.perf_counter() - start - arrivals[i]) * 1e3)
+    span_plain = time.perf_counter() - start
+
+    # (b) the server under the same stream
+    srv = Server(0, 96 << 30, lanes=args.lanes, max_batch_templates=64)
+    w = srv.submit(reqs[0].ref_key, imgs[reqs[0].ref_key], feats[0], reqs[0].probes, SERVE_TOL,
+                   L.OSS_F_ALL, SERVE_CAP)
+    srv.drain()
+    srv.release(w)
+    ids = [None] * len(reqs)
+    base = time.monotonic_ns()
+    nxt = 0
+    done = 0
+    while done < len(reqs):
+        now_s = (time.monotonic_ns() - base) * 1e-9
+        while nxt < len(reqs) and arrivals[nxt] <= now_s:
+            q = reqs[nxt]
+            ids[nxt] = srv.submit(q.ref_key, imgs[q.ref_key], feats[nxt], q.probes, SERVE_TOL,
+                                  L.OSS_F_ALL, SERVE_CAP,
+                                  arrival_ns=base + int(arrivals[nxt] * 1e9))
+            nxt += 1
+        wait = 200 if nxt == len(reqs) else max(0, min(200, int((arrivals[nxt] - now_s) * 1e6)))
+        got = srv.pump(wait)
+        done += got
+        if nxt == len(reqs) and got == 0:
+            stt = srv.stats()
+            if stt["queued"] == 0 and stt["running"] == 0:
+                raise RuntimeError(f"server idle with {len(reqs) - done} requests unfinished: "
+                                   f"{stt}")
+    span_srv = (time.monotonic_ns() - base) * 1e-9
+    lat_srv, q_srv, batch, hits, same = [], [], [], 0, 0
+    for i, rid in enumerate(ids):
+        r = srv.result(rid)
+        if r.status != L.OSS_OK:
+            raise RuntimeError(f"request {i} failed: {L.status_string(r.status)}")
+        lat_srv.append(r.latency_ms)
+        q_srv.append(r.queue_ms)
+        batch.append(r.batch_requests)
+        hits += r.resident_hit
+        mask_t = torch.empty((r.n_tmpl, r.H, r.W), dtype=torch.uint8, device=dev)
+        m = min(r.count, SERVE_CAP)
+        lst = torch.empty((max(m, 1), 4), dtype=torch.int32, device=dev)
+        _dev_copy(mask_t, r.dev_mask)
+        if m:
+            _dev_copy(lst[:m], r.dev_list)
+        same += digest(mask_t, lst, r.count) == plain_digest[i]
+        srv.release(rid)
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+
+    ps = [pixel_scales(q.side, q.side, q.probes) for q in reqs]
+    total_ps = float(sum(ps))
+    out = {
+        "metric": METRIC,
+        "value": total_ps / span_srv / 1e9,
+        "unit": "G pixel-scales/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 1,
+        "ms_per_step": span_srv * 1e3 / len(reqs),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[4], "requests": len(reqs),
+                   "distinct_references": len(images), "lanes": args.lanes, "seed": args.seed,
+                   "tolerance_P_over_Q": [p / SERVE_TOL[3] for p in SERVE_TOL[:3]],
+                   "list_cap": SERVE_CAP},
+        "served": {
+            "p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99),
+            "queue_p50_ms": _pct(q_srv, 50), "queue_p99_ms": _pct(q_srv, 99),
+            "requests_per_s": len(reqs) / span_srv,
+            "mean_requests_per_launch": float(np.mean(batch)),
+            "resident_hits": hits, "launches": st["launches"], "builds": st["builds"],
+            "evictions": st["evictions"], "bytes_peak": st["bytes_peak"],
+            "identical_to_alone": same, "of": len(reqs),
+        },
+        "per_request_scheme": {
+            "capacity_requests_per_s": capacity,
+            "p50_ms": _pct(lat_plain, 50), "p99_ms": _pct(lat_plain, 99),
+            "requests_per_s": len(reqs) / span_plain,
+            "value": total_ps / span_plain / 1e9,
+        },
+        "offered_requests_per_s": rate,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _dev_copy(dst, src_ptr: int):
+    """Device-to-device copy of dst.nbytes bytes from a raw device pointer."""
+    import ctypes as C
+
+    import torch  # noqa: F401
+    global _HIP
+    if "_HIP" not in globals():
+        _HIP = C.CDLL("libamdhip64.so.7")
+        _HIP.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _HIP.hipMemcpy.restype = C.c_int
+    rc = _HIP.hipMemcpy(dst.data_ptr(), src_ptr, dst.numel() * dst.element_size(), 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 5],
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: the headline rotation+scale screen; 3, 5: batched workloads "
-                         "(batched launch against per-template launches)")
+                         "(batched launch against per-template launches); 4: serving loop")
+    ap.add_argument("--requests", type=int, default=100, help="workload 4: requests")
+    ap.add_argument("--lanes", type=int, default=2, help="workload 4: server lanes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -237,6 +434,10 @@ def main():
               "by row bands with no exchange on the hot path, but multi-GPU runs are not part "
               "of this build.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == 4:
+        run_serving(args)
+        return
 
     import torch
 
@@ -259,7 +460,8 @@ def main():
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_LDS, args.star_lds)
     ref = ctx.reference(img, w.feat_mask, w.depth, build=False, max_radius=max(w.radii()))
     T = len(w.templates)
-    cap = 1 << 22 if not big else 1 << 25
+    # room for every candidate, so the sampled check sees a complete list
+    cap = min(T * w.H * w.W, 1 << 22 if not big else 1_600_000_000)
     mask = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
     cands = torch.empty((cap, 4), dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -305,8 +507,8 @@ def main():
     ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
     n = int(count.item())
-    vb = ref.value_bits // 8
-    abytes = algorithmic_bytes(w.H, w.W, ref_nq(w.feat_mask), T, 2 if w.depth > 8 else 1, vb)
+    eb = ref.entry_bytes
+    abytes = algorithmic_bytes(w.H, w.W, T, 2 if w.depth > 8 else 1, eb)
     abytes["star_batch"] = abytes["star_plain"]
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
             for k, v in prof.items()}
@@ -326,7 +528,7 @@ def main():
     }
     if dom in ("star_plain", "star_batch"):
         # the same launch against the vector-memory path that actually bounds it
-        lookups = lookup_pairs(w) * 8 * ref_nq(w.feat_mask) * vb
+        lookups = lookup_pairs(w, dom == "star_batch") * 8 * eb
         roof["vector_l1"] = {"achieved": lookups / avg_s / 1e9, "peak": L1_PEAK_GBPS,
                              "unit": "GB/s", "frac": lookups / avg_s / 1e9 / L1_PEAK_GBPS,
                              "lookup_bytes_per_launch": lookups}
@@ -355,6 +557,7 @@ def main():
             "tolerance_P_over_Q": [p / w.tol_Q for p in w.tol_P], "seed": args.seed,
             "pixel_scales_per_step": ps,
             "table_value_bits": ref.value_bits,
+            "table_entry_bytes": eb,
             "star_strip": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STRIP),
             "star_blocks_per_xcd": L.oss_ctx_get_option(ctx.handle,
                                                         L.OSS_OPT_STAR_BLOCKS_PER_XCD),

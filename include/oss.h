@@ -207,15 +207,28 @@ int oss_ref_build(oss_ref *ref, const void *dev_pixels, void *stream);
 int oss_ref_release(oss_ref *ref);
 
 /*
- * Read-only device view of the tables: entry (x, y) of table T for
- * quantity slot q is T[((y+1) * pitch_entries + (x+1)) * nq + q], with
- * x in [-1, W-1], y in [-1, H-1]; nq = number of bits in the feature mask;
- * values are value_bits (32: the sums modulo 2^32, or 64) wide unsigned
- * words.  Any output pointer may be NULL.
+ * Read-only device view of the tables: entry (x, y) of table T starts at
+ * byte ((y+1) * pitch_entries + (x+1)) * entry_bytes of T, with x in
+ * [-1, W-1], y in [-1, H-1] (oss_ref_layout gives entry_bytes and where each
+ * quantity sits in an entry); nq = number of bits in the feature mask;
+ * value_bits = the accumulation width (32: every sum modulo 2^32, or 64).
+ * Any output pointer may be NULL.
  */
 int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const void **Rp,
                    int64_t *pitch_entries, int32_t *nq, int32_t *value_bits,
                    int32_t *max_radius);
+
+/*
+ * Layout of one table entry of `ref` (L, R and R' share it): *entry_bytes
+ * per entry, and for each quantity slot q < nq (feature order: sum, squares,
+ * gradient, enabled ones only) the byte offset of its value in the entry and
+ * its width in bits (32: stored modulo 2^32, 64: two's complement); slots
+ * q >= nq get offset -1, width 0.  Entries are 4 * nq bytes (all 32-bit),
+ * 8 * nq bytes (all 64-bit), or 16 bytes when only the squares need 64 bits:
+ * the squares at offset 0, the other quantities at 8 and 12.
+ */
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_bytes, int32_t offset[3],
+                   int32_t bits[3]);
 
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the
@@ -291,6 +304,103 @@ int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_fe
                          int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
                          const oss_tolerance *tol, uint32_t feat_mask, void *stream,
                          oss_tune_result *out);
+
+
+/* ------------------------------------------------------------------------
+ * Serving loop.  A server owns one device, a device-memory budget, a set of
+ * lanes (one context + one stream each) and a cache of resident reference
+ * tables keyed by the caller's reference id.  Requests are queued by
+ * oss_server_submit and run by oss_server_pump: the oldest queued request is
+ * admitted when its footprint fits the budget (its reference tables unless
+ * resident, its mask of n_tmpl*H*W bytes, 16 bytes per list entry of
+ * capacity, and the lane's scale-bit workspace of 4*n_tmpl*H*W bytes),
+ * evicting least recently used resident references that no queued or
+ * running request needs (a request that does not fit waits for running
+ * work to finish or for results to be released).  Every queued request on the same reference that
+ * fits joins the admitted one in a single batched launch (oss_screen_batched
+ * over the union of their templates, each template keeping its request's
+ * tolerance and feature set); each request then gets its own compaction into
+ * its own mask and list, so its result is identical to a screen of that
+ * request alone.  Work of different references runs concurrently on the
+ * lanes.  This is an addition to the paper's method (its Algorithm 1 screens
+ * one reference against one template).
+ * ------------------------------------------------------------------------ */
+typedef struct oss_server oss_server;
+
+typedef struct oss_server_config {
+    int64_t memory_budget;        /* device bytes the server may hold (> 0) */
+    int32_t lanes;                /* concurrent lanes, 1..8 */
+    int32_t max_batch_templates;  /* templates per merged launch (>= 1); a
+                                     request with more still runs alone */
+} oss_server_config;
+
+typedef struct oss_request {
+    uint64_t ref_key;        /* equal keys promise equal pixels and desc */
+    const void *dev_pixels;  /* device pixels, read only when the reference
+                                is not resident; caller-owned, valid until
+                                the request completes */
+    oss_image_desc desc;
+    const oss_template_feat *tmpl;  /* copied by oss_server_submit */
+    int32_t n_tmpl;
+    const oss_probe *probes;        /* copied by oss_server_submit */
+    int32_t n_probes;
+    oss_tolerance tol;
+    uint32_t feat_mask;
+    int64_t list_cap;        /* candidate list capacity */
+    int64_t arrival_ns;      /* CLOCK_MONOTONIC arrival time; 0 = at submit */
+} oss_request;
+
+typedef struct oss_result {
+    int32_t status;          /* OSS_OK done, OSS_E_STATE pending, else the
+                                error the request failed with */
+    int32_t n_tmpl, H, W;
+    const uint8_t *dev_mask;       /* [n_tmpl][H][W], server-owned */
+    const oss_candidate *dev_list; /* list_cap entries, server-owned */
+    int64_t list_cap;
+    int64_t count;           /* candidates found (may exceed list_cap) */
+    double latency_ms;       /* arrival -> completion seen by the server */
+    double queue_ms;         /* arrival -> launch */
+    int32_t batch_requests;  /* requests merged into its launch */
+    int32_t resident_hit;    /* 1 if its reference tables were resident */
+    int32_t lane;
+    int32_t pad;
+} oss_result;
+
+typedef struct oss_server_stats {
+    int64_t submitted, completed, failed, launches;
+    int64_t resident_hits, builds, evictions;
+    int64_t bytes_in_use, bytes_peak, memory_budget;
+    int32_t queued, running;
+} oss_server_stats;
+
+/* Create / destroy a server on `device`.  Destroy waits for running work
+ * and frees everything the server holds, including unreleased results. */
+int oss_server_create(int device, const oss_server_config *cfg, oss_server **out);
+int oss_server_destroy(oss_server *srv);
+
+/* Validate and queue a request (nothing is launched).  *id identifies it.
+ * OSS_E_NOMEM if its footprint (with its reference not resident) exceeds
+ * the whole budget; OSS_E_ARG for invalid arguments, with the same rules as
+ * oss_screen. */
+int oss_server_submit(oss_server *srv, const oss_request *req, int64_t *id);
+
+/* Retire finished launches and admit / launch queued requests on free
+ * lanes.  If `wait_us` > 0 and nothing completed yet, polls for up to that
+ * long for a completion.  *n_completed (optional) = requests completed by
+ * this call. */
+int oss_server_pump(oss_server *srv, int64_t wait_us, int32_t *n_completed);
+
+/* Pump until no request is queued or running.  OSS_E_NOMEM if queued
+ * requests cannot be admitted until completed results are released. */
+int oss_server_drain(oss_server *srv);
+
+/* Status and output of a request (status OSS_E_STATE while pending). */
+int oss_server_result(oss_server *srv, int64_t id, oss_result *out);
+
+/* Free a completed (or failed) request's outputs; its id becomes invalid. */
+int oss_server_release(oss_server *srv, int64_t id);
+
+int oss_server_stats_read(oss_server *srv, oss_server_stats *out);
 
 #ifdef __cplusplus
 }

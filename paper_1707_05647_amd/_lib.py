@@ -25,6 +25,8 @@ EXPORTED = [
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
+    "oss_ref_layout", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
+    "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_TUNE_MAX = 64
@@ -62,6 +64,34 @@ class oss_tune_result(C.Structure):
                 ("tried", (C.c_int32 * 3) * OSS_TUNE_MAX), ("tried_ms", C.c_float * OSS_TUNE_MAX)]
 
 
+class oss_server_config(C.Structure):
+    _fields_ = [("memory_budget", C.c_int64), ("lanes", C.c_int32),
+                ("max_batch_templates", C.c_int32)]
+
+
+class oss_request(C.Structure):
+    _fields_ = [("ref_key", C.c_uint64), ("dev_pixels", C.c_void_p), ("desc", oss_image_desc),
+                ("tmpl", C.POINTER(oss_template_feat)), ("n_tmpl", C.c_int32),
+                ("probes", C.POINTER(oss_probe)), ("n_probes", C.c_int32),
+                ("tol", oss_tolerance), ("feat_mask", C.c_uint32), ("list_cap", C.c_int64),
+                ("arrival_ns", C.c_int64)]
+
+
+class oss_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_tmpl", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+                ("dev_mask", C.c_void_p), ("dev_list", C.c_void_p), ("list_cap", C.c_int64),
+                ("count", C.c_int64), ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("batch_requests", C.c_int32), ("resident_hit", C.c_int32), ("lane", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class oss_server_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "launches",
+                                         "resident_hits", "builds", "evictions", "bytes_in_use",
+                                         "bytes_peak", "memory_budget")] + \
+               [("queued", C.c_int32), ("running", C.c_int32)]
+
+
 class OssError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status_string(status)} ({status})")
@@ -95,6 +125,7 @@ def load(path: str | None = None):
     lib.oss_ref_tables.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                    C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(i32)]
+    lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
@@ -109,6 +140,14 @@ def load(path: str | None = None):
     lib.oss_autotune_batched.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32,
                                          C.POINTER(oss_probe), i32, C.POINTER(oss_tolerance), u32,
                                          vp, C.POINTER(oss_tune_result)]
+    lib.oss_server_create.argtypes = [C.c_int, C.POINTER(oss_server_config), C.POINTER(vp)]
+    lib.oss_server_destroy.argtypes = [vp]
+    lib.oss_server_submit.argtypes = [vp, C.POINTER(oss_request), C.POINTER(i64)]
+    lib.oss_server_pump.argtypes = [vp, i64, C.POINTER(i32)]
+    lib.oss_server_drain.argtypes = [vp]
+    lib.oss_server_result.argtypes = [vp, i64, C.POINTER(oss_result)]
+    lib.oss_server_release.argtypes = [vp, i64]
+    lib.oss_server_stats_read.argtypes = [vp, C.POINTER(oss_server_stats)]
     for name in EXPORTED:
         if name != "oss_status_string":
             getattr(lib, name).restype = C.c_int
@@ -231,6 +270,15 @@ def oss_ref_release(ref: int):
     _check(load().oss_ref_release(ref), "oss_ref_release")
 
 
+def oss_ref_layout(ref: int):
+    """(entry_bytes, [(offset, bits) per quantity slot])."""
+    eb = C.c_int32()
+    off = (C.c_int32 * 3)()
+    bits = (C.c_int32 * 3)()
+    _check(load().oss_ref_layout(ref, C.byref(eb), off, bits), "oss_ref_layout")
+    return eb.value, [(off[q], bits[q]) for q in range(3) if bits[q]]
+
+
 def oss_ref_tables(ref: int):
     """(L, R, Rp) device pointers, pitch in entries, number of quantities,
     value width in bits (32: sums modulo 2^32, or 64), maximum radius."""
@@ -304,3 +352,55 @@ def oss_autotune_batched(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int,
     _check(load().oss_autotune_batched(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask),
                                        _stream(stream), C.byref(out)), "oss_autotune_batched")
     return out
+
+
+# --- serving loop -----------------------------------------------------------
+
+def oss_server_create(device: int, memory_budget: int, lanes: int = 2,
+                      max_batch_templates: int = 64) -> int:
+    h = C.c_void_p()
+    cfg = oss_server_config(int(memory_budget), int(lanes), int(max_batch_templates))
+    _check(load().oss_server_create(int(device), C.byref(cfg), C.byref(h)), "oss_server_create")
+    return h.value
+
+
+def oss_server_destroy(srv: int):
+    _check(load().oss_server_destroy(srv), "oss_server_destroy")
+
+
+def oss_server_submit(srv: int, ref_key: int, pixels, tmpl, probes, tol, feat_mask: int,
+                      list_cap: int, bit_depth: int | None = None, arrival_ns: int = 0) -> int:
+    """pixels: torch device tensor [H, W] (uint8, or int16 holding uint16);
+    it must stay alive until the request completes."""
+    ta, nt, pa, npb, tl = _screen_args(tmpl, probes, tol)
+    rq = oss_request(int(ref_key), _ptr(pixels), desc_of(pixels, bit_depth), ta, nt, pa, npb, tl,
+                     int(feat_mask), int(list_cap), int(arrival_ns))
+    rid = C.c_int64()
+    _check(load().oss_server_submit(srv, C.byref(rq), C.byref(rid)), "oss_server_submit")
+    return rid.value
+
+
+def oss_server_pump(srv: int, wait_us: int = 0) -> int:
+    n = C.c_int32()
+    _check(load().oss_server_pump(srv, int(wait_us), C.byref(n)), "oss_server_pump")
+    return n.value
+
+
+def oss_server_drain(srv: int):
+    _check(load().oss_server_drain(srv), "oss_server_drain")
+
+
+def oss_server_result(srv: int, rid: int) -> oss_result:
+    out = oss_result()
+    _check(load().oss_server_result(srv, int(rid), C.byref(out)), "oss_server_result")
+    return out
+
+
+def oss_server_release(srv: int, rid: int):
+    _check(load().oss_server_release(srv, int(rid)), "oss_server_release")
+
+
+def oss_server_stats_read(srv: int) -> dict:
+    out = oss_server_stats()
+    _check(load().oss_server_stats_read(srv, C.byref(out)), "oss_server_stats_read")
+    return {n: getattr(out, n) for n, _ in oss_server_stats._fields_}

@@ -1,5 +1,5 @@
 // C ABI of the octagonal-star screening library (include/oss.h).
-#include "oss_internal.h"
+#include "api_internal.h"
 
 #include <algorithm>
 #include <climits>
@@ -8,46 +8,6 @@
 #include <new>
 
 using namespace oss;
-
-namespace {
-
-struct PlanSlot {
-    void *host = nullptr;  // pinned staging
-    void *dev = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev = nullptr;
-    bool used = false;
-};
-
-constexpr int NSLOTS = 4;
-
-}  // namespace
-
-struct oss_ctx {
-    int device = 0;
-    uint32_t *bits = nullptr;  // scale-bit words, n_tmpl * H * W
-    size_t bits_cap = 0;       // bytes
-    void *cws = nullptr;       // compaction workspace
-    size_t cws_cap = 0;        // bytes
-    PlanSlot slots[NSLOTS];
-    int next_slot = 0;
-    Profiler prof;
-    int star_strip = 512;          // OSS_OPT_STAR_STRIP
-    int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
-    int star_lds = 0;              // OSS_OPT_STAR_LDS
-    int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
-};
-
-struct oss_ref {
-    oss_ctx *ctx = nullptr;
-    oss_image_desc desc{};
-    uint32_t feat_mask = 0;
-    int32_t max_radius = 0;
-    BuildGeom geom{};
-    void *mem = nullptr;  // one allocation for everything below
-    size_t bytes = 0;
-    BuildBuffers bb{};
-};
 
 namespace oss {
 
@@ -107,7 +67,7 @@ void feature_bounds(int f, int64_t FT, int r, int rho, int P, int Q, int64_t *lo
 
 static int popc(uint32_t m) { return __builtin_popcount(m); }
 
-static bool desc_ok(const oss_image_desc *d)
+bool oss::desc_ok(const oss_image_desc *d)
 {
     if (!d || d->H <= 0 || d->W <= 0)
         return false;
@@ -202,7 +162,7 @@ enum { A_L, A_R, A_RP, A_BP, A_AGL, A_AGAD, A_AGD, A_CL, A_CAD, A_CD, A_COUNT };
 static size_t ref_layout(const BuildGeom &g, size_t off[A_COUNT])
 {
     const size_t e = (size_t)g.ebytes * (size_t)g.nq;
-    const size_t table = (size_t)(g.H + 1) * (size_t)g.pitch_e * e;
+    const size_t table = (size_t)(g.H + 1) * (size_t)g.pitch_e * (size_t)g.tab_es;
     const size_t bp = (size_t)g.H * g.nbp * e;
     const size_t car = (size_t)g.nb * g.cw * e;
     const size_t sizes[A_COUNT] = {table, table, table, bp, car, car, car, car, car, car};
@@ -227,10 +187,14 @@ static __int128 max_quantity(const oss_image_desc *d, uint32_t fm)
     return maxq;
 }
 
-static bool overflow_ok(const oss_image_desc *d, uint32_t fm)
+}  // extern "C"
+
+bool oss::overflow_ok(const oss_image_desc *d, uint32_t fm)
 {
     return (__int128)d->H * d->W * max_quantity(d, fm) < ((__int128)1 << 62);
 }
+
+extern "C" {
 
 static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
 {
@@ -238,19 +202,22 @@ static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
     return max_radius < 0 ? fit : max_radius;
 }
 
-// 32-bit storage is exact when every square and every diamond sum up to the
-// maximum radius stays below 2^32 for every stored quantity.
-static int storage_bytes(const oss_image_desc *d, uint32_t fm, int32_t R)
+// A quantity can be stored modulo 2^32 when every square and every diamond
+// sum of it up to the maximum radius stays below 2^32.  All quantities fit:
+// 32-bit entries.  Only the squares do not: mixed 16-byte entries (squares
+// in 64 bits).  Otherwise 64-bit entries.
+static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R)
 {
     const __int128 s = square_half(R);
     const __int128 area = std::max((2 * s + 1) * (2 * s + 1),
                                    (__int128)2 * R * R + 2 * (__int128)R + 1);
-    return max_quantity(d, fm) * area < ((__int128)1 << 32) ? 4 : 8;
-}
-
-static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R)
-{
-    return make_geom(d->H, d->W, popc(fm), storage_bytes(d, fm, R));
+    auto fits = [&](uint32_t m) { return max_quantity(d, m) * area < ((__int128)1 << 32); };
+    const int nq = popc(fm);
+    if (fits(fm))
+        return make_geom(d->H, d->W, nq, 4);
+    if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ))
+        return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0);
+    return make_geom(d->H, d->W, nq, 8);
 }
 
 int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_radius, size_t *out)
@@ -345,6 +312,32 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
         *value_bits = 8 * ref->geom.ebytes;
     if (max_radius)
         *max_radius = ref->max_radius;
+    return OSS_OK;
+}
+
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_bytes, int32_t offset[3], int32_t bits[3])
+{
+    if (!ref || !entry_bytes || !offset || !bits)
+        return OSS_E_ARG;
+    const BuildGeom &g = ref->geom;
+    *entry_bytes = g.tab_es;
+    int j = 0;
+    for (int q = 0; q < 3; ++q) {
+        offset[q] = -1;
+        bits[q] = 0;
+    }
+    for (int q = 0; q < g.nq; ++q) {
+        if (g.sqi < 0) {
+            offset[q] = q * g.ebytes;
+            bits[q] = 8 * g.ebytes;
+        } else if (q == g.sqi) {
+            offset[q] = 0;
+            bits[q] = 64;
+        } else {
+            offset[q] = 8 + 4 * j++;
+            bits[q] = 32;
+        }
+    }
     return OSS_OK;
 }
 
@@ -622,7 +615,7 @@ static int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_templat
     return OSS_OK;
 }
 
-static int screen_workspace(oss_ctx *ctx, int64_t n)
+int oss::screen_workspace(oss_ctx *ctx, int64_t n)
 {
     int rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap,
                   (size_t)n * sizeof(uint32_t));
@@ -685,20 +678,12 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
 // ---------------------------------------------------------------------------
 // Batched screen.
 // ---------------------------------------------------------------------------
-struct BatchHostPlan {
-    std::vector<DevBatchPass> passes;
-    std::vector<DevBatchGroup> groups;
-    std::vector<DevRadius> radii;
-    std::vector<DevBatchProbe> probes;
-    int max_group = 0;
-};
-
 // Templates sorted by radius and cut into groups of BATCH_GROUP; each group's
 // probes sorted by reference radius; every run of at most `bucket` distinct
 // radii (0: all) becomes one pass.
-static int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
-                           const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
-                           uint32_t fm, int bucket, BatchHostPlan &bp)
+int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                         const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
+                         const uint32_t *fms, int bucket, BatchHostPlan &bp)
 {
     std::vector<std::vector<oss_probe>> per(n_tmpl);
     for (int i = 0; i < n_probes; ++i) {
@@ -741,14 +726,19 @@ static int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, in
         const int rad_begin = (int)bp.radii.size();
         for (const Item &it : items) {
             if ((int)bp.radii.size() == rad_begin || bp.radii.back().r != it.r) {
-                DevRadius rd;
+                DevBatchRadius rd{};
                 rd.r = it.r;
                 rd.s = square_half(it.r);
                 rd.first = (int32_t)bp.probes.size();
                 rd.count = 0;
+                for (int q = 0; q < 3; ++q) {
+                    rd.lo[q] = INT64_MAX;
+                    rd.hi[q] = INT64_MIN;
+                }
                 bp.radii.push_back(rd);
             }
-            bp.radii.back().count++;
+            DevBatchRadius &cur = bp.radii.back();
+            cur.count++;
             DevBatchProbe dp{};
             dp.t = it.slot;
             dp.k = it.p.scale_id;
@@ -756,12 +746,18 @@ static int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, in
                 dp.lo[q] = INT64_MIN;
                 dp.hi[q] = INT64_MAX;
             }
-            const oss_template_feat &tf = tmpl[grp.tmap[it.slot]];
+            const int tt = grp.tmap[it.slot];
+            const oss_template_feat &tf = tmpl[tt];
+            const oss_tolerance &tol = tols[tt];
             for (int f = 0; f < 3; ++f) {
-                if (!(fm & (1u << f)))
+                if (!(fms[tt] & (1u << f)))
                     continue;
-                feature_bounds(f, tf.F[f], it.r, tf.rho, tol->P[f], tol->Q, &dp.lo[slot_of[f]],
+                feature_bounds(f, tf.F[f], it.r, tf.rho, tol.P[f], tol.Q, &dp.lo[slot_of[f]],
                                &dp.hi[slot_of[f]]);
+            }
+            for (int q = 0; q < 3; ++q) {
+                cur.lo[q] = std::min(cur.lo[q], dp.lo[q]);
+                cur.hi[q] = std::max(cur.hi[q], dp.hi[q]);
             }
             bp.probes.push_back(dp);
         }
@@ -785,12 +781,12 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t 
     const size_t o_pass = 0;
     const size_t o_grp = al(o_pass + bp.passes.size() * sizeof(DevBatchPass));
     const size_t o_rad = al(o_grp + bp.groups.size() * sizeof(DevBatchGroup));
-    const size_t o_prb = al(o_rad + bp.radii.size() * sizeof(DevRadius));
+    const size_t o_prb = al(o_rad + bp.radii.size() * sizeof(DevBatchRadius));
     const size_t total = al(o_prb + std::max<size_t>(1, bp.probes.size()) * sizeof(DevBatchProbe));
     std::vector<char> buf(total, 0);
     std::memcpy(buf.data() + o_pass, bp.passes.data(), bp.passes.size() * sizeof(DevBatchPass));
     std::memcpy(buf.data() + o_grp, bp.groups.data(), bp.groups.size() * sizeof(DevBatchGroup));
-    std::memcpy(buf.data() + o_rad, bp.radii.data(), bp.radii.size() * sizeof(DevRadius));
+    std::memcpy(buf.data() + o_rad, bp.radii.data(), bp.radii.size() * sizeof(DevBatchRadius));
     std::memcpy(buf.data() + o_prb, bp.probes.data(), bp.probes.size() * sizeof(DevBatchProbe));
     int rc = upload_plan(ctx, buf.data(), total, st, slot);
     if (rc != OSS_OK)
@@ -799,15 +795,15 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t 
     dev->passes = reinterpret_cast<const DevBatchPass *>(d + o_pass);
     dev->n_passes = (int)bp.passes.size();
     dev->groups = reinterpret_cast<const DevBatchGroup *>(d + o_grp);
-    dev->radii = reinterpret_cast<const DevRadius *>(d + o_rad);
+    dev->radii = reinterpret_cast<const DevBatchRadius *>(d + o_rad);
     dev->probes = reinterpret_cast<const DevBatchProbe *>(d + o_prb);
     dev->max_group = bp.max_group;
     return OSS_OK;
 }
 
 // The batched star pass alone (scale bits into the context workspace).
-static int batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip,
-                      int blocks, hipStream_t st, PlanSlot **slot)
+int oss::batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip,
+                    int blocks, hipStream_t st, PlanSlot **slot)
 {
     BatchDevPlan dev{};
     int rc = upload_batch_plan(ctx, bp, st, &dev, slot);
@@ -832,9 +828,11 @@ extern "C" int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref,
                                dev_list, dev_count);
     if (rc != OSS_OK)
         return rc;
+    const std::vector<oss_tolerance> tols(n_tmpl, *tol);
+    const std::vector<uint32_t> fms(n_tmpl, feat_mask);
     BatchHostPlan bp;
-    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, ctx->batch_bucket,
-                         bp);
+    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tols.data(), fms.data(),
+                         ctx->batch_bucket, bp);
     if (rc != OSS_OK)
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
@@ -883,8 +881,10 @@ extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
     if (rc != OSS_OK)
         return rc;
     // distinct radii per group bound the useful bucket sizes
+    const std::vector<oss_tolerance> tols(n_tmpl, *tol);
+    const std::vector<uint32_t> fms(n_tmpl, feat_mask);
     BatchHostPlan whole;
-    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, 0, whole);
+    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tols.data(), fms.data(), 0, whole);
     if (rc != OSS_OK)
         return rc;
     int max_radii = 0;
@@ -905,7 +905,8 @@ extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
     rc = OSS_OK;
     for (int bk : buckets) {
         BatchHostPlan bp;
-        rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tol, feat_mask, bk, bp);
+        rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tols.data(), fms.data(), bk,
+                             bp);
         if (rc != OSS_OK)
             break;
         for (int sp : strips) {

@@ -1,0 +1,84 @@
+// Host-side state behind the C ABI handles, shared by the screening entry
+// points and the serving loop.
+#pragma once
+
+#include "oss_internal.h"
+
+#include <vector>
+
+namespace oss {
+
+// One pinned staging buffer + device copy of a launch plan, reusable once
+// the event recorded after the launch that read it has completed.
+struct PlanSlot {
+    void *host = nullptr;  // pinned staging
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+constexpr int NSLOTS = 4;
+
+}  // namespace oss
+
+struct oss_ctx {
+    int device = 0;
+    uint32_t *bits = nullptr;  // scale-bit words, n_tmpl * H * W
+    size_t bits_cap = 0;       // bytes
+    void *cws = nullptr;       // compaction workspace
+    size_t cws_cap = 0;        // bytes
+    oss::PlanSlot slots[oss::NSLOTS];
+    int next_slot = 0;
+    oss::Profiler prof;
+    int star_strip = 512;          // OSS_OPT_STAR_STRIP
+    int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
+    int star_lds = 0;              // OSS_OPT_STAR_LDS
+    int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
+};
+
+struct oss_ref {
+    oss_ctx *ctx = nullptr;
+    oss_image_desc desc{};
+    uint32_t feat_mask = 0;
+    int32_t max_radius = 0;
+    oss::BuildGeom geom{};
+    void *mem = nullptr;  // one allocation for everything below
+    size_t bytes = 0;
+    oss::BuildBuffers bb{};
+};
+
+namespace oss {
+
+// Host plan of a batched launch: templates sorted by radius in groups of at
+// most BATCH_GROUP, each group's probes sorted by reference radius, passes
+// over runs of at most `bucket` distinct radii.
+struct BatchHostPlan {
+    std::vector<DevBatchPass> passes;
+    std::vector<DevBatchGroup> groups;
+    std::vector<DevBatchRadius> radii;
+    std::vector<DevBatchProbe> probes;
+    int max_group = 0;
+};
+
+// Tolerance and feature set per template (tols[t], fms[t]); every fms[t]
+// must be a subset of the reference's quantities.
+int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                    const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
+                    const uint32_t *fms, int bucket, BatchHostPlan &bp);
+
+// Upload the plan and launch the batched star pass into ctx->bits on `st`;
+// *slot is the plan slot to mark used once an event follows the launch.
+int batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip, int blocks,
+               hipStream_t st, PlanSlot **slot);
+
+// Image descriptor valid (sizes, dtype, depth, pitch).
+bool desc_ok(const oss_image_desc *d);
+
+// int64 table accumulation cannot overflow for this image and feature set.
+bool overflow_ok(const oss_image_desc *d, uint32_t fm);
+
+// Grow ctx's scale-bit and compaction workspaces to n = n_tmpl * H * W words.
+int screen_workspace(oss_ctx *ctx, int64_t n);
+
+}  // namespace oss

@@ -7,7 +7,9 @@
 // the star features of a radius are computed once per position and
 // compared against every probe of every template of the group at that
 // radius.  The scale bits of the group's templates live in registers
-// (indexed by the probe's uniform template slot).
+// (indexed by the probe's uniform template slot).  Each radius also carries
+// the hull of its probes' intervals: a wave none of whose positions lies in
+// the hull skips the probe loop (every probe would fail there).
 //
 // A group's distinct radii are split into buckets of consecutive radii.
 // A pass = (group, bucket); the launch walks all passes in order, each pass a
@@ -22,14 +24,15 @@
 
 namespace oss {
 
-template <typename T, int NQ, int MT>
+template <typename Tab, int MT>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
-    const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
-    int H, int W, const DevBatchPass *__restrict__ passes, int n_passes,
-    const DevBatchGroup *__restrict__ groups, const DevRadius *__restrict__ radii,
+    const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
+    int64_t pitch_e, int H, int W, const DevBatchPass *__restrict__ passes, int n_passes,
+    const DevBatchGroup *__restrict__ groups, const DevBatchRadius *__restrict__ radii,
     const DevBatchProbe *__restrict__ probes, uint32_t *__restrict__ bits, StarSweep sw)
 {
-    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    constexpr int NQ = Tab::NQ;
+    constexpr int64_t ES = Tab::ES;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int units = (sw.n_units - xcd + 7) / 8;
     const int items = units * sw.rows_per_part;
@@ -54,13 +57,20 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
             for (int t = 0; t < MT; ++t)
                 acc[t] = 0;
             for (int jr = ps.j0; jr < ps.j1; ++jr) {
-                const DevRadius rd = radii[jr];
+                const DevBatchRadius &rd = radii[jr];
                 const int r = rd.r, s = rd.s;
                 if (y < r || y > H - 1 - r)
                     continue;
                 if (x >= r && x <= W - 1 - r) {
                     int64_t F[NQ];
-                    star_sums<T, NQ>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                    star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                    bool in = true;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
+                    // skip the probe loop when no lane of the wave lies in the hull
+                    if (__builtin_amdgcn_ballot_w64(in) == 0)
+                        continue;
                     for (int p = rd.first; p < rd.first + rd.count; ++p) {
                         const DevBatchProbe pr = probes[p];
                         bool pass = true;
@@ -84,26 +94,24 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     }
 }
 
-template <typename T, int NQ>
-static void batch_launch_nq(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                            const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                            hipStream_t st)
+template <typename Tab>
+static void batch_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                         const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                         hipStream_t st)
 {
-    const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
-            *rp = static_cast<const T *>(Rp);
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
     if (bp.max_group <= 8)
-        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 8>), grid, block, 0, st, l, r, rp, g.pitch_e,
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 8>), grid, block, 0, st, L, R, Rp, g.pitch_e,
                            g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
     else if (bp.max_group <= 16)
-        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 16>), grid, block, 0, st, l, r, rp,
-                           g.pitch_e, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii,
-                           bp.probes, bits, sw);
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 16>), grid, block, 0, st, L, R, Rp, g.pitch_e,
+                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           bits, sw);
     else
-        hipLaunchKernelGGL((star_batch_kernel<T, NQ, 32>), grid, block, 0, st, l, r, rp,
-                           g.pitch_e, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii,
-                           bp.probes, bits, sw);
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 32>), grid, block, 0, st, L, R, Rp, g.pitch_e,
+                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           bits, sw);
 }
 
 template <typename T>
@@ -112,11 +120,26 @@ static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, cons
                           hipStream_t st)
 {
     switch (g.nq) {
-    case 1: batch_launch_nq<T, 1>(g, L, R, Rp, bp, bits, sw, st); break;
-    case 2: batch_launch_nq<T, 2>(g, L, R, Rp, bp, bits, sw, st); break;
-    case 3: batch_launch_nq<T, 3>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 1: batch_launch<TabU<T, 1>>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 2: batch_launch<TabU<T, 2>>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 3: batch_launch<TabU<T, 3>>(g, L, R, Rp, bp, bits, sw, st); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+static hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                            const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                            hipStream_t st)
+{
+    if (g.nq == 3 && g.sqi == 1)
+        batch_launch<TabMix<3, 1>>(g, L, R, Rp, bp, bits, sw, st);
+    else if (g.nq == 2 && g.sqi == 1)
+        batch_launch<TabMix<2, 1>>(g, L, R, Rp, bp, bits, sw, st);
+    else if (g.nq == 2 && g.sqi == 0)
+        batch_launch<TabMix<2, 0>>(g, L, R, Rp, bp, bits, sw, st);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -128,6 +151,8 @@ hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, c
         bp.max_group > BATCH_GROUP)
         return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_BATCH, stream);
+    if (g.sqi >= 0)
+        return batch_mix(g, L, R, Rp, bp, bits, sw, stream);
     if (g.ebytes == 4)
         return batch_t<uint32_t>(g, L, R, Rp, bp, bits, sw, stream);
     return batch_t<uint64_t>(g, L, R, Rp, bp, bits, sw, stream);

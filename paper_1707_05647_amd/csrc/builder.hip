@@ -31,13 +31,15 @@ namespace oss {
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-BuildGeom make_geom(int H, int W, int nq, int ebytes)
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi)
 {
     BuildGeom g;
     g.H = H;
     g.W = W;
     g.nq = nq;
     g.ebytes = ebytes;
+    g.sqi = sqi;
+    g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
     g.pitch_e = ((int64_t)W + 1 + 15) / 16 * 16;
     g.nb = cdiv(H + 1, KBAND);
     // final tiles: cores cover [-1, W-1]; the first core starts at -64+HALO <= -1
@@ -483,15 +485,30 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__rest
 //   advance:        L += P, T_ad = ta_r + P, T_d = td_l + P
 // The last row is stored after one more barrier.
 // ---------------------------------------------------------------------------
-template <typename T, int NQ>
+// Entry e of a table: NQ values of T (MIX < 0), or the 16-byte mixed entry
+// (64-bit squares from slot MIX, the other quantities modulo 2^32) written as
+// one 16-byte store.
+template <typename T, int NQ, int MIX>
 __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v)
 {
+    if constexpr (MIX < 0) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        tab[e * NQ + q] = v[q];
+        for (int q = 0; q < NQ; ++q)
+            tab[e * NQ + q] = v[q];
+    } else {
+        uint32_t o[2] = {0u, 0u};
+        int j = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q != MIX)
+                o[j++] = (uint32_t)v[q];
+        const uint64_t sq = (uint64_t)v[MIX];
+        *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(tab) + e * 16) =
+            make_uint4((uint32_t)sq, (uint32_t)(sq >> 32), o[0], o[1]);
+    }
 }
 
-template <typename Pix, unsigned FM, typename T>
+template <typename Pix, unsigned FM, typename T, int MIX>
 __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const T *__restrict__ bp,
     const T *__restrict__ cL, const T *__restrict__ cAD, const T *__restrict__ cD,
@@ -589,9 +606,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
                 r[q] = TA[q] - td_l[q];
                 rp[q] = ta_r[q] - td_l[q];
             }
-            store_entry<T, NQ>(tL, e, Lc);
-            store_entry<T, NQ>(tR, e, r);
-            store_entry<T, NQ>(tRp, e, rp);
+            store_entry<T, NQ, MIX>(tL, e, Lc);
+            store_entry<T, NQ, MIX>(tR, e, r);
+            store_entry<T, NQ, MIX>(tRp, e, rp);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -626,13 +643,13 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     }
     if (store) {
         const int64_t e = (int64_t)(ys + rows) * g.pitch_e + (x + 1);
-        store_entry<T, NQ>(tL, e, Lc);
-        store_entry<T, NQ>(tR, e, r);
-        store_entry<T, NQ>(tRp, e, rp);
+        store_entry<T, NQ, MIX>(tL, e, Lc);
+        store_entry<T, NQ, MIX>(tR, e, r);
+        store_entry<T, NQ, MIX>(tRp, e, rp);
     }
 }
 
-template <typename Pix, unsigned FM, typename T>
+template <typename Pix, unsigned FM, typename T, int MIX = -1>
 static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_bytes,
                           const BuildBuffers &bb, hipStream_t st, Profiler *prof)
 {
@@ -662,7 +679,7 @@ static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_
     }
     {
         ProfScope ps(prof, K_BAND_FINAL, st);
-        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T>), dim3(g.nfin, g.nb),
+        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, MIX>), dim3(g.nfin, g.nb),
                            dim3(BAND_THREADS), 0, st, img, pitch, g, bp, cL, cAD, cD,
                            static_cast<T *>(bb.L), static_cast<T *>(bb.R),
                            static_cast<T *>(bb.Rp));
@@ -674,6 +691,15 @@ template <typename Pix, typename T>
 static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint32_t fm,
                             const BuildBuffers &bb, hipStream_t st, Profiler *pr)
 {
+    if (g.sqi >= 0) {
+        // mixed entries: 64-bit accumulation, the squares stored in 64 bits
+        switch (fm) {
+        case 3: return build_t<Pix, 3, uint64_t, 1>(g, px, pb, bb, st, pr);
+        case 6: return build_t<Pix, 6, uint64_t, 0>(g, px, pb, bb, st, pr);
+        case 7: return build_t<Pix, 7, uint64_t, 1>(g, px, pb, bb, st, pr);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (fm) {
     case 1: return build_t<Pix, 1, T>(g, px, pb, bb, st, pr);
     case 2: return build_t<Pix, 2, T>(g, px, pb, bb, st, pr);
@@ -690,6 +716,8 @@ hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_by
                         uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
                         Profiler *prof)
 {
+    if (g.sqi >= 0 && g.ebytes != 8)
+        return hipErrorInvalidValue;
     if (g.ebytes == 4) {
         if (dtype == OSS_U8)
             return build_pix<uint8_t, uint32_t>(g, pixels, pitch_bytes, feat_mask, bb, stream,

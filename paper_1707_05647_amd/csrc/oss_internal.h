@@ -42,7 +42,9 @@ static_assert(BAND_STRIDE % 64 == 0, "tile starts must stay 64-aligned");
 
 struct BuildGeom {
     int H, W, nq;
-    int ebytes;        // bytes per table quantity: 4 (stored mod 2^32) or 8
+    int ebytes;        // bytes per accumulated quantity: 4 (mod 2^32) or 8
+    int sqi;           // mixed entries: slot of the squares among the quantities, else -1
+    int tab_es;        // bytes per table entry: nq * ebytes, or 16 for mixed entries
     int64_t pitch_e;   // table entries per row (>= W+1)
     int nb;            // bands
     int nfin, fin_x0;  // final tiles: first thread column of tile c is fin_x0 + c*BAND_STRIDE
@@ -51,7 +53,11 @@ struct BuildGeom {
     int nbp;           // row-prefix bases per row: P_y(64 j - 1), j in [0, nbp)
 };
 
-BuildGeom make_geom(int H, int W, int nq, int ebytes);
+// Table entries hold the nq quantities in feature order, each in ebytes
+// bytes; with sqi >= 0 (ebytes 8) an entry is 16 bytes instead: the squares
+// (quantity slot sqi) as 64 bits, then the other quantities in feature order
+// as 32 bits each (modulo 2^32), zero padded.
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1);
 
 // ---------------------------------------------------------------------------
 // Screening plan uploaded per call.
@@ -97,11 +103,19 @@ struct DevBatchPass {
     int32_t first;   // 1: write the group's scale bits, 0: OR into them
 };
 
+// One radius of a batched group: its probes, and the hull of their
+// intervals per feature slot (a position outside it fails every probe).
+struct DevBatchRadius {
+    int32_t r, s;
+    int32_t first, count;
+    int64_t lo[3], hi[3];
+};
+
 struct BatchDevPlan {
     const DevBatchPass *passes;
     int n_passes;
     const DevBatchGroup *groups;
-    const DevRadius *radii;
+    const DevBatchRadius *radii;
     const DevBatchProbe *probes;
     int max_group;
 };

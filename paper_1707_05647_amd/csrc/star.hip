@@ -35,13 +35,14 @@
 
 namespace oss {
 
-template <typename T, int NQ>
+template <typename Tab>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
-    const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
-    int H, int W, const DevTemplatePlan *__restrict__ plan, uint32_t *__restrict__ bits,
-    StarSweep sw)
+    const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
+    int64_t pitch_e, int H, int W, const DevTemplatePlan *__restrict__ plan,
+    uint32_t *__restrict__ bits, StarSweep sw)
 {
-    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;  // bytes per table entry
+    constexpr int NQ = Tab::NQ;
+    constexpr int64_t ES = Tab::ES;  // bytes per table entry
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int units = (sw.n_units - xcd + 7) / 8;  // units u = xcd + 8 t of this XCD
     const int items = units * sw.rows_per_part;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
                 continue;
             if (x >= r && x <= W - 1 - r) {
                 int64_t F[NQ];
-                star_sums<T, NQ>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
                 for (int p = rd.first; p < rd.first + rd.count; ++p) {
                     const DevProbe pr = plan->probes[p];
                     bool pass = true;
@@ -148,8 +149,10 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_lds_kernel(
             const bool valid = x >= r && x <= W - 1 - r;
             Entry<T, NQ> e, k;
             if (valid) {
-                e = at<T, NQ>(Rb + (int64_t)(y + r + 1) * row_bytes, lane_off);  // R(x, y+r)
-                k = at<T, NQ>(Rb + (int64_t)(y - r) * row_bytes, lane_off);      // R(x, y-r-1)
+                e = entry_at<Entry<T, NQ>>(Rb + (int64_t)(y + r + 1) * row_bytes,
+                                           lane_off);  // R(x, y+r)
+                k = entry_at<Entry<T, NQ>>(Rb + (int64_t)(y - r) * row_bytes,
+                                           lane_off);  // R(x, y-r-1)
             }
             __syncthreads();  // the previous radius' L readers are done
             const int n = strip + 2 * s + 1;
@@ -211,6 +214,15 @@ static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T 
                        stream, l, r, rp, g.pitch_e, g.H, g.W, plan, bits, sw, smax, rmax);
 }
 
+template <typename Tab>
+static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL((star_plain_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), 0,
+                       stream, L, R, Rp, g.pitch_e, g.H, g.W, plan, bits, sw);
+}
+
 template <typename T>
 static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                          const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
@@ -218,7 +230,6 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
-    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
     if (lds) {
         switch (g.nq) {
         case 1: star_lds_launch<T, 1>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
@@ -229,21 +240,27 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
         return hipGetLastError();
     }
     switch (g.nq) {
-    case 1:
-        hipLaunchKernelGGL((star_plain_kernel<T, 1>), grid, block, 0, stream, l, r, rp,
-                           g.pitch_e, g.H, g.W, plan, bits, sw);
-        break;
-    case 2:
-        hipLaunchKernelGGL((star_plain_kernel<T, 2>), grid, block, 0, stream, l, r, rp,
-                           g.pitch_e, g.H, g.W, plan, bits, sw);
-        break;
-    case 3:
-        hipLaunchKernelGGL((star_plain_kernel<T, 3>), grid, block, 0, stream, l, r, rp,
-                           g.pitch_e, g.H, g.W, plan, bits, sw);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream); break;
+    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream); break;
+    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream); break;
+    default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// Mixed 16-byte entries (the squares in 64 bits): no LDS variant.
+static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                           const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                           hipStream_t stream)
+{
+    if (g.nq == 3 && g.sqi == 1)
+        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream);
+    else if (g.nq == 2 && g.sqi == 1)
+        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream);
+    else if (g.nq == 2 && g.sqi == 0)
+        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -256,6 +273,8 @@ hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, c
     if (lds && star_lds_bytes(sw.strip, g.nq, g.ebytes, smax, rmax) > STAR_LDS_MAX)
         lds = false;
     ProfScope ps(prof, K_STAR, stream);
+    if (g.sqi >= 0)
+        return star_mix(g, L, R, Rp, plan, bits, sw, stream);
     if (g.ebytes == 4)
         return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);
     return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);

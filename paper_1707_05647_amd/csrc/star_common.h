@@ -22,17 +22,74 @@ __device__ __forceinline__ Entry<T, NQ> at(const char *row, uint32_t lane_off)
     return *reinterpret_cast<const Entry<T, NQ> *>(row + lane_off);
 }
 
+// Table entry layouts.  TabU: NQ quantities of T in feature order.  TabMix:
+// 16-byte entries with the squares (feature slot SQI) as 64 bits and the
+// other quantities, in feature order, as 32 bits modulo 2^32.  reduce()
+// forms the square and the diamond sum of every quantity in the entry's
+// width (a - b - c + d) and adds the two widened sums in 64 bits: a region
+// sum below 2^32 is exact modulo 2^32.
+template <typename T, int NQ_>
+struct TabU {
+    static constexpr int NQ = NQ_;
+    static constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    using E = Entry<T, NQ>;
+    __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
+                                                  const E &e, const E &f, const E &h, const E &k,
+                                                  int64_t *F)
+    {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            F[q] = widen((T)(a.v[q] - b.v[q] - c.v[q] + d.v[q])) +
+                   widen((T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]));
+    }
+};
+
+struct MixEntry {
+    uint64_t sq;
+    uint32_t o[2];
+};
+
+template <int NQ_, int SQI>
+struct TabMix {
+    static constexpr int NQ = NQ_;
+    static constexpr int64_t ES = 16;
+    using E = MixEntry;
+    __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
+                                                  const E &e, const E &f, const E &h, const E &k,
+                                                  int64_t *F)
+    {
+        F[SQI] = widen((uint64_t)(a.sq - b.sq - c.sq + d.sq)) +
+                 widen((uint64_t)(e.sq - f.sq - h.sq + k.sq));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q == SQI)
+                continue;
+            const int j = q < SQI ? q : q - 1;
+            F[q] = widen((uint32_t)(a.o[j] - b.o[j] - c.o[j] + d.o[j])) +
+                   widen((uint32_t)(e.o[j] - f.o[j] - h.o[j] + k.o[j]));
+        }
+    }
+};
+
+// Entry at a wave-uniform row base plus this lane's byte offset.
+template <typename E>
+__device__ __forceinline__ E entry_at(const char *row, uint32_t lane_off)
+{
+    return *reinterpret_cast<const E *>(row + lane_off);
+}
+
 // Star feature sums at (x0 + lane, y) for radius r (square half-width s):
 // the square by 4 lookups into L (Eq. S_1), the diamond by 2 into R and 2
 // into R'.  Lb/Rb/Rpb point at table column x0 (the lane adds lane_off =
 // (lane + 1) entries: table column = image column + 1); table row = image
 // row + 1.  Only called for positions where the star fits.
-template <typename T, int NQ>
+template <typename Tab>
 __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
                                           int64_t row_bytes, uint32_t lane_off, int y, int r,
                                           int s, int64_t *F)
 {
-    constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    using E = typename Tab::E;
+    constexpr int64_t ES = Tab::ES;
     const char *l_top = Lb + (int64_t)(y - s) * row_bytes;      // row y-s-1
     const char *l_bot = Lb + (int64_t)(y + s + 1) * row_bytes;  // row y+s
     const char *r_top = Rb + (int64_t)(y - r) * row_bytes;      // row y-r-1
@@ -40,18 +97,15 @@ __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const 
     const char *rp_mid = Rpb + (int64_t)y * row_bytes;           // row y-1
     const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
     const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
-    const Entry<T, NQ> a = at<T, NQ>(l_bot + ds, lane_off);    // L(x+s,   y+s)
-    const Entry<T, NQ> b = at<T, NQ>(l_bot - ds1, lane_off);   // L(x-s-1, y+s)
-    const Entry<T, NQ> c = at<T, NQ>(l_top + ds, lane_off);    // L(x+s,   y-s-1)
-    const Entry<T, NQ> d = at<T, NQ>(l_top - ds1, lane_off);   // L(x-s-1, y-s-1)
-    const Entry<T, NQ> e = at<T, NQ>(r_bot, lane_off);         // R(x, y+r)
-    const Entry<T, NQ> f = at<T, NQ>(rp_mid - dr1, lane_off);  // R'(x-r-1, y-1)
-    const Entry<T, NQ> h = at<T, NQ>(rp_mid + dr, lane_off);   // R'(x+r, y-1)
-    const Entry<T, NQ> k = at<T, NQ>(r_top, lane_off);         // R(x, y-r-1)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        F[q] = widen((T)(a.v[q] - b.v[q] - c.v[q] + d.v[q])) +
-               widen((T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]));
+    const E a = entry_at<E>(l_bot + ds, lane_off);    // L(x+s,   y+s)
+    const E b = entry_at<E>(l_bot - ds1, lane_off);   // L(x-s-1, y+s)
+    const E c = entry_at<E>(l_top + ds, lane_off);    // L(x+s,   y-s-1)
+    const E d = entry_at<E>(l_top - ds1, lane_off);   // L(x-s-1, y-s-1)
+    const E e = entry_at<E>(r_bot, lane_off);         // R(x, y+r)
+    const E f = entry_at<E>(rp_mid - dr1, lane_off);  // R'(x-r-1, y-1)
+    const E h = entry_at<E>(rp_mid + dr, lane_off);   // R'(x+r, y-1)
+    const E k = entry_at<E>(r_top, lane_off);         // R(x, y-r-1)
+    Tab::reduce(a, b, c, d, e, f, h, k, F);
 }
 
 // Position of sweep item `it` of XCD `xcd`: image row y and the strip's first

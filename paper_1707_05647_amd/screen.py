@@ -36,6 +36,7 @@ class Reference:
         self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask, max_radius)
         info = L.oss_ref_tables(self.handle)
         self.value_bits, self.max_radius = info[5], info[6]
+        self.entry_bytes, self.slots = L.oss_ref_layout(self.handle)
         if build:
             self.build(stream)
 
@@ -58,15 +59,24 @@ class Reference:
             self.handle = None
 
     def tables_host(self):
-        """Copy (L, R, R') to host arrays [H+1, W+1, nq] (uint32 holding the
-        sums modulo 2^32, or int64; synchronous; for tests and inspection)."""
+        """Copy (L, R, R') to host int64 arrays [H+1, W+1, nq]: each slot's
+        stored value (``self.slots[q][1]`` bits wide: 32 = the sums modulo
+        2^32, zero-extended; 64 = exact); synchronous; for tests and
+        inspection."""
         Lp, Rp_, Rpp, pitch, nq, vb, _ = L.oss_ref_tables(self.handle)
-        dt = np.uint32 if vb == 32 else np.int64
+        eb = self.entry_bytes
         out = []
         for p in (Lp, Rp_, Rpp):
-            a = np.empty((self.H + 1, pitch, nq), dt)
-            _hip_memcpy_d2h(a, p)
-            out.append(np.ascontiguousarray(a[:, :self.W + 1, :]))
+            raw = np.empty((self.H + 1, pitch, eb), np.uint8)
+            _hip_memcpy_d2h(raw, p)
+            raw = raw[:, :self.W + 1, :]
+            t = np.empty((self.H + 1, self.W + 1, nq), np.int64)
+            for q, (off, bits) in enumerate(self.slots):
+                nb = bits // 8
+                v = np.ascontiguousarray(raw[:, :, off:off + nb]).view(
+                    np.uint32 if nb == 4 else np.int64)[..., 0]
+                t[..., q] = v.astype(np.int64)
+            out.append(t)
         return out
 
 
@@ -126,3 +136,59 @@ def _hip_memcpy_d2h(dst: np.ndarray, src_ptr: int):
     rc = _hip.hipMemcpy(dst.ctypes.data, src_ptr, dst.nbytes, 2)  # hipMemcpyDeviceToHost
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+class Server:
+    """Serving loop over the C ABI (oss_server_*): queued requests, admission
+    by device-memory footprint, resident-reference cache, merged launches."""
+
+    def __init__(self, device: int = 0, memory_budget: int = 64 << 30, lanes: int = 2,
+                 max_batch_templates: int = 64):
+        self.handle = L.oss_server_create(device, memory_budget, lanes, max_batch_templates)
+        self._pixels = {}  # request id -> device pixels kept alive until release
+
+    def submit(self, ref_key: int, pixels, templates, probes, tol, feat_mask: int,
+               list_cap: int, bit_depth: int | None = None, arrival_ns: int = 0) -> int:
+        rid = L.oss_server_submit(self.handle, ref_key, pixels, templates, probes, tol, feat_mask,
+                                  list_cap, bit_depth, arrival_ns)
+        self._pixels[rid] = pixels
+        return rid
+
+    def pump(self, wait_us: int = 0) -> int:
+        return L.oss_server_pump(self.handle, wait_us)
+
+    def drain(self):
+        L.oss_server_drain(self.handle)
+
+    def result(self, rid: int):
+        return L.oss_server_result(self.handle, rid)
+
+    def host_result(self, rid: int):
+        """(mask ndarray [T, H, W], candidates [n, 4] int64, total count) of a
+        completed request (synchronous copies)."""
+        r = self.result(rid)
+        if r.status != L.OSS_OK:
+            raise L.OssError(r.status, f"request {rid}")
+        mask = np.empty((r.n_tmpl, r.H, r.W), np.uint8)
+        _hip_memcpy_d2h(mask, r.dev_mask)
+        n = min(r.count, r.list_cap)
+        c = np.empty((n, 4), np.int32)
+        if n:
+            _hip_memcpy_d2h(c, r.dev_list)
+        c = c.astype(np.int64)
+        if n:
+            c[:, 3] &= 0xFFFFFFFF
+        return mask, c, r.count
+
+    def release(self, rid: int):
+        L.oss_server_release(self.handle, rid)
+        self._pixels.pop(rid, None)
+
+    def stats(self) -> dict:
+        return L.oss_server_stats_read(self.handle)
+
+    def close(self):
+        if self.handle:
+            L.oss_server_destroy(self.handle)
+            self.handle = None
+            self._pixels.clear()

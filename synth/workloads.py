@@ -183,7 +183,7 @@ class Request:
 def serving_requests(n: int, rate_per_s: float, seed: int = 0, *, side_lo: int = 1024,
                      side_hi: int = 8192, reuse: float = 0.3, max_templates: int = 8,
                      rho_lo: int = 8, rho_hi: int = 128, max_scales: int = 9,
-                     blobs_per_512sq: float = 200.0):
+                     blobs_per_512sq: float = 200.0, device=None):
     """Poisson request stream.  Returns (requests, images) where ``images``
     maps ref_key -> reference image.  Sides are log-uniform in
     [side_lo, side_hi]; a fraction ``reuse`` of requests names a reference
@@ -201,7 +201,7 @@ def serving_requests(n: int, rate_per_s: float, seed: int = 0, *, side_lo: int =
             key = len(images)
             side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
             images[key] = blob_image(side, side, make_rng(40, seed * 100003 + key),
-                                     blobs_per_512sq=blobs_per_512sq)
+                                     blobs_per_512sq=blobs_per_512sq, device=device)
         ref = images[key]
         side = ref.shape[0]
         n_t = int(rng.integers(1, max_templates + 1))

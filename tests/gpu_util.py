@@ -89,6 +89,7 @@ class Runner:
             bit_depth = 8 if img.dtype == np.uint8 else 16
         ref = self.ctx.reference(t_img, fm, bit_depth, max_radius=max_radius)
         self.last_value_bits = ref.value_bits
+        self.last_entry_bytes = ref.entry_bytes
         tm = [self.L.oss_template_features(px, rho, tm_fm or fm, bit_depth=bit_depth)
               for px, rho in templates]
         H, W = img.shape

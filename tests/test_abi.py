@@ -45,12 +45,16 @@ def test_status_strings(lib):
 
 def test_ref_bytes(lib):
     d = lib.image_desc(4096, 4096)
-    b3 = lib.oss_ref_bytes(d, 7)           # any radius: squares need int64
+    # any radius (up to 2047): the squares need 64 bits, the sums (255 A(r))
+    # and the gradients (510 A(r) <= 4.28e9) still fit 32: 16-byte entries
+    b3 = lib.oss_ref_bytes(d, 7)
     b1 = lib.oss_ref_bytes(d, 1)           # 8-bit sums fit 32 bits at any radius
     b3_64 = lib.oss_ref_bytes(d, 7, 64)    # radius <= 64: every sum below 2^32
+    b3_big = lib.oss_ref_bytes(d, 7, 3000)  # gradients past 2^32: 64-bit entries
     tables = 3 * 4097 * 4112
-    assert tables * 4 <= b1 < tables * 4 * 1.2 and b3 >= 3 * tables * 8
-    assert b3 < 3 * tables * 8 * 1.2
+    assert tables * 4 <= b1 < tables * 4 * 1.2
+    assert tables * 16 <= b3 < tables * 16 * 1.2
+    assert 3 * tables * 8 <= b3_big < 3 * tables * 8 * 1.2
     assert 3 * tables * 4 <= b3_64 < 3 * tables * 4 * 1.2
     # 12-bit squares at radius 96 do not fit 32 bits; sums alone do
     d12 = lib.image_desc(1024, 1024, lib.OSS_U16, 12)
@@ -124,3 +128,21 @@ def test_screen_argument_errors_before_any_launch(lib):
                         None) == lib.OSS_E_ARG
     assert L.oss_ref_create(None, None, 7, -1, None) == lib.OSS_E_ARG
     assert L.oss_ref_build(None, None, None) == lib.OSS_E_ARG
+
+
+def test_server_argument_errors(lib):
+    """Config and null-handle errors are reported before any device work."""
+    L = lib.load()
+    h = C.c_void_p()
+    for budget, lanes, mb in ((0, 1, 1), (1 << 30, 0, 1), (1 << 30, 9, 1), (1 << 30, 1, 0)):
+        cfg = lib.oss_server_config(budget, lanes, mb)
+        assert L.oss_server_create(0, C.byref(cfg), C.byref(h)) == lib.OSS_E_ARG
+    assert L.oss_server_create(0, None, C.byref(h)) == lib.OSS_E_ARG
+    rid = C.c_int64()
+    assert L.oss_server_submit(None, None, C.byref(rid)) == lib.OSS_E_ARG
+    assert L.oss_server_pump(None, 0, None) == lib.OSS_E_ARG
+    assert L.oss_server_drain(None) == lib.OSS_E_ARG
+    assert L.oss_server_release(None, 1) == lib.OSS_E_ARG
+    assert L.oss_server_destroy(None) == lib.OSS_E_ARG
+    out = lib.oss_result()
+    assert L.oss_server_result(None, 1, C.byref(out)) == lib.OSS_E_ARG

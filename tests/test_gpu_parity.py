@@ -30,6 +30,9 @@ TABLE_CASES = [
     (70, 450, 8, 4, 0, -1),
     (64, 64, 16, 2, 0, -1),         # full 16-bit squares (64-bit storage)
     (91, 931, 16, 1, 0, 3),         # 16-bit sums, 32-bit storage
+    (129, 100, 12, 7, 0, 40),       # mixed entries: 64-bit squares, 32-bit sums and gradients
+    (61, 530, 8, 3, 7, 200),        # mixed entries, sums and squares
+    (45, 300, 12, 6, 0, 60),        # mixed entries, squares and gradients
 ]
 
 
@@ -50,21 +53,26 @@ def test_tables_match_definitions(runner, case):
     ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
     torch.cuda.synchronize()
     got = ref.tables_host()
-    bits = ref.value_bits
+    slots = ref.slots
     ref.release()
     want = tables_numpy(img, fm)
-    if bits == 32:
-        want = [w_ % (1 << 32) for w_ in want]
+    for w_ in want:
+        for q, (_, b) in enumerate(slots):
+            if b == 32:
+                w_[..., q] %= 1 << 32
     bad = []
     for name, g, w in zip(("L", "R", "R'"), got, want):
         diff = np.argwhere(g.astype(np.int64) != w)
         if len(diff):
             bad.append(f"{name}: {len(diff)} wrong entries of {g.size}, first (row, col, q) "
                        f"{diff[:6].tolist()} (table row = y+1, col = x+1)")
-    assert not bad, f"{bits}-bit tables: " + "; ".join(bad)
+    assert not bad, f"tables with slots {slots}: " + "; ".join(bad)
 
 
-WIDTHS = pytest.mark.parametrize("max_r", [-2, 1 << 20], ids=["w32", "w64"])
+# max radius -> storage: the probes' own maximum (32-bit entries unless the
+# sums need more), 200 (64-bit squares in mixed 16-byte entries for 8- and
+# 12-bit pixels), 2^20 (64-bit entries)
+WIDTHS = pytest.mark.parametrize("max_r", [-2, 200, 1 << 20], ids=["w32", "wmix", "w64"])
 
 
 def _screen_and_compare(runner, w, max_r=-1, **kw):
@@ -75,7 +83,8 @@ def _screen_and_compare(runner, w, max_r=-1, **kw):
     say(f"screen workload {w.cfg_id} {w.H}x{w.W} T={len(tm)} probes={len(w.probes)} {kw}")
     mask, cands, n = runner.screen(w.ref, tm, w.probes, w.feat_mask, P, Q,
                                    bit_depth=w.depth, max_radius=max_r, **kw)
-    say(f"  storage {runner.last_value_bits}-bit, {n} candidates")
+    say(f"  storage {runner.last_value_bits}-bit, {runner.last_entry_bytes} B entries, "
+        f"{n} candidates")
     want = oc.screen_full(w.ref, tm, w.probes, w.feat_mask, P, Q)
     wmask, wlist = oc.mask_and_list(want)
     assert n == len(wlist)
@@ -163,7 +172,8 @@ def test_overflow_edge_constant_max(runner, depth, max_r):
 
 def test_32bit_storage_near_its_limit(runner):
     """12-bit pixels, radius 10: square sums of squares reach 3.77e9 < 2^32,
-    so the reference is stored in 32-bit words; radius 11 would not fit."""
+    so the reference is stored in 32-bit words; at radius 11 the squares
+    need 64 bits (mixed 16-byte entries) while sums and gradients still fit."""
     rng = np.random.default_rng(4)
     img = rng.integers(3900, 4096, (64, 80)).astype(np.uint16)
     img[20:40, 30:50] = 4095
@@ -175,7 +185,7 @@ def test_32bit_storage_near_its_limit(runner):
     want = oc.screen_full(img, tm, probes, 7, P, Q)
     assert np.array_equal(cands, oc.mask_and_list(want)[1]) and n > 0
     mask, cands, n = runner.screen(img, tm, probes, 7, P, Q, bit_depth=12, max_radius=11)
-    assert runner.last_value_bits == 64
+    assert runner.last_value_bits == 64 and runner.last_entry_bytes == 16  # 64-bit squares only
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
 
 
