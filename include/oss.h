@@ -136,11 +136,16 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *   OSS_OPT_BATCH_BUCKET         oss_screen_batched: at most this many distinct
  *                                radii per pass (0: all radii of a template
  *                                group in one pass; default 0)
+ *   OSS_OPT_TABLE_PLANAR         1: references created afterwards store each
+ *                                quantity in a table plane of its own when
+ *                                every quantity fits 32-bit storage, instead
+ *                                of side by side in one entry; default 0
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
 #define OSS_OPT_STAR_LDS 3
 #define OSS_OPT_BATCH_BUCKET 4
+#define OSS_OPT_TABLE_PLANAR 5
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 
@@ -219,15 +224,17 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
                    int32_t *max_radius);
 
 /*
- * Layout of one table entry of `ref` (L, R and R' share it): *entry_bytes
- * per entry, and for each quantity slot q < nq (feature order: sum, squares,
- * gradient, enabled ones only) the byte offset of its value in the entry and
- * its width in bits (32: stored modulo 2^32, 64: two's complement); slots
- * q >= nq get offset -1, width 0.  Entries are 4 * nq bytes (all 32-bit),
- * 8 * nq bytes (all 64-bit), or 16 bytes when only the squares need 64 bits:
- * the squares at offset 0, the other quantities at 8 and 12.
+ * Layout of the tables of `ref` (L, R and R' share it): quantity slot q
+ * (feature order: sum, squares, gradient, enabled ones only) of entry
+ * (x, y) is the bits[q]-wide value (32: stored modulo 2^32, 64: two's
+ * complement) at byte ((y+1) * pitch_entries + (x+1)) * entry_stride +
+ * offset[q] of the table; slots q >= nq get offset -1, width 0.  Interleaved
+ * entries are 4 * nq bytes (all 32-bit), 8 * nq bytes (all 64-bit) or 16
+ * bytes when only the squares need 64 bits (squares at offset 0, the other
+ * quantities at 8 and 12); planar tables (OSS_OPT_TABLE_PLANAR) have
+ * entry_stride 4 and one plane per quantity at offset q * plane bytes.
  */
-int oss_ref_layout(const oss_ref *ref, int32_t *entry_bytes, int32_t offset[3],
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[3],
                    int32_t bits[3]);
 
 /* Template features (host, synchronous): the radius-rho star at the centre

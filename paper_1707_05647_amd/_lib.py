@@ -29,6 +29,7 @@ EXPORTED = [
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
+OSS_OPT_TABLE_PLANAR = 5
 OSS_TUNE_MAX = 64
 
 
@@ -125,7 +126,7 @@ def load(path: str | None = None):
     lib.oss_ref_tables.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                    C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(i32)]
-    lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]
     lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
@@ -271,9 +272,9 @@ def oss_ref_release(ref: int):
 
 
 def oss_ref_layout(ref: int):
-    """(entry_bytes, [(offset, bits) per quantity slot])."""
+    """(entry_stride, [(offset, bits) per quantity slot])."""
     eb = C.c_int32()
-    off = (C.c_int32 * 3)()
+    off = (C.c_int64 * 3)()
     bits = (C.c_int32 * 3)()
     _check(load().oss_ref_layout(ref, C.byref(eb), off, bits), "oss_ref_layout")
     return eb.value, [(off[q], bits[q]) for q in range(3) if bits[q]]

@@ -162,7 +162,7 @@ enum { A_L, A_R, A_RP, A_BP, A_AGL, A_AGAD, A_AGD, A_CL, A_CAD, A_CD, A_COUNT };
 static size_t ref_layout(const BuildGeom &g, size_t off[A_COUNT])
 {
     const size_t e = (size_t)g.ebytes * (size_t)g.nq;
-    const size_t table = (size_t)(g.H + 1) * (size_t)g.pitch_e * (size_t)g.tab_es;
+    const size_t table = (size_t)g.tab_bytes;
     const size_t bp = (size_t)g.H * g.nbp * e;
     const size_t car = (size_t)g.nb * g.cw * e;
     const size_t sizes[A_COUNT] = {table, table, table, bp, car, car, car, car, car, car};
@@ -204,9 +204,9 @@ static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
 
 // A quantity can be stored modulo 2^32 when every square and every diamond
 // sum of it up to the maximum radius stays below 2^32.  All quantities fit:
-// 32-bit entries.  Only the squares do not: mixed 16-byte entries (squares
-// in 64 bits).  Otherwise 64-bit entries.
-static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R)
+// 32-bit entries (interleaved, or planar on request).  Only the squares do
+// not: mixed 16-byte entries (squares in 64 bits).  Otherwise 64-bit entries.
+static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int planar)
 {
     const __int128 s = square_half(R);
     const __int128 area = std::max((2 * s + 1) * (2 * s + 1),
@@ -214,7 +214,7 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R)
     auto fits = [&](uint32_t m) { return max_quantity(d, m) * area < ((__int128)1 << 32); };
     const int nq = popc(fm);
     if (fits(fm))
-        return make_geom(d->H, d->W, nq, 4);
+        return make_geom(d->H, d->W, nq, 4, -1, planar);
     if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ))
         return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0);
     return make_geom(d->H, d->W, nq, 8);
@@ -224,9 +224,11 @@ int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_ra
 {
     if (!out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
         return OSS_E_ARG;
-    const BuildGeom g = ref_geom(desc, feat_mask, resolve_max_radius(desc, max_radius));
+    // the larger of the interleaved and the planar layout
+    const int32_t R = resolve_max_radius(desc, max_radius);
     size_t off[A_COUNT];
-    *out = ref_layout(g, off);
+    *out = std::max(ref_layout(ref_geom(desc, feat_mask, R, 0), off),
+                    ref_layout(ref_geom(desc, feat_mask, R, 1), off));
     return OSS_OK;
 }
 
@@ -247,7 +249,7 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
     r->desc = *desc;
     r->feat_mask = feat_mask;
     r->max_radius = resolve_max_radius(desc, max_radius);
-    r->geom = ref_geom(desc, feat_mask, r->max_radius);
+    r->geom = ref_geom(desc, feat_mask, r->max_radius, ctx->table_planar);
     size_t off[A_COUNT];
     r->bytes = ref_layout(r->geom, off);
     if (hipMalloc(&r->mem, r->bytes) != hipSuccess) {
@@ -315,19 +317,22 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
     return OSS_OK;
 }
 
-int oss_ref_layout(const oss_ref *ref, int32_t *entry_bytes, int32_t offset[3], int32_t bits[3])
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[3], int32_t bits[3])
 {
-    if (!ref || !entry_bytes || !offset || !bits)
+    if (!ref || !entry_stride || !offset || !bits)
         return OSS_E_ARG;
     const BuildGeom &g = ref->geom;
-    *entry_bytes = g.tab_es;
+    *entry_stride = g.tab_es;
     int j = 0;
     for (int q = 0; q < 3; ++q) {
         offset[q] = -1;
         bits[q] = 0;
     }
     for (int q = 0; q < g.nq; ++q) {
-        if (g.sqi < 0) {
+        if (g.planar) {
+            offset[q] = q * g.plane;
+            bits[q] = 8 * g.ebytes;
+        } else if (g.sqi < 0) {
             offset[q] = q * g.ebytes;
             bits[q] = 8 * g.ebytes;
         } else if (q == g.sqi) {
@@ -420,6 +425,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->batch_bucket = value;
         return OSS_OK;
+    case OSS_OPT_TABLE_PLANAR:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->table_planar = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -434,6 +444,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_STAR_BLOCKS_PER_XCD: *value = ctx->star_blocks_per_xcd; return OSS_OK;
     case OSS_OPT_STAR_LDS: *value = ctx->star_lds; return OSS_OK;
     case OSS_OPT_BATCH_BUCKET: *value = ctx->batch_bucket; return OSS_OK;
+    case OSS_OPT_TABLE_PLANAR: *value = ctx->table_planar; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }

@@ -35,6 +35,7 @@ struct oss_ctx {
     int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
     int star_lds = 0;              // OSS_OPT_STAR_LDS
     int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
+    int table_planar = 0;          // OSS_OPT_TABLE_PLANAR
 };
 
 struct oss_ref {

@@ -27,7 +27,8 @@ namespace oss {
 template <typename Tab, int MT>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
-    int64_t pitch_e, int H, int W, const DevBatchPass *__restrict__ passes, int n_passes,
+    int64_t pitch_e, int64_t plane, int H, int W, const DevBatchPass *__restrict__ passes,
+    int n_passes,
     const DevBatchGroup *__restrict__ groups, const DevBatchRadius *__restrict__ radii,
     const DevBatchProbe *__restrict__ probes, uint32_t *__restrict__ bits, StarSweep sw)
 {
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                     continue;
                 if (x >= r && x <= W - 1 - r) {
                     int64_t F[NQ];
-                    star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                    star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
                     bool in = true;
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
@@ -102,15 +103,15 @@ static void batch_launch(const BuildGeom &g, const void *L, const void *R, const
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
     if (bp.max_group <= 8)
         hipLaunchKernelGGL((star_batch_kernel<Tab, 8>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
     else if (bp.max_group <= 16)
         hipLaunchKernelGGL((star_batch_kernel<Tab, 16>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
     else
         hipLaunchKernelGGL((star_batch_kernel<Tab, 32>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
+                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
 }
 
@@ -119,6 +120,15 @@ static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, cons
                           const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
                           hipStream_t st)
 {
+    if (g.planar) {
+        switch (g.nq) {
+        case 1: batch_launch<TabP<T, 1>>(g, L, R, Rp, bp, bits, sw, st); break;
+        case 2: batch_launch<TabP<T, 2>>(g, L, R, Rp, bp, bits, sw, st); break;
+        case 3: batch_launch<TabP<T, 3>>(g, L, R, Rp, bp, bits, sw, st); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (g.nq) {
     case 1: batch_launch<TabU<T, 1>>(g, L, R, Rp, bp, bits, sw, st); break;
     case 2: batch_launch<TabU<T, 2>>(g, L, R, Rp, bp, bits, sw, st); break;

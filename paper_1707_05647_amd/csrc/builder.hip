@@ -31,7 +31,7 @@ namespace oss {
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi)
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
 {
     BuildGeom g;
     g.H = H;
@@ -39,8 +39,17 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi)
     g.nq = nq;
     g.ebytes = ebytes;
     g.sqi = sqi;
-    g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
+    g.planar = (planar && sqi < 0) ? 1 : 0;
     g.pitch_e = ((int64_t)W + 1 + 15) / 16 * 16;
+    if (g.planar) {
+        g.tab_es = ebytes;
+        g.plane = ((int64_t)(H + 1) * g.pitch_e * ebytes + 255) / 256 * 256;
+        g.tab_bytes = g.plane * nq;
+    } else {
+        g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
+        g.plane = 0;
+        g.tab_bytes = (int64_t)(H + 1) * g.pitch_e * g.tab_es;
+    }
     g.nb = cdiv(H + 1, KBAND);
     // final tiles: cores cover [-1, W-1]; the first core starts at -64+HALO <= -1
     g.fin_x0 = -64;
@@ -485,13 +494,19 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__rest
 //   advance:        L += P, T_ad = ta_r + P, T_d = td_l + P
 // The last row is stored after one more barrier.
 // ---------------------------------------------------------------------------
-// Entry e of a table: NQ values of T (MIX < 0), or the 16-byte mixed entry
-// (64-bit squares from slot MIX, the other quantities modulo 2^32) written as
-// one 16-byte store.
+// Entry e of a table: NQ values of T side by side (MIX == -1), one value in
+// each of NQ planes plane_e values apart (MIX == -2), or the 16-byte mixed
+// entry (64-bit squares from slot MIX, the other quantities modulo 2^32)
+// written as one 16-byte store.
 template <typename T, int NQ, int MIX>
-__device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v)
+__device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v,
+                                            int64_t plane_e)
 {
-    if constexpr (MIX < 0) {
+    if constexpr (MIX == -2) {  // planar
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            tab[q * plane_e + e] = v[q];
+    } else if constexpr (MIX < 0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             tab[e * NQ + q] = v[q];
@@ -515,6 +530,7 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     T *__restrict__ tL, T *__restrict__ tR, T *__restrict__ tRp)
 {
     constexpr int NQ = Feat<FM>::NQ;
+    const int64_t plane_e = g.plane / (int64_t)sizeof(T);
     constexpr int NW = BAND_THREADS / 64;
     __shared__ T s_wt[2][NW][NQ];
     __shared__ T s_eta[2][NW][NQ];
@@ -606,9 +622,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
                 r[q] = TA[q] - td_l[q];
                 rp[q] = ta_r[q] - td_l[q];
             }
-            store_entry<T, NQ, MIX>(tL, e, Lc);
-            store_entry<T, NQ, MIX>(tR, e, r);
-            store_entry<T, NQ, MIX>(tRp, e, rp);
+            store_entry<T, NQ, MIX>(tL, e, Lc, plane_e);
+            store_entry<T, NQ, MIX>(tR, e, r, plane_e);
+            store_entry<T, NQ, MIX>(tRp, e, rp, plane_e);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -643,9 +659,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     }
     if (store) {
         const int64_t e = (int64_t)(ys + rows) * g.pitch_e + (x + 1);
-        store_entry<T, NQ, MIX>(tL, e, Lc);
-        store_entry<T, NQ, MIX>(tR, e, r);
-        store_entry<T, NQ, MIX>(tRp, e, rp);
+        store_entry<T, NQ, MIX>(tL, e, Lc, plane_e);
+        store_entry<T, NQ, MIX>(tR, e, r, plane_e);
+        store_entry<T, NQ, MIX>(tRp, e, rp, plane_e);
     }
 }
 
@@ -691,6 +707,18 @@ template <typename Pix, typename T>
 static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint32_t fm,
                             const BuildBuffers &bb, hipStream_t st, Profiler *pr)
 {
+    if (g.planar) {
+        switch (fm) {
+        case 1: return build_t<Pix, 1, T, -2>(g, px, pb, bb, st, pr);
+        case 2: return build_t<Pix, 2, T, -2>(g, px, pb, bb, st, pr);
+        case 3: return build_t<Pix, 3, T, -2>(g, px, pb, bb, st, pr);
+        case 4: return build_t<Pix, 4, T, -2>(g, px, pb, bb, st, pr);
+        case 5: return build_t<Pix, 5, T, -2>(g, px, pb, bb, st, pr);
+        case 6: return build_t<Pix, 6, T, -2>(g, px, pb, bb, st, pr);
+        case 7: return build_t<Pix, 7, T, -2>(g, px, pb, bb, st, pr);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (g.sqi >= 0) {
         // mixed entries: 64-bit accumulation, the squares stored in 64 bits
         switch (fm) {

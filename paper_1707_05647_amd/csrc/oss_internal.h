@@ -44,7 +44,10 @@ struct BuildGeom {
     int H, W, nq;
     int ebytes;        // bytes per accumulated quantity: 4 (mod 2^32) or 8
     int sqi;           // mixed entries: slot of the squares among the quantities, else -1
-    int tab_es;        // bytes per table entry: nq * ebytes, or 16 for mixed entries
+    int planar;        // 1: one plane per quantity (entry stride ebytes)
+    int tab_es;        // entry stride in bytes: nq * ebytes, 16 (mixed) or ebytes (planar)
+    int64_t plane;     // planar: bytes from one quantity's plane to the next, else 0
+    int64_t tab_bytes; // bytes of one table
     int64_t pitch_e;   // table entries per row (>= W+1)
     int nb;            // bands
     int nfin, fin_x0;  // final tiles: first thread column of tile c is fin_x0 + c*BAND_STRIDE
@@ -56,8 +59,9 @@ struct BuildGeom {
 // Table entries hold the nq quantities in feature order, each in ebytes
 // bytes; with sqi >= 0 (ebytes 8) an entry is 16 bytes instead: the squares
 // (quantity slot sqi) as 64 bits, then the other quantities in feature order
-// as 32 bits each (modulo 2^32), zero padded.
-BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1);
+// as 32 bits each (modulo 2^32), zero padded.  planar (sqi < 0 only): each
+// quantity in a plane of its own, planes 256-byte aligned.
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1, int planar = 0);
 
 // ---------------------------------------------------------------------------
 // Screening plan uploaded per call.

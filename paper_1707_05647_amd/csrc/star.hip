@@ -38,7 +38,7 @@ namespace oss {
 template <typename Tab>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
-    int64_t pitch_e, int H, int W, const DevTemplatePlan *__restrict__ plan,
+    int64_t pitch_e, int64_t plane, int H, int W, const DevTemplatePlan *__restrict__ plan,
     uint32_t *__restrict__ bits, StarSweep sw)
 {
     constexpr int NQ = Tab::NQ;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
                 continue;
             if (x >= r && x <= W - 1 - r) {
                 int64_t F[NQ];
-                star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F);
+                star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
                 for (int p = rd.first; p < rd.first + rd.count; ++p) {
                     const DevProbe pr = plan->probes[p];
                     bool pass = true;
@@ -220,7 +220,7 @@ static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, 
                               hipStream_t stream)
 {
     hipLaunchKernelGGL((star_plain_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), 0,
-                       stream, L, R, Rp, g.pitch_e, g.H, g.W, plan, bits, sw);
+                       stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
 }
 
 template <typename T>
@@ -230,6 +230,15 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
+    if (g.planar) {
+        switch (g.nq) {
+        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream); break;
+        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream); break;
+        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (lds) {
         switch (g.nq) {
         case 1: star_lds_launch<T, 1>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;

@@ -33,6 +33,10 @@ struct TabU {
     static constexpr int NQ = NQ_;
     static constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
     using E = Entry<T, NQ>;
+    __device__ static __forceinline__ E load(const char *p, int64_t)
+    {
+        return *reinterpret_cast<const E *>(p);
+    }
     __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
                                                   const E &e, const E &f, const E &h, const E &k,
                                                   int64_t *F)
@@ -54,6 +58,10 @@ struct TabMix {
     static constexpr int NQ = NQ_;
     static constexpr int64_t ES = 16;
     using E = MixEntry;
+    __device__ static __forceinline__ E load(const char *p, int64_t)
+    {
+        return *reinterpret_cast<const E *>(p);
+    }
     __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
                                                   const E &e, const E &f, const E &h, const E &k,
                                                   int64_t *F)
@@ -68,6 +76,30 @@ struct TabMix {
             F[q] = widen((uint32_t)(a.o[j] - b.o[j] - c.o[j] + d.o[j])) +
                    widen((uint32_t)(e.o[j] - f.o[j] - h.o[j] + k.o[j]));
         }
+    }
+};
+
+// Planar tables: quantity q of an entry sits `plane` bytes after quantity
+// q-1; the entry stride is sizeof(T).  A wave's lookup is then NQ loads of
+// 64 consecutive values each instead of one load of 64 interleaved entries.
+template <typename T, int NQ_>
+struct TabP {
+    static constexpr int NQ = NQ_;
+    static constexpr int64_t ES = (int64_t)sizeof(T);
+    using E = Entry<T, NQ>;
+    __device__ static __forceinline__ E load(const char *p, int64_t plane)
+    {
+        E e;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            e.v[q] = *reinterpret_cast<const T *>(p + q * plane);
+        return e;
+    }
+    __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
+                                                  const E &e, const E &f, const E &h, const E &k,
+                                                  int64_t *F)
+    {
+        TabU<T, NQ>::reduce(a, b, c, d, e, f, h, k, F);
     }
 };
 
@@ -86,7 +118,7 @@ __device__ __forceinline__ E entry_at(const char *row, uint32_t lane_off)
 template <typename Tab>
 __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
                                           int64_t row_bytes, uint32_t lane_off, int y, int r,
-                                          int s, int64_t *F)
+                                          int s, int64_t *F, int64_t plane)
 {
     using E = typename Tab::E;
     constexpr int64_t ES = Tab::ES;
@@ -97,14 +129,14 @@ __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const 
     const char *rp_mid = Rpb + (int64_t)y * row_bytes;           // row y-1
     const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
     const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
-    const E a = entry_at<E>(l_bot + ds, lane_off);    // L(x+s,   y+s)
-    const E b = entry_at<E>(l_bot - ds1, lane_off);   // L(x-s-1, y+s)
-    const E c = entry_at<E>(l_top + ds, lane_off);    // L(x+s,   y-s-1)
-    const E d = entry_at<E>(l_top - ds1, lane_off);   // L(x-s-1, y-s-1)
-    const E e = entry_at<E>(r_bot, lane_off);         // R(x, y+r)
-    const E f = entry_at<E>(rp_mid - dr1, lane_off);  // R'(x-r-1, y-1)
-    const E h = entry_at<E>(rp_mid + dr, lane_off);   // R'(x+r, y-1)
-    const E k = entry_at<E>(r_top, lane_off);         // R(x, y-r-1)
+    const E a = Tab::load(l_bot + ds + lane_off, plane);    // L(x+s,   y+s)
+    const E b = Tab::load(l_bot - ds1 + lane_off, plane);   // L(x-s-1, y+s)
+    const E c = Tab::load(l_top + ds + lane_off, plane);    // L(x+s,   y-s-1)
+    const E d = Tab::load(l_top - ds1 + lane_off, plane);   // L(x-s-1, y-s-1)
+    const E e = Tab::load(r_bot + lane_off, plane);         // R(x, y+r)
+    const E f = Tab::load(rp_mid - dr1 + lane_off, plane);  // R'(x-r-1, y-1)
+    const E h = Tab::load(rp_mid + dr + lane_off, plane);   // R'(x+r, y-1)
+    const E k = Tab::load(r_top + lane_off, plane);         // R(x, y-r-1)
     Tab::reduce(a, b, c, d, e, f, h, k, F);
 }
 

@@ -64,17 +64,22 @@ class Reference:
         2^32, zero-extended; 64 = exact); synchronous; for tests and
         inspection."""
         Lp, Rp_, Rpp, pitch, nq, vb, _ = L.oss_ref_tables(self.handle)
-        eb = self.entry_bytes
+        es = self.entry_bytes  # entry stride
+        H1 = self.H + 1
+        n = H1 * pitch
+        # bytes the table spans on the device, and a host buffer that also
+        # holds the reshaped views' unused tails
+        used = max(off + (n - 1) * es + bits // 8 for off, bits in self.slots)
+        span = max(off for off, _ in self.slots) + n * es
         out = []
         for p in (Lp, Rp_, Rpp):
-            raw = np.empty((self.H + 1, pitch, eb), np.uint8)
-            _hip_memcpy_d2h(raw, p)
-            raw = raw[:, :self.W + 1, :]
-            t = np.empty((self.H + 1, self.W + 1, nq), np.int64)
+            raw = np.zeros(span, np.uint8)
+            _hip_memcpy_d2h(raw[:used], p)
+            t = np.empty((H1, self.W + 1, nq), np.int64)
             for q, (off, bits) in enumerate(self.slots):
                 nb = bits // 8
-                v = np.ascontiguousarray(raw[:, :, off:off + nb]).view(
-                    np.uint32 if nb == 4 else np.int64)[..., 0]
+                v = raw[off:off + n * es].reshape(H1, pitch, es)[:, :self.W + 1, :nb]
+                v = np.ascontiguousarray(v).view(np.uint32 if nb == 4 else np.int64)[..., 0]
                 t[..., q] = v.astype(np.int64)
             out.append(t)
         return out

@@ -36,8 +36,9 @@ TABLE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("planar", [0, 1], ids=["interleaved", "planar"])
 @pytest.mark.parametrize("case", TABLE_CASES, ids=lambda c: "x".join(map(str, c)))
-def test_tables_match_definitions(runner, case):
+def test_tables_match_definitions(runner, case, planar):
     H, W, depth, fm, pad, max_r = case
     rng = np.random.default_rng(H * 1000 + W)
     dt = np.uint8 if depth == 8 else np.uint16
@@ -50,8 +51,15 @@ def test_tables_match_definitions(runner, case):
         t_img = runner.L.device_image(wide, runner.dev)[:, :W]
     else:
         t_img = runner.L.device_image(img, runner.dev)
-    ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
+    L = runner.L
+    L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, planar)
+    try:
+        ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
+    finally:
+        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 0)
     torch.cuda.synchronize()
+    if planar and ref.value_bits == 32:
+        assert ref.entry_bytes == 4 and len(ref.slots) == bin(fm).count("1")
     got = ref.tables_host()
     slots = ref.slots
     ref.release()
@@ -245,3 +253,38 @@ def test_cfg2_full_size_sampled(runner):
     assert np.array_equal(bits[0, ys, xs], want[0])
     # the planted template survives at its true radius (32 = scale id 2)
     assert bits[0, t.cy, t.cx] & (1 << 2)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_planar_tables_same_results(runner, cfg):
+    """Planar 32-bit tables (one plane per quantity): plain and batched
+    screens equal the oracle (workload 3 keeps its probes of radius <= 40,
+    where squares of 8-bit pixels still fit 32 bits)."""
+    kw = {1: {},
+          2: dict(H=230, W=270, blobs_per_512sq=800, sig_hi=24),
+          3: dict(H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20)}[cfg]
+    w = make_workload(cfg, 1, **kw)
+    if cfg == 3:
+        w.probes = [p for p in w.probes if p[2] <= 40]
+    max_r = max(p[2] for p in w.probes)
+    L = runner.L
+    L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
+    try:
+        _screen_and_compare(runner, w, max_r)
+        assert runner.last_entry_bytes == 4
+        img = L.device_image(w.ref, runner.dev)
+        ref = runner.ctx.reference(img, w.feat_mask, w.depth, max_radius=max_r)
+        tm = [L.oss_template_features(t.pixels, t.rho, w.feat_mask, bit_depth=w.depth)
+              for t in w.templates]
+        res = runner.ctx.screen(ref, tm, w.probes, (*w.tol_P, w.tol_Q), w.feat_mask,
+                                list_cap=len(tm) * w.H * w.W, batched=True)
+        runner.torch.cuda.synchronize()
+        got = res.host()
+        ref.release()
+    finally:
+        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 0)
+    want = oc.screen_full(w.ref, [(t.pixels, t.rho) for t in w.templates], w.probes,
+                          w.feat_mask, w.tol_P, w.tol_Q)
+    wmask, wlist = oc.mask_and_list(want)
+    assert got[2] == len(wlist) and np.array_equal(got[0], wmask)
+    assert np.array_equal(got[1], wlist)
