@@ -62,6 +62,10 @@ def _declare(lib):
     lib.oracle_screen.argtypes = [u16p, i32p, C.c_int, C.c_int, C.c_int64, i32p, i32p, C.c_int64,
                                   i32p, C.c_int, i64p, i32p, C.c_int, C.c_int, i32p, C.c_int, u32p]
     lib.oracle_screen.restype = C.c_int
+    lib.oracle_screen_rings.argtypes = [u16p, i32p, C.c_int, C.c_int, C.c_int64, i32p, i32p,
+                                        C.c_int64, i32p, C.c_int, i64p, i32p, C.c_int, C.c_int,
+                                        C.c_int, i32p, C.c_int, u32p]
+    lib.oracle_screen_rings.restype = C.c_int
     return lib
 
 
@@ -180,6 +184,61 @@ def screen_full(img, templates, probes, feat_mask: int, P, Q: int, lib=None) -> 
     ys, xs = np.meshgrid(np.arange(H, dtype=np.int32), np.arange(W, dtype=np.int32),
                          indexing="ij")
     bits = screen_positions(a, templates, probes, feat_mask, P, Q, xs.ravel(), ys.ravel(), lib)
+    return bits.reshape(len(templates), H, W)
+
+
+def ring_radii(r: int, n_rings: int, lib=None) -> list:
+    """r, s(r), s(s(r)), ...: the radii of the n_rings concentric central
+    stars, each a factor sqrt 2 smaller (rounded as the square half-width)."""
+    out = [int(r)]
+    for _ in range(n_rings - 1):
+        out.append(square_half(out[-1], lib))
+    return out
+
+
+def template_ring_features(tmpl, rho: int, n_rings: int, lib=None):
+    """([n_rings][3] features, [n_rings] radii) of the template's central
+    stars of radii rho, s(rho), s(s(rho)), ..."""
+    radii = ring_radii(rho, n_rings, lib)
+    return np.stack([template_features(tmpl, rj, lib) for rj in radii]), radii
+
+
+def screen_rings_positions(img, templates, probes, feat_mask: int, P, Q: int, n_rings: int,
+                           xs, ys, lib=None, G=None) -> np.ndarray:
+    """bits[n_tmpl, n] of the multi-central-area screen: probe (t, k, r)
+    passes where the stars of radii r, s(r), ... all match the template's
+    central stars of radii rho, s(rho), ...  (n_rings of them)."""
+    lib = lib or load()
+    a = _img16(img)
+    H, W = a.shape
+    if G is None:
+        G = gradient(a, lib)
+    FT = np.zeros((len(templates), n_rings, 3), np.int64)
+    rho = np.zeros((len(templates), n_rings), np.int32)
+    for t, (px, r0) in enumerate(templates):
+        FT[t], rho[t] = template_ring_features(px, r0, n_rings, lib)
+    parr = np.ascontiguousarray(np.array(sorted(probes), np.int32).reshape(-1, 3))
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    bits = np.zeros((len(templates), len(xs)), np.uint32)
+    Pa = np.ascontiguousarray(list(P) + [0] * (3 - len(P)), np.int32)
+    rc = lib.oracle_screen_rings(a, np.ascontiguousarray(G, np.int32), H, W, W, xs, ys, len(xs),
+                                 parr, len(parr), np.ascontiguousarray(FT), rho, len(templates),
+                                 int(n_rings), int(feat_mask), Pa, int(Q), bits)
+    if rc != 0:
+        raise ValueError("oracle_screen_rings rejected its arguments")
+    return bits
+
+
+def screen_rings_full(img, templates, probes, feat_mask: int, P, Q: int, n_rings: int,
+                      lib=None) -> np.ndarray:
+    """bits[n_tmpl, H, W] of the multi-central-area screen."""
+    a = _img16(img)
+    H, W = a.shape
+    ys, xs = np.meshgrid(np.arange(H, dtype=np.int32), np.arange(W, dtype=np.int32),
+                         indexing="ij")
+    bits = screen_rings_positions(a, templates, probes, feat_mask, P, Q, n_rings, xs.ravel(),
+                                  ys.ravel(), lib)
     return bits.reshape(len(templates), H, W)
 
 

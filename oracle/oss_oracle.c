@@ -228,3 +228,60 @@ int oracle_screen(const uint16_t *img, const int32_t *G, int H, int W, int64_t s
     free(area_rho);
     return 0;
 }
+
+/*
+ * Multi-central-area screen (Sec. "Scale Invariance", the paragraph on
+ * central areas of different sizes and Fig. ring): besides the star of the
+ * probe's radius r, the concentric central stars of radii r_1 = s(r) and
+ * r_{j+1} = s(r_j) (s(r) = round(r / sqrt 2): each ring a factor lambda =
+ * sqrt 2 smaller) must match the template's central stars of radii
+ * rho_j, and the probe passes only if every one of the n_rings areas
+ * passes every enabled feature test.
+ *   FT:  [n_tmpl][n_rings][3] template features of ring j at radius rho_j
+ *   rho: [n_tmpl][n_rings] template ring radii rho_j
+ * n_rings = 1 is oracle_screen.  A probe needs the outer star (radius r)
+ * to fit; the inner ones then fit too.
+ */
+int oracle_screen_rings(const uint16_t *img, const int32_t *G, int H, int W, int64_t stride,
+                        const int32_t *xs, const int32_t *ys, int64_t n,
+                        const int32_t *probes, int n_probes, const int64_t *FT,
+                        const int32_t *rho, int n_tmpl, int n_rings, int feat_mask,
+                        const int32_t *P, int Q, uint32_t *bits)
+{
+    if (Q <= 0 || n_rings < 1 || n_rings > 8)
+        return -1;
+    for (int p = 0; p < n_probes; p++) {
+        int t = probes[3 * p], k = probes[3 * p + 1], r = probes[3 * p + 2];
+        if (t < 0 || t >= n_tmpl || k < 0 || k > 31 || r < 0)
+            return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        for (int t = 0; t < n_tmpl; t++)
+            bits[(int64_t)t * n + i] = 0;
+        for (int p = 0; p < n_probes; p++) {
+            int t = probes[3 * p], k = probes[3 * p + 1], r = probes[3 * p + 2];
+            int pass = 1;
+            int rj = r;
+            for (int j = 0; j < n_rings && pass; j++) {
+                int64_t F[3];
+                if (star_at(img, G, H, W, stride, xs[i], ys[i], rj, F) != 0) {
+                    pass = 0;
+                    break;
+                }
+                int rho_j = rho[t * n_rings + j];
+                const int64_t *ft = FT + 3 * ((int64_t)t * n_rings + j);
+                for (int f = 0; f < 3 && pass; f++) {
+                    if (!(feat_mask & (1 << f)))
+                        continue;
+                    pass = feature_pass(f, F[f], ft[f], rj, rho_j, oracle_star_area(rj),
+                                        oracle_star_area(rho_j), P[f], Q);
+                }
+                rj = oracle_square_half(rj);
+            }
+            if (pass)
+                bits[(int64_t)t * n + i] |= 1u << k;
+        }
+    }
+    return 0;
+}

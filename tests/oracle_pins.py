@@ -197,5 +197,98 @@ def check_planted_exact(lib):
     assert bits[0, 0] == 0
 
 
+def _py_pass(f, F, FT, r, rho, P, Q):
+    """The feature test in Python integers, with the weighted areas from the
+    enumerator's pixel sets (an implementation independent of the oracle)."""
+    def area(rr):
+        return len(en.square_pixels(rr)) + len(en.diamond_pixels(rr))
+    c_ref, c_t = (r, rho) if f == 2 else (1, 1)
+    x_ref = F * area(rho) * c_ref
+    x_t = FT * area(r) * c_t
+    return (Q - P) * x_t <= Q * x_ref <= (Q + P) * x_t
+
+
+def _ring_chain(r, n):
+    out = [r]
+    for _ in range(n - 1):
+        out.append(en.nearest_half_width(out[-1]))
+    return out
+
+
+def check_rings_brute_force(lib):
+    """Multi-central-area screen (Sec. "Scale Invariance", central areas of
+    sizes n, n/lambda, n/lambda^2 with lambda = sqrt 2): at every position of
+    a small image, probe (t, k, r) passes iff for every ring j the star of
+    radius r_j (r_0 = r, r_{j+1} = round(r_j / sqrt 2)) matches the
+    template's central star of radius rho_j the same way; enumerated in
+    Python from the star's pixel sets."""
+    img = _rand_img((21, 24), 31)
+    rng = np.random.default_rng(32)
+    templates = []
+    for rho in (5, 4):
+        cx, cy = int(rng.integers(rho + 1, 24 - rho - 1)), int(rng.integers(rho + 1, 21 - rho - 1))
+        tm = img[cy - rho - 1:cy + rho + 2, cx - rho - 1:cx + rho + 2].copy()
+        tm = np.clip(tm.astype(np.int64) + rng.integers(-6, 7, tm.shape), 0, 255).astype(np.uint8)
+        templates.append((tm, rho))
+    probes = [(0, 0, 4), (0, 1, 5), (0, 2, 6), (1, 0, 3), (1, 3, 4)]
+    P, Q = (25, 45, 60), 100
+    ys, xs = np.mgrid[0:21, 0:24]
+    rows = img.tolist()
+    seen = set()
+    for n_rings in (1, 2, 3):
+        got = oc.screen_rings_positions(img, templates, probes, 7, P, Q, n_rings, xs.ravel(),
+                                        ys.ravel(), lib)
+        for t, (tm, rho) in enumerate(templates):
+            trows = tm.tolist()
+            c = ((tm.shape[1] - 1) // 2, (tm.shape[0] - 1) // 2)
+            rho_c = _ring_chain(rho, n_rings)
+            FT = [en.star_features(trows, c[0], c[1], rj) for rj in rho_c]
+            for i, (x, y) in enumerate(zip(xs.ravel(), ys.ravel())):
+                want = 0
+                for tt, k, r in probes:
+                    if tt != t:
+                        continue
+                    ok = True
+                    for j, rj in enumerate(_ring_chain(r, n_rings)):
+                        F = en.star_features(rows, int(x), int(y), rj)
+                        if F is None:
+                            ok = False
+                            break
+                        ok = all(_py_pass(f, F[f], FT[j][f], rj, rho_c[j], P[f], Q)
+                                 for f in range(3))
+                        if not ok:
+                            break
+                    want |= (1 << k) if ok else 0
+                assert int(got[t, i]) == want, (n_rings, t, x, y, int(got[t, i]), want)
+                seen.add(want != 0)
+    assert seen == {True, False}  # the case mixes passing and failing positions
+
+
+def check_rings_consistency(lib):
+    """One ring is the plain screen; more rings never add candidates; an
+    exact cut survives at its centre at P = 0 with every ring."""
+    from synth import blob_image, make_rng, cut_patch
+    img = blob_image(80, 90, make_rng(98, 0), blobs_per_512sq=1500, sig_hi=10)
+    cx, cy, rho = 44, 37, 10
+    tm = cut_patch(img, cx, cy, rho + 1)
+    tms = [(tm, rho)]
+    probes = [(0, 0, 8), (0, 1, 10), (0, 2, 13)]
+    P, Q = (8, 12, 40), 100
+    plain = oc.screen_full(img, tms, probes, 7, P, Q, lib)
+    prev = None
+    for n_rings in (1, 2, 3, 4):
+        b = oc.screen_rings_full(img, tms, probes, 7, P, Q, n_rings, lib)
+        if n_rings == 1:
+            assert np.array_equal(b, plain)
+        else:
+            assert not (b & ~prev).any()
+        prev = b
+        exact = oc.screen_rings_positions(img, tms, [(0, 0, rho)], 7, (0, 0, 0), 1, n_rings,
+                                          [cx], [cy], lib)
+        assert exact[0, 0] == 1, n_rings
+    assert (prev != plain).any()  # the rings do prune
+
+
 ALL_CHECKS = [check_half_width_and_area, check_golden_7x7, check_enumerator, check_correlate,
-              check_closed_forms, check_d4, check_compare, check_planted_exact]
+              check_closed_forms, check_d4, check_compare, check_planted_exact,
+              check_rings_brute_force, check_rings_consistency]
