@@ -58,17 +58,22 @@ def pixel_scales(H, W, probes):
     return sum(max(0, H - 2 * r) * max(0, W - 2 * r) for _, _, r in probes)
 
 
-def lookup_pairs(w, batched=False, group=32):
+def lookup_pairs(w, batched=False, group=32, rings=1):
     """Valid (position, radius) pairs whose star sums a launch evaluates, each
     8 table lookups per quantity: one per (template, distinct radius) for
     per-template launches; one per (template group, distinct radius) for the
     batched launch (templates sorted by radius, groups of 32)."""
+    def chain(r):
+        out = [r]
+        for _ in range(rings - 1):  # central-star radii s(r), s(s(r)), ...
+            out.append((math.isqrt(2 * out[-1] ** 2) + 1) // 2 if out[-1] else 0)
+        return out
     if batched:
         order = sorted(range(len(w.templates)), key=lambda t: w.templates[t].rho)
         gid = {t: i // group for i, t in enumerate(order)}
-        pairs = set((gid[t], r) for t, _, r in w.probes)
+        pairs = set((gid[t], rj) for t, _, r in w.probes for rj in chain(r))
     else:
-        pairs = set((t, r) for t, _, r in w.probes)
+        pairs = set((t, rj) for t, _, r in w.probes for rj in chain(r))
     return sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, r in pairs)
 
 
@@ -110,7 +115,7 @@ def traffic_for(kernel: str):
 
 
 def cpu_baseline(w, bits_gpu, seconds: float, seed: int = 1, gpu_bits=None, gpu_mask=None,
-                 list_complete=True):
+                 list_complete=True, rings=1):
     """The oracle as it stands, on a random sample of positions of the same
     workload, timed; and the GPU's scale bits (and mask) at those positions
     compared with the oracle's."""
@@ -133,15 +138,22 @@ def cpu_baseline(w, bits_gpu, seconds: float, seed: int = 1, gpu_bits=None, gpu_
             tot += int(((xs >= r) & (xs <= w.W - 1 - r) & (ys >= r) & (ys <= w.H - 1 - r)).sum())
         return tot
 
+    def screen(xs, ys):
+        if rings > 1:
+            return oc.screen_rings_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q,
+                                             rings, xs, ys, G=G)
+        return oc.screen_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q, xs, ys,
+                                   G=G)
+
     n0 = 512 if len(w.probes) > 50 else 4096
     xs, ys = sample(n0)
     t0 = time.perf_counter()
-    oc.screen_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q, xs, ys, G=G)
+    screen(xs, ys)
     dt = max(time.perf_counter() - t0, 1e-4)
     n = int(max(n0, min(8_000_000, n0 * seconds / dt)))
     xs, ys = sample(n)
     t0 = time.perf_counter()
-    bits = oc.screen_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q, xs, ys, G=G)
+    bits = screen(xs, ys)
     dt = time.perf_counter() - t0
     pairs = valid_pairs(xs, ys)
     if gpu_bits is None:
@@ -191,7 +203,7 @@ def run_steps(step, steps, warmup, ctx, L, torch):
     return (t1 - t0) / steps, L.oss_ctx_profile_read(ctx.handle)
 
 
-def sampled_check(w, cands, n, cap, mask_dev, seconds):
+def sampled_check(w, cands, n, cap, mask_dev, seconds, rings=1):
     """CPU baseline on a random sample plus the GPU/oracle comparison there,
     from the sorted candidate list (scale bits) and the mask."""
     import numpy as np
@@ -226,7 +238,7 @@ def sampled_check(w, cands, n, cap, mask_dev, seconds):
         return mask_dev[:, yt, xt].cpu().numpy()
 
     return cpu_baseline(w, None, seconds, gpu_bits=gpu_bits, gpu_mask=gpu_mask,
-                        list_complete=n <= cap)
+                        list_complete=n <= cap, rings=rings)
 
 
 SERVE_TOL = (4, 8, 65, 100)
@@ -414,6 +426,8 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: the headline rotation+scale screen; 3, 5: batched workloads "
                          "(batched launch against per-template launches); 4: serving loop")
+    ap.add_argument("--rings", type=int, default=1,
+                    help="central-star rings per probe (multi-central-area screen); 1 = off")
     ap.add_argument("--requests", type=int, default=100, help="workload 4: requests")
     ap.add_argument("--lanes", type=int, default=2, help="workload 4: server lanes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -475,13 +489,23 @@ def main():
         return [L.oss_template_features(t.pixels, t.rho, w.feat_mask, bit_depth=w.depth)
                 for t in w.templates]
 
+    def tfeat_rings():
+        return [L.oss_template_features_rings(t.pixels, t.rho, w.feat_mask, args.rings,
+                                              bit_depth=w.depth) for t in w.templates]
+
     def make_step(batched):
         def step():
             tm = tfeat()
             ref.build(stream)
             L.oss_screen(ctx.handle, ref.handle, tm, w.probes, tol, w.feat_mask, mask, cands, cap,
                          count, stream, batched=batched)
-        return step
+
+        def step_rings():
+            tm = tfeat_rings()
+            ref.build(stream)
+            L.oss_screen_rings(ctx.handle, ref.handle, tm, w.probes, tol, w.feat_mask, mask,
+                               cands, cap, count, stream)
+        return step_rings if args.rings > 1 else step
 
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
@@ -506,7 +530,8 @@ def main():
                                         torch)
         extra["plain_ms_per_step"] = plain_s * 1e3
         extra["plain_kernels"] = {k: v[1] / max(v[0], 1) for k, v in plain_prof.items()}
-    sec, prof = run_steps(make_step(big), args.steps, args.warmup, ctx, L, torch)
+    sec, prof = run_steps(make_step(big or args.rings > 1), args.steps, args.warmup, ctx, L,
+                          torch)
 
     ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
@@ -532,7 +557,7 @@ def main():
     }
     if dom in ("star_plain", "star_batch"):
         # the same launch against the vector-memory path that actually bounds it
-        lookups = lookup_pairs(w, dom == "star_batch") * 8 * eb
+        lookups = lookup_pairs(w, dom == "star_batch", rings=args.rings) * 8 * eb
         roof["vector_l1"] = {"achieved": lookups / avg_s / 1e9, "peak": L1_PEAK_GBPS,
                              "unit": "GB/s", "frac": lookups / avg_s / 1e9 / L1_PEAK_GBPS,
                              "lookup_bytes_per_launch": lookups}
@@ -568,7 +593,8 @@ def main():
             "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
             "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
-            "launch": "batched" if big else "plain",
+            "launch": "batched" if (big or args.rings > 1) else "plain",
+            "rings": args.rings,
         },
         "roofline": roof,
         "kernels": kern,
@@ -577,7 +603,7 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds)
+        out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds, args.rings)
     ref.release()
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -287,6 +287,37 @@ int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat
                        oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
                        void *stream);
 
+/* ------------------------------------------------------------------------
+ * Multi-central-area screen (Sec. "Scale Invariance", central areas of
+ * sizes n, n/lambda, n/lambda^2 with lambda = sqrt 2, Fig. ring): a probe
+ * (t, k, r) passes where its star of radius r passes and so do the
+ * concentric central stars of radii r_1 = s(r), r_2 = s(r_1), ... (s(r) =
+ * round(r / sqrt 2), the square half-width above), each compared with the
+ * template's central star of the matching ring by the same feature test.
+ * ------------------------------------------------------------------------ */
+#define OSS_MAX_RINGS 4
+
+/* Features of the template's central stars of radii rho, s(rho), ...
+ * (n_rings of them, 1..OSS_MAX_RINGS) into out[0..n_rings-1]; rho < 0
+ * picks the default radius as oss_template_features does.  Host-side,
+ * synchronous. */
+int oss_template_features_rings(const void *host_pixels, const oss_image_desc *desc,
+                                int32_t rho, uint32_t feat_mask, int32_t n_rings,
+                                oss_template_feat *out);
+
+/* Screen with n_rings central stars per probe.  tmpl is [n_tmpl][n_rings]:
+ * tmpl[t * n_rings + j] holds template t's ring-j features and radius (as
+ * from oss_template_features_rings).  Ring j of probe (t, k, r) compares the
+ * reference star of radius r_j with tmpl[t * n_rings + j].  Other arguments,
+ * outputs and errors as oss_screen_batched (one pass per template group:
+ * OSS_OPT_BATCH_BUCKET does not apply).  n_rings = 1 gives oss_screen's
+ * results. */
+int oss_screen_rings(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                     int32_t n_tmpl, int32_t n_rings, const oss_probe *probes, int32_t n_probes,
+                     const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                     oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                     void *stream);
+
 #define OSS_TUNE_MAX 64
 /* Autotuner result: the chosen shape, its time, and every candidate tried
  * (strip, blocks per XCD, bucket) with its time in ms. */

@@ -25,11 +25,12 @@ EXPORTED = [
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
-    "oss_ref_layout", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
+    "oss_ref_layout", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_OPT_TABLE_PLANAR = 5
+OSS_MAX_RINGS = 4
 OSS_TUNE_MAX = 64
 
 
@@ -138,6 +139,11 @@ def load(path: str | None = None):
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
     lib.oss_screen_batched.argtypes = lib.oss_screen.argtypes
+    lib.oss_template_features_rings.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32, i32,
+                                                C.POINTER(oss_template_feat)]
+    lib.oss_screen_rings.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, i32,
+                                     C.POINTER(oss_probe), i32, C.POINTER(oss_tolerance), u32, vp,
+                                     vp, i64, vp, vp]
     lib.oss_autotune_batched.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32,
                                          C.POINTER(oss_probe), i32, C.POINTER(oss_tolerance), u32,
                                          vp, C.POINTER(oss_tune_result)]
@@ -405,3 +411,32 @@ def oss_server_stats_read(srv: int) -> dict:
     out = oss_server_stats()
     _check(load().oss_server_stats_read(srv, C.byref(out)), "oss_server_stats_read")
     return {n: getattr(out, n) for n, _ in oss_server_stats._fields_}
+
+
+# --- multi-central-area screen -------------------------------------------------
+
+def oss_template_features_rings(pixels, rho: int, feat_mask: int, n_rings: int,
+                                bit_depth: int | None = None) -> list:
+    a = np.ascontiguousarray(pixels)
+    d = desc_of(a, bit_depth)
+    out = (oss_template_feat * n_rings)()
+    _check(load().oss_template_features_rings(a.ctypes.data, C.byref(d), int(rho),
+                                              int(feat_mask), int(n_rings), out),
+           "oss_template_features_rings")
+    return list(out)
+
+
+def oss_screen_rings(ctx: int, ref: int, tmpl_rings, probes, tol, feat_mask: int, mask=None,
+                     cand_list=None, list_cap: int = 0, count=None, stream=None):
+    """tmpl_rings: one list of n_rings oss_template_feat per template (as from
+    oss_template_features_rings)."""
+    n_rings = len(tmpl_rings[0])
+    if any(len(r) != n_rings for r in tmpl_rings):
+        raise ValueError("every template needs the same number of rings")
+    flat = [f for rings in tmpl_rings for f in rings]
+    ta, _, pa, npb, tl = _screen_args(flat, probes, tol)
+    if count is None:
+        raise ValueError("count tensor required")
+    _check(load().oss_screen_rings(ctx, ref, ta, len(tmpl_rings), n_rings, pa, npb, C.byref(tl),
+                                   int(feat_mask), _ptr(mask), _ptr(cand_list), int(list_cap),
+                                   _ptr(count), _stream(stream)), "oss_screen_rings")

@@ -400,6 +400,19 @@ int oss_template_features(const void *host_pixels, const oss_image_desc *desc, i
     return OSS_OK;
 }
 
+int oss_template_features_rings(const void *host_pixels, const oss_image_desc *desc,
+                                int32_t rho, uint32_t feat_mask, int32_t n_rings,
+                                oss_template_feat *out)
+{
+    if (!out || n_rings < 1 || n_rings > MAX_RINGS)
+        return OSS_E_ARG;
+    int rc = oss_template_features(host_pixels, desc, rho, feat_mask, &out[0]);
+    for (int j = 1; j < n_rings && rc == OSS_OK; ++j)
+        rc = oss_template_features(host_pixels, desc, square_half(out[j - 1].rho), feat_mask,
+                                   &out[j]);
+    return rc;
+}
+
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
 {
     if (!ctx)
@@ -694,8 +707,13 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
 // radii (0: all) becomes one pass.
 int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
                          const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
-                         const uint32_t *fms, int bucket, BatchHostPlan &bp)
+                         const uint32_t *fms, int bucket, BatchHostPlan &bp, int n_rings)
 {
+    if (n_rings < 1 || n_rings > MAX_RINGS)
+        return OSS_E_ARG;
+    bp.rings = n_rings;
+    if (n_rings > 1)
+        bucket = 0;  // the ring tests of a probe combine in registers: one pass
     std::vector<std::vector<oss_probe>> per(n_tmpl);
     for (int i = 0; i < n_probes; ++i) {
         const oss_probe &p = probes[i];
@@ -712,22 +730,28 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
     std::vector<int> order(n_tmpl);
     for (int t = 0; t < n_tmpl; ++t)
         order[t] = t;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return tmpl[a].rho < tmpl[b].rho; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return tmpl[(int64_t)a * n_rings].rho < tmpl[(int64_t)b * n_rings].rho;
+    });
     for (int g0 = 0; g0 < n_tmpl; g0 += BATCH_GROUP) {
         const int nt = std::min(BATCH_GROUP, n_tmpl - g0);
         DevBatchGroup grp{};
         grp.n_t = nt;
         struct Item {
-            int r, slot;
+            int r, slot, ring;
             oss_probe p;
         };
         std::vector<Item> items;
         for (int i = 0; i < nt; ++i) {
             const int t = order[g0 + i];
             grp.tmap[i] = t;
-            for (const oss_probe &p : per[t])
-                items.push_back({p.r, i, p});
+            for (const oss_probe &p : per[t]) {
+                int rj = p.r;
+                for (int j = 0; j < n_rings; ++j) {
+                    items.push_back({rj, i, j, p});
+                    rj = square_half(rj);
+                }
+            }
         }
         std::stable_sort(items.begin(), items.end(),
                          [](const Item &a, const Item &b) { return a.r < b.r; });
@@ -753,12 +777,13 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
             DevBatchProbe dp{};
             dp.t = it.slot;
             dp.k = it.p.scale_id;
+            dp.ring = it.ring;
             for (int q = 0; q < 3; ++q) {
                 dp.lo[q] = INT64_MIN;
                 dp.hi[q] = INT64_MAX;
             }
             const int tt = grp.tmap[it.slot];
-            const oss_template_feat &tf = tmpl[tt];
+            const oss_template_feat &tf = tmpl[(int64_t)tt * n_rings + it.ring];
             const oss_tolerance &tol = tols[tt];
             for (int f = 0; f < 3; ++f) {
                 if (!(fms[tt] & (1u << f)))
@@ -767,8 +792,10 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
                                &dp.hi[slot_of[f]]);
             }
             for (int q = 0; q < 3; ++q) {
-                cur.lo[q] = std::min(cur.lo[q], dp.lo[q]);
-                cur.hi[q] = std::max(cur.hi[q], dp.hi[q]);
+                // a central-star test must run (and may fail) wherever the
+                // radius is evaluated: no hull skip at radii that carry one
+                cur.lo[q] = std::min(cur.lo[q], it.ring ? INT64_MIN : dp.lo[q]);
+                cur.hi[q] = std::max(cur.hi[q], it.ring ? INT64_MAX : dp.hi[q]);
             }
             bp.probes.push_back(dp);
         }
@@ -809,6 +836,7 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t 
     dev->radii = reinterpret_cast<const DevBatchRadius *>(d + o_rad);
     dev->probes = reinterpret_cast<const DevBatchProbe *>(d + o_prb);
     dev->max_group = bp.max_group;
+    dev->rings = bp.rings;
     return OSS_OK;
 }
 
@@ -844,6 +872,57 @@ extern "C" int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref,
     BatchHostPlan bp;
     rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tols.data(), fms.data(),
                          ctx->batch_bucket, bp);
+    if (rc != OSS_OK)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
+    rc = screen_workspace(ctx, n);
+    if (rc != OSS_OK)
+        return rc;
+    PlanSlot *slot = nullptr;
+    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
+                       ctx->cws, st, &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
+    return OSS_OK;
+}
+
+extern "C" int oss_screen_rings(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                                int32_t n_tmpl, int32_t n_rings, const oss_probe *probes,
+                                int32_t n_probes, const oss_tolerance *tol, uint32_t feat_mask,
+                                uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
+                                int64_t *dev_count, void *stream)
+{
+    if (n_rings < 1 || n_rings > MAX_RINGS || n_tmpl <= 0 || !tmpl)
+        return OSS_E_ARG;
+    // the outer template features are checked like oss_screen's, the rings
+    // for their feature set and radius
+    std::vector<oss_template_feat> outer(n_tmpl);
+    for (int t = 0; t < n_tmpl; ++t) {
+        outer[t] = tmpl[(int64_t)t * n_rings];
+        for (int j = 1; j < n_rings; ++j) {
+            const oss_template_feat &f = tmpl[(int64_t)t * n_rings + j];
+            if ((f.feat_mask & feat_mask) != feat_mask || f.rho < 0)
+                return OSS_E_ARG;
+        }
+    }
+    int rc = check_screen_args(ctx, ref, outer.data(), n_tmpl, probes, n_probes, tol, feat_mask,
+                               list_cap, dev_list, dev_count);
+    if (rc != OSS_OK)
+        return rc;
+    const std::vector<oss_tolerance> tols(n_tmpl, *tol);
+    const std::vector<uint32_t> fms(n_tmpl, feat_mask);
+    BatchHostPlan bp;
+    rc = make_batch_plan(ref, tmpl, n_tmpl, probes, n_probes, tols.data(), fms.data(),
+                         ctx->batch_bucket, bp, n_rings);
     if (rc != OSS_OK)
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)

@@ -60,13 +60,17 @@ struct BatchHostPlan {
     std::vector<DevBatchRadius> radii;
     std::vector<DevBatchProbe> probes;
     int max_group = 0;
+    int rings = 1;
 };
 
 // Tolerance and feature set per template (tols[t], fms[t]); every fms[t]
-// must be a subset of the reference's quantities.
+// must be a subset of the reference's quantities.  With n_rings > 1,
+// tmpl is [n_tmpl][n_rings] (ring j of template t at tmpl[t * n_rings + j])
+// and every probe is also tested at its central radii s(r), s(s(r)), ...
+// against the template's rings; the plan then has one pass per group.
 int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
                     const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
-                    const uint32_t *fms, int bucket, BatchHostPlan &bp);
+                    const uint32_t *fms, int bucket, BatchHostPlan &bp, int n_rings = 1);
 
 // Upload the plan and launch the batched star pass into ctx->bits on `st`;
 // *slot is the plan slot to mark used once an event follows the launch.

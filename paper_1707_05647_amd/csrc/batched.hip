@@ -1,6 +1,9 @@
 // Batched screen: every probe of every template in one persistent launch
 // over one reference's tables (Algorithm 1's patch loop for all templates
-// and scales at once).
+// and scales at once).  With central-star rings (Sec. "Scale Invariance",
+// central areas of sizes n, n/lambda, n/lambda^2) each probe also has
+// entries at its central radii; a probe's bit survives where its own star
+// passes and none of its central stars fails.
 //
 // Templates are sorted by radius and cut into groups of at most
 // BATCH_GROUP; within a group the probes are grouped by reference radius, so
@@ -24,7 +27,7 @@
 
 namespace oss {
 
-template <typename Tab, int MT>
+template <typename Tab, int MT, bool RINGS>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
     int64_t pitch_e, int64_t plane, int H, int W, const DevBatchPass *__restrict__ passes,
@@ -53,10 +56,14 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
             const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
             const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
             const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
-            uint32_t acc[MT];
+            uint32_t acc[MT];            // scale bits whose own star passes
+            uint32_t fail[RINGS ? MT : 1];  // scale bits a central star fails
 #pragma unroll
-            for (int t = 0; t < MT; ++t)
+            for (int t = 0; t < MT; ++t) {
                 acc[t] = 0;
+                if constexpr (RINGS)
+                    fail[t] = 0;
+            }
             for (int jr = ps.j0; jr < ps.j1; ++jr) {
                 const DevBatchRadius &rd = radii[jr];
                 const int r = rd.r, s = rd.s;
@@ -78,7 +85,14 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
                             pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
-                        acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                        if constexpr (RINGS) {
+                            if (pr.ring)
+                                fail[pr.t] |= pass ? 0u : (1u << pr.k);
+                            else
+                                acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                        } else {
+                            acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                        }
                     }
                 }
             }
@@ -87,7 +101,10 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 for (int t = 0; t < MT; ++t) {
                     if (t < nt) {
                         uint32_t *w = bits + (int64_t)grp->tmap[t] * hw + (int64_t)y * W + x;
-                        *w = ps.first ? acc[t] : (*w | acc[t]);
+                        uint32_t v = acc[t];
+                        if constexpr (RINGS)
+                            v &= ~fail[t];  // one pass per group: final here
+                        *w = ps.first ? v : (*w | v);
                     }
                 }
             }
@@ -101,16 +118,27 @@ static void batch_launch(const BuildGeom &g, const void *L, const void *R, const
                          hipStream_t st)
 {
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+    if (bp.rings > 1) {
+        if (bp.max_group <= 8)
+            hipLaunchKernelGGL((star_batch_kernel<Tab, 8, true>), grid, block, 0, st, L, R, Rp,
+                               g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,
+                               bp.radii, bp.probes, bits, sw);
+        else
+            hipLaunchKernelGGL((star_batch_kernel<Tab, 32, true>), grid, block, 0, st, L, R, Rp,
+                               g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,
+                               bp.radii, bp.probes, bits, sw);
+        return;
+    }
     if (bp.max_group <= 8)
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 8>), grid, block, 0, st, L, R, Rp, g.pitch_e,
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 8, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
                            g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
     else if (bp.max_group <= 16)
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 16>), grid, block, 0, st, L, R, Rp, g.pitch_e,
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 16, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
                            g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
     else
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 32>), grid, block, 0, st, L, R, Rp, g.pitch_e,
+        hipLaunchKernelGGL((star_batch_kernel<Tab, 32, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
                            g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
                            bits, sw);
 }

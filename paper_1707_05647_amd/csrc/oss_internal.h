@@ -91,8 +91,10 @@ constexpr int BATCH_GROUP = 32;  // templates per group (scale bits kept in regi
 struct DevBatchProbe {
     int64_t lo[3];
     int64_t hi[3];
-    int32_t t;   // template slot within its group
-    int32_t k;   // scale bit
+    int32_t t;     // template slot within its group
+    int32_t k;     // scale bit
+    int32_t ring;  // 0: the probe's own star; j > 0: its j-th central star
+    int32_t pad;
 };
 
 struct DevBatchGroup {
@@ -115,6 +117,8 @@ struct DevBatchRadius {
     int64_t lo[3], hi[3];
 };
 
+constexpr int MAX_RINGS = 4;
+
 struct BatchDevPlan {
     const DevBatchPass *passes;
     int n_passes;
@@ -122,6 +126,7 @@ struct BatchDevPlan {
     const DevBatchRadius *radii;
     const DevBatchProbe *probes;
     int max_group;
+    int rings;  // 1: plain probes; > 1: central-star rings (one pass per group)
 };
 
 // exact bounds: F passes feature f of a probe iff lo <= F <= hi

@@ -146,3 +146,19 @@ def test_server_argument_errors(lib):
     assert L.oss_server_destroy(None) == lib.OSS_E_ARG
     out = lib.oss_result()
     assert L.oss_server_result(None, 1, C.byref(out)) == lib.OSS_E_ARG
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_template_ring_features_match_oracle(lib, seed):
+    rng = np.random.default_rng(40 + seed)
+    h, w = int(rng.integers(9, 60)), int(rng.integers(9, 60))
+    img = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    rho = min((w - 1) // 2, (h - 1) // 2) - 1
+    for n_rings in (1, 2, 3, 4):
+        got = lib.oss_template_features_rings(img, rho, 7, n_rings)
+        want, radii = oc.template_ring_features(img, rho, n_rings)
+        assert [g.rho for g in got] == radii
+        assert [list(g.F) for g in got] == want.tolist()
+    for bad in (0, 5):
+        with pytest.raises(lib.OssError):
+            lib.oss_template_features_rings(img, rho, 7, bad)
