@@ -242,6 +242,33 @@ def screen_rings_full(img, templates, probes, feat_mask: int, P, Q: int, n_rings
     return bits.reshape(len(templates), H, W)
 
 
+def star_support(r: int, lib=None) -> np.ndarray:
+    """[2r+1, 2r+1] bool: the pixels the radius-r star covers (weight > 0)."""
+    lib = lib or load()
+    return np.array([[lib.oracle_star_weight(dx, dy, r) > 0 for dx in range(-r, r + 1)]
+                     for dy in range(-r, r + 1)], bool)
+
+
+def region_full(H: int, W: int, n_tmpl: int, cands, radius_of: dict, lib=None) -> np.ndarray:
+    """Preserved region [n_tmpl, H, W] (uint8): the union, over every
+    candidate (t, y, x, scale_bits) and every scale bit k it carries, of the
+    pixels covered by the star of radius radius_of[(t, k)] centred on it
+    (Sec. "Experimental Results", Exp. I: the regions the pre-processor
+    preserves, whose complement is the pruned region)."""
+    lib = lib or load()
+    out = np.zeros((n_tmpl, H, W), np.uint8)
+    sup = {}
+    for t, y, x, bits in np.asarray(cands, np.int64).reshape(-1, 4):
+        for k in range(32):
+            if not (int(bits) >> k) & 1:
+                continue
+            r = radius_of[(int(t), k)]
+            if r not in sup:
+                sup[r] = star_support(r, lib)
+            out[t, y - r:y + r + 1, x - r:x + r + 1] |= sup[r]
+    return out
+
+
 def mask_and_list(bits: np.ndarray):
     """Candidate mask (uint8, 1 = survives at some scale) and the candidate
     list as an [n, 4] int64 array of (t, y, x, scale_bits) in (t, y, x) order."""

@@ -289,6 +289,34 @@ def check_rings_consistency(lib):
     assert (prev != plain).any()  # the rings do prune
 
 
+def check_region(lib):
+    """Preserved region: one candidate covers exactly its star's pixels (the
+    7x7 example of Fig. os for r = 3, the enumerator's square and diamond
+    pixel sets otherwise); several candidates and scales give the union."""
+    golden = read_golden_star() > 0
+    reg = oc.region_full(9, 9, 1, [(0, 4, 4, 1)], {(0, 0): 3}, lib)
+    assert (reg[0, 1:8, 1:8].astype(bool) == golden).all() and reg.sum() == golden.sum()
+    for r in (1, 2, 5, 8, 13):
+        n = 2 * r + 5
+        reg = oc.region_full(n, n, 1, [(0, r + 2, r + 2, 1)], {(0, 0): r}, lib)
+        want = np.zeros((n, n), bool)
+        for dx, dy in en.square_pixels(r) + en.diamond_pixels(r):
+            want[r + 2 + dy, r + 2 + dx] = True
+        assert (reg[0].astype(bool) == want).all(), r
+    # two scales on one candidate, two candidates, two templates
+    radius_of = {(0, 0): 2, (0, 3): 4, (1, 1): 3}
+    cands = [(0, 6, 5, 0b1001), (0, 9, 12, 0b1), (1, 7, 7, 0b10)]
+    reg = oc.region_full(16, 18, 2, cands, radius_of, lib)
+    want = np.zeros((2, 16, 18), bool)
+    for t, y, x, bits in cands:
+        for k in range(4):
+            if (bits >> k) & 1:
+                r = radius_of[(t, k)]
+                for dx, dy in en.square_pixels(r) + en.diamond_pixels(r):
+                    want[t, y + dy, x + dx] = True
+    assert (reg.astype(bool) == want).all()
+
+
 ALL_CHECKS = [check_half_width_and_area, check_golden_7x7, check_enumerator, check_correlate,
               check_closed_forms, check_d4, check_compare, check_planted_exact,
-              check_rings_brute_force, check_rings_consistency]
+              check_rings_brute_force, check_rings_consistency, check_region]
