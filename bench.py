@@ -417,6 +417,46 @@ def _dev_copy(dst, src_ptr: int):
         raise RuntimeError(f"hipMemcpy failed ({rc})")
 
 
+def evaluate_regions(w, ctx, L, torch, dev, cands, count, cap):
+    """Exp. I's quality columns on the synthetic stand-in: the preserved
+    region (union of the candidates' star footprints, oss_region), the pruned
+    share of the image, and the overlap of the preserved region with the
+    ground truth, the star footprint of the planted object (radius = the
+    object's radius in the reference, at the planted centre); a screen
+    succeeds for a template when that overlap is at least 90%."""
+    T = len(w.templates)
+    region = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.oss_region(ctx.handle, w.H, w.W, T, w.probes, cands, cap, count, region)
+    e1.record()
+    torch.cuda.synchronize()
+    gt = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
+    one = torch.zeros((T, 4), dtype=torch.int32, device=dev)
+    gt_probes = []
+    for t, tp in enumerate(w.templates):
+        r = int(round(tp.obj_radius))
+        one[t] = torch.tensor([t, tp.cy, tp.cx, 1], dtype=torch.int32)
+        gt_probes.append((t, 0, r))
+    n1 = torch.tensor([T], dtype=torch.int64, device=dev)
+    L.oss_region(ctx.handle, w.H, w.W, T, gt_probes, one, T, n1, gt)
+    torch.cuda.synchronize()
+    hw = float(w.H * w.W)
+    kept = region.flatten(1).sum(1, dtype=torch.int64).cpu().tolist()
+    both = (region & gt).flatten(1).sum(1, dtype=torch.int64).cpu().tolist()
+    gts = gt.flatten(1).sum(1, dtype=torch.int64).cpu().tolist()
+    overlap = [100.0 * b / g for b, g in zip(both, gts)]
+    return {
+        "pruned_region_pct": 100.0 * (1 - sum(kept) / (T * hw)),
+        "overlap_pct_mean": sum(overlap) / T,
+        "overlap_pct_min": min(overlap),
+        "success_90": sum(o >= 90.0 for o in overlap),
+        "templates": T,
+        "region_ms": e0.elapsed_time(e1),
+        "ground_truth": "star footprint of radius round(object radius) at the planted centre",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,6 +466,9 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: the headline rotation+scale screen; 3, 5: batched workloads "
                          "(batched launch against per-template launches); 4: serving loop")
+    ap.add_argument("--evaluate", type=int, default=-1,
+                    help="1: preserved region, overlap with the planted ground truth and the 90%% "
+                         "success criterion after the timed steps (default: on for workload 2)")
     ap.add_argument("--rings", type=int, default=1,
                     help="central-star rings per probe (multi-central-area screen); 1 = off")
     ap.add_argument("--requests", type=int, default=100, help="workload 4: requests")
@@ -602,6 +645,8 @@ def main():
         "pruned_patch_pct": 100.0 * (1 - n / float(T * w.H * w.W)),
     }
     out.update(extra)
+    if args.evaluate == 1 or (args.evaluate < 0 and args.workload == 2):
+        out["evaluation"] = evaluate_regions(w, ctx, L, torch, dev, cands, count, cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds, args.rings)
     ref.release()

@@ -318,6 +318,24 @@ int oss_screen_rings(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *
                      oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
                      void *stream);
 
+/*
+ * Preserved region of a screen (Sec. "Experimental Results", Exp. I: the
+ * regions the pre-processor keeps; one minus their share of the image is
+ * the pruned region).  dev_region [n_tmpl][H][W] (uint8, caller-owned) gets
+ * 1 where the pixel lies inside the star of radius r of a candidate of
+ * template t in dev_list whose scale bits include k, for some probe
+ * (t, k, r) in `probes` (the probe set of the screen that produced the
+ * list), and 0 elsewhere.  The list and its count are read on the device
+ * (entries past min(*dev_count, list_cap) are ignored), so the call needs no
+ * synchronisation after the screen on the same stream.  Works in a context
+ * workspace of about 50 bytes per pixel of the image padded by the largest
+ * radius; one table build and one single-radius star pass per distinct
+ * (template, radius).  Asynchronous on `stream`.
+ */
+int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl, const oss_probe *probes,
+               int32_t n_probes, const oss_candidate *dev_list, int64_t list_cap,
+               const int64_t *dev_count, uint8_t *dev_region, void *stream);
+
 #define OSS_TUNE_MAX 64
 /* Autotuner result: the chosen shape, its time, and every candidate tried
  * (strip, blocks per XCD, bucket) with its time in ms. */

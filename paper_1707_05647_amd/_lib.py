@@ -25,7 +25,7 @@ EXPORTED = [
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
-    "oss_ref_layout", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
+    "oss_ref_layout", "oss_region", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
@@ -139,6 +139,7 @@ def load(path: str | None = None):
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
     lib.oss_screen_batched.argtypes = lib.oss_screen.argtypes
+    lib.oss_region.argtypes = [vp, i32, i32, i32, C.POINTER(oss_probe), i32, vp, i64, vp, vp, vp]
     lib.oss_template_features_rings.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32, i32,
                                                 C.POINTER(oss_template_feat)]
     lib.oss_screen_rings.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, i32,
@@ -440,3 +441,13 @@ def oss_screen_rings(ctx: int, ref: int, tmpl_rings, probes, tol, feat_mask: int
     _check(load().oss_screen_rings(ctx, ref, ta, len(tmpl_rings), n_rings, pa, npb, C.byref(tl),
                                    int(feat_mask), _ptr(mask), _ptr(cand_list), int(list_cap),
                                    _ptr(count), _stream(stream)), "oss_screen_rings")
+
+
+def oss_region(ctx: int, H: int, W: int, n_tmpl: int, probes, cand_list, list_cap: int, count,
+               region, stream=None):
+    """region: torch uint8 [n_tmpl, H, W] on the device (overwritten)."""
+    npb = len(probes)
+    pa = (oss_probe * max(1, npb))(*[oss_probe(int(t), int(k), int(r)) for t, k, r in probes])
+    _check(load().oss_region(ctx, int(H), int(W), int(n_tmpl), pa, npb, _ptr(cand_list),
+                             int(list_cap), _ptr(count), _ptr(region), _stream(stream)),
+           "oss_region")

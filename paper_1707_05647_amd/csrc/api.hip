@@ -151,6 +151,8 @@ int oss_ctx_destroy(oss_ctx *ctx)
         (void)hipFree(ctx->bits);
     if (ctx->cws)
         (void)hipFree(ctx->cws);
+    if (ctx->rws)
+        (void)hipFree(ctx->rws);
     delete ctx;
     return OSS_OK;
 }
@@ -1047,5 +1049,105 @@ extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
     ctx->star_strip = out->strip;
     ctx->star_blocks_per_xcd = out->blocks_per_xcd;
     ctx->batch_bucket = out->bucket_radii;
+    return OSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Preserved region (dilation of the candidates by their stars through the
+// tables of a zero-padded indicator image; see csrc/region.hip).
+// ---------------------------------------------------------------------------
+extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
+                          const oss_probe *probes, int32_t n_probes, const oss_candidate *dev_list,
+                          int64_t list_cap, const int64_t *dev_count, uint8_t *dev_region,
+                          void *stream)
+{
+    if (!ctx || H <= 0 || W <= 0 || n_tmpl <= 0 || n_probes < 0 || (n_probes > 0 && !probes) ||
+        list_cap < 0 || (list_cap > 0 && !dev_list) || !dev_count || !dev_region)
+        return OSS_E_ARG;
+    // scale bits of each (template, radius); radii that cannot fit carry no candidates
+    std::vector<std::pair<std::pair<int, int>, uint32_t>> groups;
+    int R = 0;
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0)
+            return OSS_E_ARG;
+        if (2 * (int64_t)p.r + 1 > std::min(H, W))
+            continue;
+        const std::pair<int, int> key(p.template_id, p.r);
+        auto it = std::find_if(groups.begin(), groups.end(),
+                               [&](const auto &g) { return g.first == key; });
+        if (it == groups.end())
+            groups.push_back({key, 1u << p.scale_id});
+        else
+            it->second |= 1u << p.scale_id;
+        R = std::max(R, (int)p.r);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemsetAsync(dev_region, 0, (size_t)n_tmpl * H * W, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (groups.empty())
+        return OSS_OK;
+    const int Hp = H + 2 * R, Wp = W + 2 * R;
+    const oss_image_desc d{Hp, Wp, (int64_t)Wp, OSS_U8, 1};
+    const BuildGeom g = ref_geom(&d, OSS_F_SUM, R, 0);
+    size_t off[A_COUNT];
+    const size_t tb = ref_layout(g, off);
+    const size_t o_ind = (tb + 255) / 256 * 256;
+    const size_t o_hit = o_ind + ((size_t)Hp * Wp + 255) / 256 * 256;
+    const size_t total = o_hit + (size_t)Hp * Wp * sizeof(uint32_t);
+    int rc = grow(&ctx->rws, &ctx->rws_cap, total);
+    if (rc != OSS_OK)
+        return rc;
+    char *m = static_cast<char *>(ctx->rws);
+    BuildBuffers bb{};
+    bb.L = m + off[A_L];
+    bb.R = m + off[A_R];
+    bb.Rp = m + off[A_RP];
+    bb.bp = m + off[A_BP];
+    bb.agg_L = m + off[A_AGL];
+    bb.agg_AD = m + off[A_AGAD];
+    bb.agg_D = m + off[A_AGD];
+    bb.c_L = m + off[A_CL];
+    bb.c_AD = m + off[A_CAD];
+    bb.c_D = m + off[A_CD];
+    uint8_t *ind = reinterpret_cast<uint8_t *>(m + o_ind);
+    uint32_t *hit = reinterpret_cast<uint32_t *>(m + o_hit);
+    const StarSweep sw = make_sweep(Hp, Wp, ctx->star_strip, ctx->star_blocks_per_xcd);
+    for (const auto &grp : groups) {
+        const int t = grp.first.first, r = grp.first.second;
+        if (hipMemsetAsync(ind, 0, (size_t)Hp * Wp, st) != hipSuccess ||
+            launch_region_scatter(dev_list, list_cap, dev_count, t, grp.second, H, W, R, Wp, ind,
+                                  st) !=
+                hipSuccess ||
+            launch_build(g, ind, Wp, OSS_U8, OSS_F_SUM, bb, st, &ctx->prof) != hipSuccess)
+            return OSS_E_DEVICE;
+        // one radius, one interval: star sum of the indicator >= 1
+        DevTemplatePlan pl{};
+        pl.n_radii = 1;
+        pl.radii[0].r = r;
+        pl.radii[0].s = square_half(r);
+        pl.radii[0].first = 0;
+        pl.radii[0].count = 1;
+        for (int q = 0; q < 3; ++q) {
+            pl.probes[0].lo[q] = INT64_MIN;
+            pl.probes[0].hi[q] = INT64_MAX;
+        }
+        pl.probes[0].lo[0] = 1;
+        pl.probes[0].k = 0;
+        PlanSlot *slot = nullptr;
+        rc = upload_plan(ctx, &pl, sizeof(pl), st, &slot);
+        if (rc != OSS_OK)
+            return rc;
+        if (launch_star_plain(g, bb.L, bb.R, bb.Rp, static_cast<const DevTemplatePlan *>(slot->dev),
+                              hit, sw, 0, 0, false, st, &ctx->prof) != hipSuccess ||
+            hipEventRecord(slot->ev, st) != hipSuccess)
+            return OSS_E_DEVICE;
+        slot->used = true;
+        if (launch_region_or(hit, H, W, R, Wp, dev_region + (int64_t)t * H * W, st) != hipSuccess)
+            return OSS_E_DEVICE;
+    }
     return OSS_OK;
 }

@@ -218,6 +218,12 @@ hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, c
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);
+hipError_t launch_region_scatter(const oss_candidate *list, int64_t list_cap,
+                                 const int64_t *count, int t, uint32_t bits, int H, int W,
+                                 int pad, int64_t wp, uint8_t *ind, hipStream_t st);
+hipError_t launch_region_or(const uint32_t *hit, int H, int W, int pad, int64_t wp,
+                            uint8_t *region, hipStream_t st);
+
 hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
                           oss_candidate *list, int64_t list_cap, int64_t *count, void *workspace,
                           hipStream_t stream, Profiler *prof);

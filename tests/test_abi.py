@@ -162,3 +162,10 @@ def test_template_ring_features_match_oracle(lib, seed):
     for bad in (0, 5):
         with pytest.raises(lib.OssError):
             lib.oss_template_features_rings(img, rho, 7, bad)
+
+
+def test_region_argument_errors(lib):
+    L = lib.load()
+    pr = (lib.oss_probe * 1)(lib.oss_probe(0, 0, 3))
+    dummy = C.c_void_p(1)
+    assert L.oss_region(None, 8, 8, 1, pr, 1, dummy, 1, dummy, dummy, None) == lib.OSS_E_ARG
