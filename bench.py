@@ -480,6 +480,8 @@ def main():
                     help="star kernel strip width (threads per block); 0 = library default")
     ap.add_argument("--star-blocks", type=int, default=0,
                     help="star kernel persistent blocks per XCD; 0 = library default")
+    ap.add_argument("--pipe", type=int, default=-1,
+                    help="1/0: software-pipelined / one-radius-at-a-time star pass; -1 = default")
     ap.add_argument("--planar", type=int, default=-1,
                     help="1/0: planar / interleaved tables; -1 = library default")
     ap.add_argument("--star-lds", type=int, default=-1,
@@ -519,6 +521,8 @@ def main():
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_LDS, args.star_lds)
     if args.planar >= 0:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR, args.planar)
+    if args.pipe >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
     ref = ctx.reference(img, w.feat_mask, w.depth, build=False, max_radius=max(w.radii()))
     T = len(w.templates)
     # room for every candidate, so the sampled check sees a complete list
@@ -635,6 +639,7 @@ def main():
                                                         L.OSS_OPT_STAR_BLOCKS_PER_XCD),
             "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
             "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
+            "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if (big or args.rings > 1) else "plain",
             "rings": args.rings,

@@ -140,12 +140,17 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                quantity in a table plane of its own when
  *                                every quantity fits 32-bit storage, instead
  *                                of side by side in one entry; default 0
+ *   OSS_OPT_STAR_PIPE            1: oss_screen's star pass issues the next
+ *                                radius' lookups before comparing the
+ *                                current one (software pipelining); the LDS
+ *                                option takes precedence; default 0
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
 #define OSS_OPT_STAR_LDS 3
 #define OSS_OPT_BATCH_BUCKET 4
 #define OSS_OPT_TABLE_PLANAR 5
+#define OSS_OPT_STAR_PIPE 6
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 

@@ -445,6 +445,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->table_planar = value;
         return OSS_OK;
+    case OSS_OPT_STAR_PIPE:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->star_pipe = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -460,6 +465,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_STAR_LDS: *value = ctx->star_lds; return OSS_OK;
     case OSS_OPT_BATCH_BUCKET: *value = ctx->batch_bucket; return OSS_OK;
     case OSS_OPT_TABLE_PLANAR: *value = ctx->table_planar; return OSS_OK;
+    case OSS_OPT_STAR_PIPE: *value = ctx->star_pipe; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }
@@ -686,8 +692,9 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
             rmax = std::max(rmax, (int)plans[t].radii[j].r);
         }
         hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
-                                         ctx->bits + hw * t, sw, smax, rmax, ctx->star_lds != 0,
-                                         st, &ctx->prof);
+                                         ctx->bits + hw * t, sw, smax, rmax,
+                                         ctx->star_lds ? 1 : (ctx->star_pipe ? 2 : 0), st,
+                                         &ctx->prof);
         if (e != hipSuccess)
             return OSS_E_DEVICE;
     }
@@ -1142,7 +1149,8 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
         if (rc != OSS_OK)
             return rc;
         if (launch_star_plain(g, bb.L, bb.R, bb.Rp, static_cast<const DevTemplatePlan *>(slot->dev),
-                              hit, sw, 0, 0, false, st, &ctx->prof) != hipSuccess ||
+                              hit, sw, 0, 0, ctx->star_pipe ? 2 : 0, st, &ctx->prof) !=
+                hipSuccess ||
             hipEventRecord(slot->ev, st) != hipSuccess)
             return OSS_E_DEVICE;
         slot->used = true;

@@ -36,6 +36,7 @@ struct oss_ctx {
     int star_lds = 0;              // OSS_OPT_STAR_LDS
     int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
     int table_planar = 0;          // OSS_OPT_TABLE_PLANAR
+    int star_pipe = 0;             // OSS_OPT_STAR_PIPE
     void *rws = nullptr;           // preserved-region workspace (tables of the padded
     size_t rws_cap = 0;            // indicator image, the image, the star pass output)
 };

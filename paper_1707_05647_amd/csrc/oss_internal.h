@@ -208,9 +208,12 @@ StarSweep make_sweep(int H, int W, int strip, int blocks_per_xcd);
 // and radius among the template's probes).
 constexpr size_t STAR_LDS_MAX = 64 * 1024;
 size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax);
+// variant: 0 one radius at a time, 1 LDS-staged rows (32/64-bit
+// interleaved entries only), 2 software-pipelined radii
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                             int smax, int rmax, bool lds, hipStream_t stream, Profiler *prof);
+                             int smax, int rmax, int variant, hipStream_t stream,
+                             Profiler *prof);
 
 hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,

@@ -83,6 +83,110 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     }
 }
 
+// Software-pipelined form of the same screen: the 8 lookups of the next
+// radius are issued before the current radius is reduced and compared, so
+// every wave keeps two radii of loads in flight.  Lookups use the column
+// clamped into the radius' valid range (every lane loads, no lane masking;
+// lanes outside the range discard the result), and only radii whose star
+// fits the row and the image width are walked: with the radii ascending
+// they are a prefix of the template's list.
+template <typename Tab>
+struct Looks {
+    typename Tab::E a, b, c, d, e, f, h, k;
+};
+
+template <typename Tab>
+__device__ __forceinline__ void star_load(Looks<Tab> &o, const char *L, const char *R,
+                                          const char *Rp, int64_t row_bytes, int xc, int y,
+                                          int r, int s, int64_t plane)
+{
+    constexpr uint32_t ES = (uint32_t)Tab::ES;
+    const char *l_top = L + (int64_t)(y - s) * row_bytes;      // row y-s-1
+    const char *l_bot = L + (int64_t)(y + s + 1) * row_bytes;  // row y+s
+    const char *r_top = R + (int64_t)(y - r) * row_bytes;      // row y-r-1
+    const char *r_bot = R + (int64_t)(y + r + 1) * row_bytes;  // row y+r
+    const char *rp_mid = Rp + (int64_t)y * row_bytes;           // row y-1
+    // byte offsets of table columns (image column + 1) from the row start
+    const uint32_t c0 = (uint32_t)(xc + 1) * ES;                 // x
+    const uint32_t cs = (uint32_t)(xc + s + 1) * ES;             // x+s
+    const uint32_t cs1 = (uint32_t)(xc - s) * ES;                // x-s-1
+    const uint32_t cr = (uint32_t)(xc + r + 1) * ES;             // x+r
+    const uint32_t cr1 = (uint32_t)(xc - r) * ES;                // x-r-1
+    o.a = Tab::load(l_bot + cs, plane);    // L(x+s,   y+s)
+    o.b = Tab::load(l_bot + cs1, plane);   // L(x-s-1, y+s)
+    o.c = Tab::load(l_top + cs, plane);    // L(x+s,   y-s-1)
+    o.d = Tab::load(l_top + cs1, plane);   // L(x-s-1, y-s-1)
+    o.e = Tab::load(r_bot + c0, plane);    // R(x, y+r)
+    o.f = Tab::load(rp_mid + cr1, plane);  // R'(x-r-1, y-1)
+    o.h = Tab::load(rp_mid + cr, plane);   // R'(x+r, y-1)
+    o.k = Tab::load(r_top + c0, plane);    // R(x, y-r-1)
+}
+
+template <typename Tab>
+__global__ __launch_bounds__(STAR_MAX_THREADS) void star_pipe_kernel(
+    const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
+    int64_t pitch_e, int64_t plane, int H, int W, const DevTemplatePlan *__restrict__ plan,
+    uint32_t *__restrict__ bits, StarSweep sw)
+{
+    constexpr int NQ = Tab::NQ;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int units = (sw.n_units - xcd + 7) / 8;
+    const int items = units * sw.rows_per_part;
+    const int64_t row_bytes = pitch_e * Tab::ES;
+    const char *Lt = static_cast<const char *>(L);
+    const char *Rt = static_cast<const char *>(R);
+    const char *Rpt = static_cast<const char *>(Rp);
+    const int nr = plan->n_radii;
+    for (int it = j; it < items; it += sw.blocks_per_xcd) {
+        int y, x0;
+        sweep_item(sw, xcd, it, (int)blockDim.x, &y, &x0);
+        if (y >= H)
+            continue;
+        const int x = x0 + threadIdx.x;
+        int nv = 0;
+        while (nv < nr) {
+            const int r = plan->radii[nv].r;
+            if (y < r || y > H - 1 - r || 2 * r + 1 > W)
+                break;
+            ++nv;
+        }
+        uint32_t acc = 0;
+        if (nv > 0) {
+            DevRadius rd = plan->radii[0];
+            Looks<Tab> cur;
+            star_load<Tab>(cur, Lt, Rt, Rpt, row_bytes, min(max(x, rd.r), W - 1 - rd.r), y, rd.r,
+                           rd.s, plane);
+            for (int jr = 0; jr < nv; ++jr) {
+                const bool more = jr + 1 < nv;
+                Looks<Tab> nxt;
+                DevRadius rn = rd;
+                if (more) {
+                    rn = plan->radii[jr + 1];
+                    star_load<Tab>(nxt, Lt, Rt, Rpt, row_bytes, min(max(x, rn.r), W - 1 - rn.r), y,
+                                   rn.r, rn.s, plane);
+                }
+                int64_t F[NQ];
+                Tab::reduce(cur.a, cur.b, cur.c, cur.d, cur.e, cur.f, cur.h, cur.k, F);
+                const bool xv = x >= rd.r && x <= W - 1 - rd.r;
+                for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                    const DevProbe pr = plan->probes[p];
+                    bool pass = xv;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                    acc |= pass ? (1u << pr.k) : 0u;
+                }
+                if (more) {
+                    cur = nxt;
+                    rd = rn;
+                }
+            }
+        }
+        if (x < W)
+            bits[(int64_t)y * W + x] = acc;
+    }
+}
+
 // Same screen with the rows that several lookups share staged in LDS: per
 // block row (strip columns [x0, x0 + strip) of image row y) the R' row y-1
 // is loaded once for all radii over [x0 - r_max - 1, x0 + strip - 1 + r_max],
@@ -217,24 +321,28 @@ static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T 
 template <typename Tab>
 static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                               const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                              hipStream_t stream)
+                              hipStream_t stream, bool pipe)
 {
-    hipLaunchKernelGGL((star_plain_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), 0,
-                       stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+    if (pipe)
+        hipLaunchKernelGGL((star_pipe_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), 0,
+                           stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+    else
+        hipLaunchKernelGGL((star_plain_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip),
+                           0, stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
 }
 
 template <typename T>
 static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                          const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                         int smax, int rmax, bool lds, hipStream_t stream)
+                         int smax, int rmax, bool lds, bool pipe, hipStream_t stream)
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
     if (g.planar) {
         switch (g.nq) {
-        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream); break;
-        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream); break;
-        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream); break;
+        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -249,9 +357,9 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
         return hipGetLastError();
     }
     switch (g.nq) {
-    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream); break;
-    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream); break;
-    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream); break;
+    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -260,14 +368,14 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
 // Mixed 16-byte entries (the squares in 64 bits): no LDS variant.
 static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                            const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                           hipStream_t stream)
+                           hipStream_t stream, bool pipe)
 {
     if (g.nq == 3 && g.sqi == 1)
-        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream);
+        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
     else if (g.nq == 2 && g.sqi == 1)
-        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream);
+        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
     else if (g.nq == 2 && g.sqi == 0)
-        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream);
+        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -275,18 +383,21 @@ static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, con
 
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                             int smax, int rmax, bool lds, hipStream_t stream, Profiler *prof)
+                             int smax, int rmax, int variant, hipStream_t stream,
+                             Profiler *prof)
 {
+    bool lds = variant == 1;
+    const bool pipe = variant == 2;
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1)
         return hipErrorInvalidValue;
     if (lds && star_lds_bytes(sw.strip, g.nq, g.ebytes, smax, rmax) > STAR_LDS_MAX)
         lds = false;
     ProfScope ps(prof, K_STAR, stream);
     if (g.sqi >= 0)
-        return star_mix(g, L, R, Rp, plan, bits, sw, stream);
+        return star_mix(g, L, R, Rp, plan, bits, sw, stream, pipe);
     if (g.ebytes == 4)
-        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);
-    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, stream);
+        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, pipe, stream);
+    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, pipe, stream);
 }
 
 }  // namespace oss

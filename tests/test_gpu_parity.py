@@ -288,3 +288,25 @@ def test_planar_tables_same_results(runner, cfg):
     wmask, wlist = oc.mask_and_list(want)
     assert got[2] == len(wlist) and np.array_equal(got[0], wmask)
     assert np.array_equal(got[1], wlist)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+@WIDTHS
+def test_pipelined_star_same_results(runner, cfg, max_r):
+    """The software-pipelined star pass (OSS_OPT_STAR_PIPE) equals the oracle
+    on every workload shape and entry layout, also with narrow strips."""
+    kw = {1: {},
+          2: dict(H=230, W=270, blobs_per_512sq=800, sig_hi=24),
+          3: dict(H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20),
+          5: dict(H=224, W=240, n_templates=3, blobs_per_512sq=1200, sig_hi=20)}[cfg]
+    w = make_workload(cfg, 5, **kw)
+    L = runner.L
+    h = runner.ctx.handle
+    L.oss_ctx_set_option(h, L.OSS_OPT_STAR_PIPE, 1)
+    try:
+        _screen_and_compare(runner, w, max_r)
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STRIP, 64)
+        _screen_and_compare(runner, w, max_r, pitch_pad=5)
+    finally:
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_PIPE, 0)
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STRIP, 512)
