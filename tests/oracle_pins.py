@@ -317,6 +317,55 @@ def check_region(lib):
     assert (reg.astype(bool) == want).all()
 
 
+def check_alg1(lib):
+    """Algorithm 1's pieces: the scale bands for [1/2, 2] (four bands; sizes
+    from exact integer square roots), the bilinear resize on a textbook
+    example (pixel-centre aligned, edges replicated, half up), the
+    quantiser's marking guarantee (Sec. "Scale Invariance": marking Q(f-q/2),
+    Q(f), Q(f+q/2) admits every g with |f - g| < q/2), and the exact-copy
+    guarantee at unit scale."""
+    from fractions import Fraction as Fr
+
+    from oracle import alg1
+    assert alg1.band_count(Fr(1, 2), Fr(2)) == 4
+    assert alg1.band_count(Fr(1), Fr(1)) == 0 and alg1.band_count(Fr(3, 4), Fr(1)) == 1
+    assert alg1.bands(64, Fr(1, 2), Fr(2)) == [(91, 91, 128), (64, 64, 90), (46, 46, 64),
+                                               (32, 32, 45)]
+    assert alg1.bands(33, Fr(1, 2), Fr(2)) == [(47, 47, 66), (33, 33, 46), (24, 24, 33),
+                                               (17, 17, 23)]
+    # resize: 2x2 -> 4x4 and back, identity, constants
+    up = alg1.resize(np.array([[0, 100], [0, 100]], np.uint16), 4)
+    assert (up == np.array([[0, 25, 75, 100]] * 4)).all(), up
+    down = alg1.resize(up, 2)
+    assert (down == np.array([[13, 88]] * 2)).all(), down
+    rng = np.random.default_rng(5)
+    t = rng.integers(0, 256, (9, 9)).astype(np.uint16)
+    assert (alg1.resize(t, 9) == t).all()
+    assert (alg1.resize(np.full((7, 7), 200, np.uint16), 12) == 200).all()
+    # marking guarantee, on random rationals
+    for _ in range(2000):
+        q = int(rng.integers(1, 50))
+        f = Fr(int(rng.integers(0, 10 ** 6)), int(rng.integers(1, 7)))
+        g = f + Fr(int(rng.integers(-10 ** 4, 10 ** 4)), 10 ** 4) * Fr(q, 2)
+        if abs(f - g) >= Fr(q, 2):
+            continue
+        marked = {alg1.quantise(f - Fr(q, 2), q), alg1.quantise(f, q),
+                  alg1.quantise(f + Fr(q, 2), q)}
+        assert alg1.quantise(g, q) in marked
+    assert [alg1.quantise(v, 10) for v in (4, 5, 14, 15, Fr(29, 2))] == [0, 1, 1, 2, 1]
+    # an exact cut survives at its centre in the band holding k = n
+    from synth import blob_image, make_rng, cut_patch
+    img = blob_image(120, 130, make_rng(97, 0), blobs_per_512sq=1500, sig_hi=10)
+    cx, cy, half = 64, 58, 12
+    tm = cut_patch(img, cx, cy, half)                          # n = 25
+    n = 2 * half + 1
+    bits = alg1.screen(img, [tm], Fr(1, 2), Fr(2), (1, 60, 1), 3, lib)
+    b = [i for i, (_, lo, hi) in enumerate(alg1.bands(n, Fr(1, 2), Fr(2))) if lo <= n <= hi][0]
+    assert (int(bits[0, cy, cx]) >> b) & 1
+    # fine steps keep few patches
+    assert bits[0].astype(bool).sum() < 0.2 * bits[0].size
+
+
 ALL_CHECKS = [check_half_width_and_area, check_golden_7x7, check_enumerator, check_correlate,
               check_closed_forms, check_d4, check_compare, check_planted_exact,
-              check_rings_brute_force, check_rings_consistency, check_region]
+              check_rings_brute_force, check_rings_consistency, check_region, check_alg1]
