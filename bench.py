@@ -469,6 +469,9 @@ def main():
     ap.add_argument("--evaluate", type=int, default=-1,
                     help="1: preserved region, overlap with the planted ground truth and the 90%% "
                          "success criterion after the timed steps (default: on for workload 2)")
+    ap.add_argument("--alg1", type=int, default=0,
+                    help="1: screen with Algorithm 1 taken literally (sqrt 2 scale bands over "
+                         "[1/2, 2], quantised membership) instead of the probe radii")
     ap.add_argument("--rings", type=int, default=1,
                     help="central-star rings per probe (multi-central-area screen); 1 = off")
     ap.add_argument("--requests", type=int, default=100, help="workload 4: requests")
@@ -523,7 +526,13 @@ def main():
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR, args.planar)
     if args.pipe >= 0:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
-    ref = ctx.reference(img, w.feat_mask, w.depth, build=False, max_radius=max(w.radii()))
+    max_r = max(w.radii())
+    if args.alg1:
+        from fractions import Fraction
+        max_r = max(p.r for t, tp in enumerate(w.templates)
+                    for p in L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2),
+                                               (1, 1, 1), w.feat_mask, bit_depth=w.depth))
+    ref = ctx.reference(img, w.feat_mask, w.depth, build=False, max_radius=max_r)
     T = len(w.templates)
     # room for every candidate, so the sampled check sees a complete list
     cap = min(T * w.H * w.W, 1 << 22 if not big else 1_600_000_000)
@@ -540,7 +549,26 @@ def main():
         return [L.oss_template_features_rings(t.pixels, t.rho, w.feat_mask, args.rings,
                                               bit_depth=w.depth) for t in w.templates]
 
+    ALG1_Q = (4, 300, 6) if w.depth == 8 else (64, 80000, 90)
+
+    def alg1_probes():
+        from fractions import Fraction
+        out = []
+        for t, tp in enumerate(w.templates):
+            out += L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2), ALG1_Q,
+                                     w.feat_mask, bit_depth=w.depth)
+        return out
+
     def make_step(batched):
+        def step_alg1():
+            pr = alg1_probes()
+            ref.build(stream)
+            L.oss_screen_intervals(ctx.handle, ref.handle, T, pr, w.feat_mask, mask, cands, cap,
+                                   count, stream)
+
+        if args.alg1:
+            return step_alg1
+
         def step():
             tm = tfeat()
             ref.build(stream)
@@ -580,7 +608,12 @@ def main():
     sec, prof = run_steps(make_step(big or args.rings > 1), args.steps, args.warmup, ctx, L,
                           torch)
 
-    ps = pixel_scales(w.H, w.W, w.probes)
+    if args.alg1:
+        # one pixel-scale per (valid position, template, band)
+        bands = {(p.template_id, p.scale_id, p.r) for p in alg1_probes()}
+        ps = sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, _, r in bands)
+    else:
+        ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
     n = int(count.item())
     eb = ref.entry_bytes
@@ -643,6 +676,7 @@ def main():
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if (big or args.rings > 1) else "plain",
             "rings": args.rings,
+            "alg1": bool(args.alg1),
         },
         "roofline": roof,
         "kernels": kern,
@@ -652,7 +686,7 @@ def main():
     out.update(extra)
     if args.evaluate == 1 or (args.evaluate < 0 and args.workload == 2):
         out["evaluation"] = evaluate_regions(w, ctx, L, torch, dev, cands, count, cap)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.alg1:
         out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds, args.rings)
     ref.release()
     ctx.close()

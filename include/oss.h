@@ -341,6 +341,64 @@ int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl, const oss_pro
                int32_t n_probes, const oss_candidate *dev_list, int64_t list_cap,
                const int64_t *dev_count, uint8_t *dev_region, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Interval probes and Algorithm 1 taken literally.
+ * ------------------------------------------------------------------------ */
+
+/* A probe given by explicit inclusive bounds on the star's feature sums
+ * (feature order: sum, squares, gradient; bounds of features outside the
+ * screen's feature mask are ignored). */
+typedef struct oss_interval_probe {
+    int32_t template_id;  /* result row t */
+    int32_t scale_id;     /* result bit k (0..31) */
+    int32_t r;            /* star radius, 0..the reference's max radius */
+    int32_t pad;
+    int64_t lo[3], hi[3];
+} oss_interval_probe;
+
+/*
+ * Screen with interval probes: bit k of template t is set where, for some
+ * probe (t, k, r), the radius-r star fits and every enabled feature sum lies
+ * in [lo, hi] (several probes sharing (t, k) give the union of their boxes).
+ * One batched launch (OSS_OPT_STAR_* and OSS_OPT_BATCH_BUCKET apply);
+ * outputs, ownership and errors as oss_screen.
+ */
+int oss_screen_intervals(oss_ctx *ctx, const oss_ref *ref, int32_t n_tmpl,
+                         const oss_interval_probe *probes, int32_t n_probes, uint32_t feat_mask,
+                         uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
+                         int64_t *dev_count, void *stream);
+
+/* Parameters of Algorithm 1: the scale range [alpha, beta] as fractions and
+ * the quantisation step of each feature in units of its per-pixel mean
+ * (grey levels, squared grey levels, gradient units). */
+typedef struct oss_alg1_params {
+    int32_t alpha_num, alpha_den, beta_num, beta_den;
+    int32_t q[3];
+    uint32_t feat_mask;
+} oss_alg1_params;
+
+/*
+ * The template side of Algorithm 1 (Sec. "Scale Invariance", Algorithm 1,
+ * Eq. F_n) for one square template of width n, as interval probes of
+ * template t: lambda = sqrt 2; band b = 0 .. B-1, B = the smallest integer
+ * with lambda^B >= beta/alpha, covers the template sizes k = ceil(m_b) ..
+ * floor(lambda m_b), m_b = beta n / lambda^(b+1), and screens patches of
+ * size m = ceil(m_b) with the star of radius (m-1)/2.  For each k the
+ * template is resized to k x k (bilinear, pixel centres aligned, edges
+ * replicated, rounded half up, exact integers), its central m x m crop's
+ * star features F are quantised with Q(f) = floor(f/q + 1/2), q = q_f A(r),
+ * and the cells Q(F - q/2), Q(F), Q(F + q/2) of every feature are marked;
+ * the marked box of k becomes one probe (scale_id = b) bounding the sums to
+ * the cells floor(F/q) .. floor(F/q) + 1.  Identical boxes are emitted
+ * once.  Writes up to `cap` probes to out and the number needed to *n_out;
+ * OSS_E_NOMEM if cap is smaller.  Host-side, synchronous.  Errors: a
+ * non-square template, alpha > beta, non-positive fractions or steps, more
+ * than 32 bands.
+ */
+int oss_alg1_probes(const void *host_pixels, const oss_image_desc *desc, int32_t t,
+                    const oss_alg1_params *params, oss_interval_probe *out, int32_t cap,
+                    int32_t *n_out);
+
 #define OSS_TUNE_MAX 64
 /* Autotuner result: the chosen shape, its time, and every candidate tried
  * (strip, blocks per XCD, bucket) with its time in ms. */

@@ -25,7 +25,7 @@ EXPORTED = [
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
-    "oss_ref_layout", "oss_region", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
+    "oss_ref_layout", "oss_region", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
@@ -65,6 +65,16 @@ class oss_tune_result(C.Structure):
     _fields_ = [("strip", C.c_int32), ("blocks_per_xcd", C.c_int32), ("bucket_radii", C.c_int32),
                 ("ms", C.c_float), ("n_tried", C.c_int32),
                 ("tried", (C.c_int32 * 3) * OSS_TUNE_MAX), ("tried_ms", C.c_float * OSS_TUNE_MAX)]
+
+
+class oss_interval_probe(C.Structure):
+    _fields_ = [("template_id", C.c_int32), ("scale_id", C.c_int32), ("r", C.c_int32),
+                ("pad", C.c_int32), ("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3)]
+
+
+class oss_alg1_params(C.Structure):
+    _fields_ = [("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("beta_num", C.c_int32),
+                ("beta_den", C.c_int32), ("q", C.c_int32 * 3), ("feat_mask", C.c_uint32)]
 
 
 class oss_server_config(C.Structure):
@@ -140,6 +150,11 @@ def load(path: str | None = None):
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
     lib.oss_screen_batched.argtypes = lib.oss_screen.argtypes
+    lib.oss_screen_intervals.argtypes = [vp, vp, i32, C.POINTER(oss_interval_probe), i32, u32,
+                                         vp, vp, i64, vp, vp]
+    lib.oss_alg1_probes.argtypes = [vp, C.POINTER(oss_image_desc), i32,
+                                    C.POINTER(oss_alg1_params), C.POINTER(oss_interval_probe),
+                                    i32, C.POINTER(i32)]
     lib.oss_region.argtypes = [vp, i32, i32, i32, C.POINTER(oss_probe), i32, vp, i64, vp, vp, vp]
     lib.oss_template_features_rings.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32, i32,
                                                 C.POINTER(oss_template_feat)]
@@ -452,3 +467,37 @@ def oss_region(ctx: int, H: int, W: int, n_tmpl: int, probes, cand_list, list_ca
     _check(load().oss_region(ctx, int(H), int(W), int(n_tmpl), pa, npb, _ptr(cand_list),
                              int(list_cap), _ptr(count), _ptr(region), _stream(stream)),
            "oss_region")
+
+
+# --- interval probes and Algorithm 1 -----------------------------------------------
+
+def oss_alg1_probes(pixels, t: int, alpha, beta, q, feat_mask: int,
+                    bit_depth: int | None = None) -> list:
+    """Algorithm 1's interval probes of one square template (alpha, beta as
+    fractions.Fraction or (num, den))."""
+    from fractions import Fraction
+    a, b = Fraction(alpha), Fraction(beta)
+    a_img = np.ascontiguousarray(pixels)
+    d = desc_of(a_img, bit_depth)
+    prm = oss_alg1_params(a.numerator, a.denominator, b.numerator, b.denominator,
+                          (C.c_int32 * 3)(*[int(v) for v in q]), int(feat_mask))
+    n = C.c_int32()
+    rc = load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), None, 0,
+                                C.byref(n))
+    if rc not in (OSS_OK, OSS_E_NOMEM):
+        _check(rc, "oss_alg1_probes")
+    out = (oss_interval_probe * max(1, n.value))()
+    _check(load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), out,
+                                  n.value, C.byref(n)), "oss_alg1_probes")
+    return list(out[:n.value])
+
+
+def oss_screen_intervals(ctx: int, ref: int, n_tmpl: int, probes, feat_mask: int, mask=None,
+                         cand_list=None, list_cap: int = 0, count=None, stream=None):
+    npb = len(probes)
+    pa = (oss_interval_probe * max(1, npb))(*probes)
+    if count is None:
+        raise ValueError("count tensor required")
+    _check(load().oss_screen_intervals(ctx, ref, int(n_tmpl), pa, npb, int(feat_mask),
+                                       _ptr(mask), _ptr(cand_list), int(list_cap), _ptr(count),
+                                       _stream(stream)), "oss_screen_intervals")

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -350,18 +351,14 @@ int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[3],
 
 // Template features on the host: star sums at the template centre, summed
 // row by row over the square's and the diamond's spans.
-int oss_template_features(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
-                          uint32_t feat_mask, oss_template_feat *out)
+}  // extern "C"
+
+// Star sums of radius rho at (cx, cy) of a host image (gradient clamped to
+// the image), for the enabled features (others 0).  The star must fit.
+static void star_feats_at(const void *host_pixels, const oss_image_desc *desc, int cx, int cy,
+                          int rho, uint32_t feat_mask, int64_t F[3])
 {
-    if (!host_pixels || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
-        return OSS_E_ARG;
     const int H = desc->H, W = desc->W;
-    const int cx = (W - 1) / 2, cy = (H - 1) / 2;
-    const int rmax = std::min(std::min(cx, W - 1 - cx), std::min(cy, H - 1 - cy));
-    if (rho < 0)
-        rho = rmax - ((feat_mask & OSS_F_GRAD) ? 1 : 0);
-    if (rho < 0 || rho > rmax)
-        return OSS_E_ARG;
     const unsigned char *base = static_cast<const unsigned char *>(host_pixels);
     auto pix = [&](int x, int y) -> int64_t {
         const unsigned char *row = base + (int64_t)y * desc->pitch_bytes;
@@ -394,9 +391,26 @@ int oss_template_features(const void *host_pixels, const oss_image_desc *desc, i
         const int h = rho - (dy < 0 ? -dy : dy);
         span(cy + dy, cx - h, cx + h);
     }
-    out->F[0] = (feat_mask & OSS_F_SUM) ? f1 : 0;
-    out->F[1] = (feat_mask & OSS_F_SQ) ? f2 : 0;
-    out->F[2] = (feat_mask & OSS_F_GRAD) ? fg : 0;
+    F[0] = (feat_mask & OSS_F_SUM) ? f1 : 0;
+    F[1] = (feat_mask & OSS_F_SQ) ? f2 : 0;
+    F[2] = (feat_mask & OSS_F_GRAD) ? fg : 0;
+}
+
+extern "C" {
+
+int oss_template_features(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
+                          uint32_t feat_mask, oss_template_feat *out)
+{
+    if (!host_pixels || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+        return OSS_E_ARG;
+    const int H = desc->H, W = desc->W;
+    const int cx = (W - 1) / 2, cy = (H - 1) / 2;
+    const int rmax = std::min(std::min(cx, W - 1 - cx), std::min(cy, H - 1 - cy));
+    if (rho < 0)
+        rho = rmax - ((feat_mask & OSS_F_GRAD) ? 1 : 0);
+    if (rho < 0 || rho > rmax)
+        return OSS_E_ARG;
+    star_feats_at(host_pixels, desc, cx, cy, rho, feat_mask, out->F);
     out->rho = rho;
     out->feat_mask = feat_mask;
     return OSS_OK;
@@ -714,65 +728,46 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
 // Templates sorted by radius and cut into groups of BATCH_GROUP; each group's
 // probes sorted by reference radius; every run of at most `bucket` distinct
 // radii (0: all) becomes one pass.
-int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
-                         const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
-                         const uint32_t *fms, int bucket, BatchHostPlan &bp, int n_rings)
+// One entry of a template's part of a batched plan: a test at radius r
+// with bounds per table slot, setting (ring 0) or vetoing (ring > 0) bit k.
+struct PlanEntry {
+    int r, k, ring;
+    int64_t lo[3], hi[3];
+};
+
+// Groups of at most BATCH_GROUP templates in `order`, each group's entries
+// sorted by radius, passes over runs of at most `bucket` distinct radii.
+static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
+                         const std::vector<int> &order, int bucket, BatchHostPlan &bp)
 {
-    if (n_rings < 1 || n_rings > MAX_RINGS)
-        return OSS_E_ARG;
-    bp.rings = n_rings;
-    if (n_rings > 1)
-        bucket = 0;  // the ring tests of a probe combine in registers: one pass
-    std::vector<std::vector<oss_probe>> per(n_tmpl);
-    for (int i = 0; i < n_probes; ++i) {
-        const oss_probe &p = probes[i];
-        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
-            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
-            return OSS_E_ARG;
-        per[p.template_id].push_back(p);
-        if ((int)per[p.template_id].size() > OSS_MAX_SCALES)
-            return OSS_E_ARG;
-    }
-    int slot_of[3], slot = 0;
-    for (int f = 0; f < 3; ++f)
-        slot_of[f] = (ref->feat_mask & (1u << f)) ? slot++ : -1;
-    std::vector<int> order(n_tmpl);
-    for (int t = 0; t < n_tmpl; ++t)
-        order[t] = t;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return tmpl[(int64_t)a * n_rings].rho < tmpl[(int64_t)b * n_rings].rho;
-    });
+    const int n_tmpl = (int)order.size();
     for (int g0 = 0; g0 < n_tmpl; g0 += BATCH_GROUP) {
         const int nt = std::min(BATCH_GROUP, n_tmpl - g0);
         DevBatchGroup grp{};
         grp.n_t = nt;
         struct Item {
-            int r, slot, ring;
-            oss_probe p;
+            int slot;
+            const PlanEntry *e;
         };
         std::vector<Item> items;
         for (int i = 0; i < nt; ++i) {
             const int t = order[g0 + i];
             grp.tmap[i] = t;
-            for (const oss_probe &p : per[t]) {
-                int rj = p.r;
-                for (int j = 0; j < n_rings; ++j) {
-                    items.push_back({rj, i, j, p});
-                    rj = square_half(rj);
-                }
-            }
+            for (const PlanEntry &e : per[t])
+                items.push_back({i, &e});
         }
         std::stable_sort(items.begin(), items.end(),
-                         [](const Item &a, const Item &b) { return a.r < b.r; });
+                         [](const Item &a, const Item &b) { return a.e->r < b.e->r; });
         const int gi = (int)bp.groups.size();
         bp.groups.push_back(grp);
         bp.max_group = std::max(bp.max_group, nt);
         const int rad_begin = (int)bp.radii.size();
         for (const Item &it : items) {
-            if ((int)bp.radii.size() == rad_begin || bp.radii.back().r != it.r) {
+            const PlanEntry &e = *it.e;
+            if ((int)bp.radii.size() == rad_begin || bp.radii.back().r != e.r) {
                 DevBatchRadius rd{};
-                rd.r = it.r;
-                rd.s = square_half(it.r);
+                rd.r = e.r;
+                rd.s = square_half(e.r);
                 rd.first = (int32_t)bp.probes.size();
                 rd.count = 0;
                 for (int q = 0; q < 3; ++q) {
@@ -785,26 +780,15 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
             cur.count++;
             DevBatchProbe dp{};
             dp.t = it.slot;
-            dp.k = it.p.scale_id;
-            dp.ring = it.ring;
+            dp.k = e.k;
+            dp.ring = e.ring;
             for (int q = 0; q < 3; ++q) {
-                dp.lo[q] = INT64_MIN;
-                dp.hi[q] = INT64_MAX;
-            }
-            const int tt = grp.tmap[it.slot];
-            const oss_template_feat &tf = tmpl[(int64_t)tt * n_rings + it.ring];
-            const oss_tolerance &tol = tols[tt];
-            for (int f = 0; f < 3; ++f) {
-                if (!(fms[tt] & (1u << f)))
-                    continue;
-                feature_bounds(f, tf.F[f], it.r, tf.rho, tol.P[f], tol.Q, &dp.lo[slot_of[f]],
-                               &dp.hi[slot_of[f]]);
-            }
-            for (int q = 0; q < 3; ++q) {
+                dp.lo[q] = e.lo[q];
+                dp.hi[q] = e.hi[q];
                 // a central-star test must run (and may fail) wherever the
                 // radius is evaluated: no hull skip at radii that carry one
-                cur.lo[q] = std::min(cur.lo[q], it.ring ? INT64_MIN : dp.lo[q]);
-                cur.hi[q] = std::max(cur.hi[q], it.ring ? INT64_MAX : dp.hi[q]);
+                cur.lo[q] = std::min(cur.lo[q], e.ring ? INT64_MIN : dp.lo[q]);
+                cur.hi[q] = std::max(cur.hi[q], e.ring ? INT64_MAX : dp.hi[q]);
             }
             bp.probes.push_back(dp);
         }
@@ -817,6 +801,102 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
             j0 = j1;
         } while (j0 < rad_end);
     }
+}
+
+// feature f -> table slot (the reference's quantities in bit order), -1 if absent
+static void slots_of(uint32_t ref_fm, int slot_of[3])
+{
+    int slot = 0;
+    for (int f = 0; f < 3; ++f)
+        slot_of[f] = (ref_fm & (1u << f)) ? slot++ : -1;
+}
+
+int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                         const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
+                         const uint32_t *fms, int bucket, BatchHostPlan &bp, int n_rings)
+{
+    if (n_rings < 1 || n_rings > MAX_RINGS)
+        return OSS_E_ARG;
+    bp.rings = n_rings;
+    if (n_rings > 1)
+        bucket = 0;  // the ring tests of a probe combine in registers: one pass
+    std::vector<int> count(n_tmpl, 0);
+    int slot_of[3];
+    slots_of(ref->feat_mask, slot_of);
+    std::vector<std::vector<PlanEntry>> per(n_tmpl);
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
+            return OSS_E_ARG;
+        const int t = p.template_id;
+        if (++count[t] > OSS_MAX_SCALES)
+            return OSS_E_ARG;
+        int rj = p.r;
+        for (int j = 0; j < n_rings; ++j) {
+            PlanEntry e{};
+            e.r = rj;
+            e.k = p.scale_id;
+            e.ring = j;
+            for (int q = 0; q < 3; ++q) {
+                e.lo[q] = INT64_MIN;
+                e.hi[q] = INT64_MAX;
+            }
+            const oss_template_feat &tf = tmpl[(int64_t)t * n_rings + j];
+            const oss_tolerance &tol = tols[t];
+            for (int f = 0; f < 3; ++f) {
+                if (!(fms[t] & (1u << f)))
+                    continue;
+                feature_bounds(f, tf.F[f], rj, tf.rho, tol.P[f], tol.Q, &e.lo[slot_of[f]],
+                               &e.hi[slot_of[f]]);
+            }
+            per[t].push_back(e);
+            rj = square_half(rj);
+        }
+    }
+    std::vector<int> order(n_tmpl);
+    for (int t = 0; t < n_tmpl; ++t)
+        order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return tmpl[(int64_t)a * n_rings].rho < tmpl[(int64_t)b * n_rings].rho;
+    });
+    build_groups(per, order, bucket, bp);
+    return OSS_OK;
+}
+
+// Plan of caller-given interval probes (bounds in feature order).
+static int make_interval_plan(const oss_ref *ref, int32_t n_tmpl, const oss_interval_probe *probes,
+                              int32_t n_probes, uint32_t fm, int bucket, BatchHostPlan &bp)
+{
+    int slot_of[3];
+    slots_of(ref->feat_mask, slot_of);
+    std::vector<std::vector<PlanEntry>> per(n_tmpl);
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_interval_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
+            return OSS_E_ARG;
+        PlanEntry e{};
+        e.r = p.r;
+        e.k = p.scale_id;
+        e.ring = 0;
+        for (int q = 0; q < 3; ++q) {
+            e.lo[q] = INT64_MIN;
+            e.hi[q] = INT64_MAX;
+        }
+        for (int f = 0; f < 3; ++f) {
+            if (!(fm & (1u << f)))
+                continue;
+            e.lo[slot_of[f]] = p.lo[f];
+            e.hi[slot_of[f]] = p.hi[f];
+        }
+        per[p.template_id].push_back(e);
+    }
+    std::vector<int> order(n_tmpl);
+    for (int t = 0; t < n_tmpl; ++t)
+        order[t] = t;
+    bp.rings = 1;
+    build_groups(per, order, bucket, bp);
     return OSS_OK;
 }
 
@@ -1157,5 +1237,198 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
         if (launch_region_or(hit, H, W, R, Wp, dev_region + (int64_t)t * H * W, st) != hipSuccess)
             return OSS_E_DEVICE;
     }
+    return OSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Interval probes and Algorithm 1's template side.
+// ---------------------------------------------------------------------------
+extern "C" int oss_screen_intervals(oss_ctx *ctx, const oss_ref *ref, int32_t n_tmpl,
+                                    const oss_interval_probe *probes, int32_t n_probes,
+                                    uint32_t feat_mask, uint8_t *dev_mask,
+                                    oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                                    void *stream)
+{
+    if (!ctx || !ref || n_tmpl <= 0 || n_probes < 0 || (n_probes > 0 && !probes) ||
+        !dev_count || list_cap < 0 || (list_cap > 0 && !dev_list))
+        return OSS_E_ARG;
+    if (ref->ctx != ctx)
+        return OSS_E_STATE;
+    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask))
+        return OSS_E_ARG;
+    BatchHostPlan bp;
+    int rc = make_interval_plan(ref, n_tmpl, probes, n_probes, feat_mask, ctx->batch_bucket, bp);
+    if (rc != OSS_OK)
+        return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
+    rc = screen_workspace(ctx, n);
+    if (rc != OSS_OK)
+        return rc;
+    PlanSlot *slot = nullptr;
+    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
+                       ctx->cws, st, &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
+    return OSS_OK;
+}
+
+namespace {
+
+uint64_t isqrt_u64(unsigned __int128 v)
+{
+    uint64_t x = (uint64_t)std::sqrt((long double)v);
+    while ((unsigned __int128)x * x > v)
+        --x;
+    while ((unsigned __int128)(x + 1) * (x + 1) <= v)
+        ++x;
+    return x;
+}
+
+// floor(a / (d sqrt2^e)) and its ceiling, a >= 0, d > 0: exact (an odd
+// power leaves sqrt(2 a^2), irrational for a > 0, so never an integer).
+int64_t floor_sqrt2(int64_t a, int64_t d, int e)
+{
+    if (e % 2 == 0)
+        return a / (d << (e / 2));
+    return (int64_t)(isqrt_u64((unsigned __int128)2 * a * a) / (uint64_t)(d << ((e + 1) / 2)));
+}
+
+int64_t ceil_sqrt2(int64_t a, int64_t d, int e)
+{
+    if (e % 2 == 0) {
+        const int64_t den = d << (e / 2);
+        return (a + den - 1) / den;
+    }
+    return a == 0 ? 0 : floor_sqrt2(a, d, e) + 1;
+}
+
+// Bilinear n x n -> k x k, pixel centres aligned, edges replicated, rounded
+// half up; weights in units of 1/(2k), exact integers.
+void resize_square(const std::vector<int64_t> &src, int n, int k, std::vector<uint16_t> &dst)
+{
+    std::vector<int> i0(k), i1(k);
+    std::vector<int64_t> w(k);
+    const int64_t D = 2 * (int64_t)k;
+    for (int i = 0; i < k; ++i) {
+        const int64_t num = (2 * (int64_t)i + 1) * n - k;  // source coordinate times 2k
+        int64_t x0 = 0, wx = 0;
+        if (num >= 0) {
+            x0 = num / D;
+            wx = num % D;
+        }
+        if (x0 >= n - 1) {
+            x0 = n - 1;
+            wx = 0;
+        }
+        i0[i] = (int)x0;
+        i1[i] = (int)std::min<int64_t>(x0 + 1, n - 1);
+        w[i] = wx;
+    }
+    dst.assign((size_t)k * k, 0);
+    const int64_t den = D * D;
+    for (int y = 0; y < k; ++y) {
+        for (int x = 0; x < k; ++x) {
+            const int64_t t0 = (D - w[x]) * src[(size_t)i0[y] * n + i0[x]] +
+                               w[x] * src[(size_t)i0[y] * n + i1[x]];
+            const int64_t t1 = (D - w[x]) * src[(size_t)i1[y] * n + i0[x]] +
+                               w[x] * src[(size_t)i1[y] * n + i1[x]];
+            const int64_t v = (D - w[y]) * t0 + w[y] * t1;
+            dst[(size_t)y * k + x] = (uint16_t)((2 * v + den) / (2 * den));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int oss_alg1_probes(const void *host_pixels, const oss_image_desc *desc, int32_t t,
+                               const oss_alg1_params *p, oss_interval_probe *out, int32_t cap,
+                               int32_t *n_out)
+{
+    if (!host_pixels || !desc_ok(desc) || !p || !n_out || cap < 0 || (cap > 0 && !out) ||
+        t < 0 || desc->H != desc->W || p->alpha_num <= 0 || p->alpha_den <= 0 ||
+        p->beta_num <= 0 || p->beta_den <= 0 || p->feat_mask == 0 ||
+        (p->feat_mask & ~OSS_F_ALL))
+        return OSS_E_ARG;
+    // alpha <= beta
+    if ((int64_t)p->alpha_num * p->beta_den > (int64_t)p->beta_num * p->alpha_den)
+        return OSS_E_ARG;
+    for (int f = 0; f < 3; ++f)
+        if ((p->feat_mask & (1u << f)) && p->q[f] <= 0)
+            return OSS_E_ARG;
+    const int n = desc->W;
+    // B: smallest with 2^B (alpha_num beta_den)^2 >= (beta_num alpha_den)^2
+    const __int128 num2 = (__int128)p->beta_num * p->alpha_den * p->beta_num * p->alpha_den;
+    const __int128 den2 = (__int128)p->alpha_num * p->beta_den * p->alpha_num * p->beta_den;
+    int B = 0;
+    while (((__int128)den2 << B) < num2) {
+        if (++B > OSS_MAX_SCALES)
+            return OSS_E_ARG;
+    }
+    // the template as int64 pixels
+    std::vector<int64_t> px((size_t)n * n);
+    const unsigned char *base = static_cast<const unsigned char *>(host_pixels);
+    for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) {
+            const unsigned char *row = base + (int64_t)y * desc->pitch_bytes;
+            if (desc->dtype == OSS_U8) {
+                px[(size_t)y * n + x] = row[x];
+            } else {
+                uint16_t v;
+                std::memcpy(&v, row + 2 * (int64_t)x, 2);
+                px[(size_t)y * n + x] = v;
+            }
+        }
+    const int64_t a = (int64_t)p->beta_num * n, d = p->beta_den;  // beta n = a / d
+    std::vector<oss_interval_probe> res;
+    std::vector<uint16_t> Y;
+    for (int b = 0; b < B; ++b) {
+        const int64_t k_lo = ceil_sqrt2(a, d, b + 1), k_hi = floor_sqrt2(a, d, b);
+        const int m = (int)k_lo;
+        if (m < 1)
+            continue;
+        const int r = (m - 1) / 2;
+        const int64_t A = star_area(r);
+        const size_t band_first = res.size();
+        for (int64_t k = k_lo; k <= k_hi; ++k) {
+            resize_square(px, n, (int)k, Y);
+            oss_image_desc yd{(int32_t)k, (int32_t)k, 2 * k, OSS_U16, 16};
+            const int c = (int)((k - m) / 2 + (m - 1) / 2);
+            int64_t F[3];
+            star_feats_at(Y.data(), &yd, c, c, r, p->feat_mask, F);
+            oss_interval_probe pr{};
+            pr.template_id = t;
+            pr.scale_id = b;
+            pr.r = r;
+            for (int f = 0; f < 3; ++f) {
+                pr.lo[f] = INT64_MIN;
+                pr.hi[f] = INT64_MAX;
+                if (!(p->feat_mask & (1u << f)))
+                    continue;
+                const int64_t q = (int64_t)p->q[f] * A;
+                const int64_t c0 = F[f] / q;  // F >= 0: floor(F / q)
+                pr.lo[f] = q * c0 - q / 2;
+                pr.hi[f] = q * (c0 + 2) - q / 2 - 1;
+            }
+            bool dup = false;
+            for (size_t i = band_first; i < res.size() && !dup; ++i)
+                dup = std::memcmp(res[i].lo, pr.lo, sizeof(pr.lo)) == 0 &&
+                      std::memcmp(res[i].hi, pr.hi, sizeof(pr.hi)) == 0;
+            if (!dup)
+                res.push_back(pr);
+        }
+    }
+    *n_out = (int32_t)res.size();
+    if ((int64_t)res.size() > cap)
+        return OSS_E_NOMEM;
+    std::copy(res.begin(), res.end(), out);
     return OSS_OK;
 }

@@ -169,3 +169,52 @@ def test_region_argument_errors(lib):
     pr = (lib.oss_probe * 1)(lib.oss_probe(0, 0, 3))
     dummy = C.c_void_p(1)
     assert L.oss_region(None, 8, 8, 1, pr, 1, dummy, 1, dummy, dummy, None) == lib.OSS_E_ARG
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_alg1_probes_match_oracle_membership(lib, seed):
+    """The library's Algorithm 1 template side (resize, crop, star features,
+    quantiser, marking) gives, band by band, exactly the oracle's marked
+    cells: each probe box is the product of two cells per feature."""
+    from fractions import Fraction as Fr
+    from itertools import product
+
+    from oracle import alg1
+    rng = np.random.default_rng(60 + seed)
+    n = int(rng.integers(9, 30))
+    depth = 8 if seed != 2 else 12
+    img = rng.integers(0, 2 ** depth, (n, n)).astype(np.uint8 if depth == 8 else np.uint16)
+    fm = (7, 3, 5)[seed]
+    qbar = (3, 150, 4) if depth == 8 else (40, 40000, 60)
+    alpha, beta = (Fr(1, 2), Fr(2)) if seed != 1 else (Fr(3, 4), Fr(3, 2))
+    probes = lib.oss_alg1_probes(img, 5, alpha, beta, qbar, fm, bit_depth=depth)
+    want = alg1.membership(img, alpha, beta, qbar, fm)
+    feats = [f for f in range(3) if fm & (1 << f)]
+    assert {p.scale_id for p in probes} <= set(range(len(want)))
+    for b, (r, q, marked) in enumerate(want):
+        got = set()
+        for p in probes:
+            if p.scale_id != b:
+                continue
+            assert p.template_id == 5 and p.r == r
+            cells = []
+            for f in feats:
+                lo_c, hi_c = alg1.quantise(p.lo[f], q[f]), alg1.quantise(p.hi[f], q[f])
+                assert hi_c == lo_c + 1
+                # the bounds are the box's exact edges
+                assert alg1.quantise(p.lo[f] - 1, q[f]) == lo_c - 1
+                assert alg1.quantise(p.hi[f] + 1, q[f]) == hi_c + 1
+                cells.append((lo_c, hi_c))
+            got.update(product(*cells))
+        assert got == marked, (b, len(got), len(marked))
+
+
+def test_alg1_argument_errors(lib):
+    from fractions import Fraction as Fr
+    img = np.zeros((9, 9), np.uint8)
+    for kw in (dict(alpha=Fr(2), beta=Fr(1, 2), q=(1, 1, 1)),
+               dict(alpha=Fr(1, 2), beta=Fr(2), q=(0, 1, 1))):
+        with pytest.raises(lib.OssError):
+            lib.oss_alg1_probes(img, 0, kw["alpha"], kw["beta"], kw["q"], 7)
+    with pytest.raises(lib.OssError):
+        lib.oss_alg1_probes(np.zeros((9, 8), np.uint8), 0, Fr(1, 2), Fr(2), (1, 1, 1), 7)
