@@ -66,6 +66,9 @@ def _declare(lib):
                                         C.c_int64, i32p, C.c_int, i64p, i32p, C.c_int, C.c_int,
                                         C.c_int, i32p, C.c_int, u32p]
     lib.oracle_screen_rings.restype = C.c_int
+    lib.oracle_moments.argtypes = [u16p, C.c_int, C.c_int, C.c_int64, i32p, i32p, C.c_int64,
+                                   C.c_int, i64p]
+    lib.oracle_moments.restype = None
     return lib
 
 

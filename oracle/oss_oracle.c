@@ -285,3 +285,44 @@ int oracle_screen_rings(const uint16_t *img, const int32_t *G, int H, int W, int
     }
     return 0;
 }
+
+/*
+ * The paper's own patch features over the star (Sec. "Patch Features":
+ * mean, Eq. S_sigma variance, and the horizontal / vertical gradients as
+ * inner products with the extended Prewitt ramps, Eq. T_x; Sec. "Rotation
+ * Invariance": their magnitude).  For n positions and radius r, F is
+ * [n][4] = (sum I, sum I^2, sum (i - x) I, sum (j - y) I) over the star with
+ * its 0/1/2 weights, summed pixel by pixel; -1 ... when the star does not
+ * fit (slot 0 = -1 marks it).
+ */
+void oracle_moments(const uint16_t *img, int H, int W, int64_t stride, const int32_t *xs,
+                    const int32_t *ys, int64_t n, int r, int64_t *F)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        int x = xs[i], y = ys[i];
+        int64_t *o = F + 4 * i;
+        if (x < r || x > W - 1 - r || y < r || y > H - 1 - r) {
+            o[0] = o[1] = o[2] = o[3] = -1;
+            continue;
+        }
+        int s = oracle_square_half(r);
+        int64_t f1 = 0, f2 = 0, mx = 0, my = 0;
+        for (int dy = -r; dy <= r; dy++) {
+            for (int dx = -r; dx <= r; dx++) {
+                int w = weight_rs(dx, dy, r, s);
+                if (!w)
+                    continue;
+                int64_t v = img[(int64_t)(y + dy) * stride + x + dx];
+                f1 += w * v;
+                f2 += (int64_t)w * v * v;
+                mx += (int64_t)w * dx * v;
+                my += (int64_t)w * dy * v;
+            }
+        }
+        o[0] = f1;
+        o[1] = f2;
+        o[2] = mx;
+        o[3] = my;
+    }
+}

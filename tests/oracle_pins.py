@@ -366,6 +366,73 @@ def check_alg1(lib):
     assert bits[0].astype(bool).sum() < 0.2 * bits[0].size
 
 
+def _star_pixels(r):
+    """(dx, dy, weight) over the enumerator's square and diamond sets."""
+    w = {}
+    for dx, dy in en.square_pixels(r) + en.diamond_pixels(r):
+        w[(dx, dy)] = w.get((dx, dy), 0) + 1
+    return [(dx, dy, v) for (dx, dy), v in w.items()]
+
+
+def check_moments(lib):
+    """The paper's features over the star: first moments against the extended
+    Prewitt ramps (correlation with the weighted ramp kernels and a linear
+    ramp's closed form), their magnitude under quarter turns, and the three
+    tests on hand cases and exact cuts."""
+    from oracle import moments as om
+    # closed form on a linear ramp I = a x + b y + c: Sx = a sum w dx^2, Sy = b sum w dy^2
+    H, W, a, b, c = 40, 44, 3, 2, 7
+    yy, xx = np.mgrid[0:H, 0:W]
+    img = (a * xx + b * yy + c).astype(np.uint16)
+    for r in (2, 5, 9):
+        pix = _star_pixels(r)
+        sxx = sum(v * dx * dx for dx, dy, v in pix)
+        syy = sum(v * dy * dy for dx, dy, v in pix)
+        A = sum(v for _, _, v in pix)
+        F = om.moments(img, [20], [19], r, lib)[0]
+        assert F[0] == A * (a * 20 + b * 19 + c)
+        assert F[1] == sum(v * (a * (20 + dx) + b * (19 + dy) + c) ** 2 for dx, dy, v in pix)
+        assert F[2] == a * sxx and F[3] == b * syy, (r, F)
+    # correlation with the weighted ramp kernels (scipy), random image
+    img = _rand_img((23, 27), 41)
+    for r in (1, 3, 6):
+        kx = np.zeros((2 * r + 1, 2 * r + 1), np.int64)
+        ky = np.zeros_like(kx)
+        for dx, dy, v in _star_pixels(r):
+            kx[dy + r, dx + r] = v * dx
+            ky[dy + r, dx + r] = v * dy
+        ys, xs = np.mgrid[r:23 - r, r:27 - r]
+        F = om.moments(img, xs.ravel(), ys.ravel(), r, lib)
+        assert (F[:, 2] == correlate2d(img.astype(np.int64), kx, "valid").ravel()).all()
+        assert (F[:, 3] == correlate2d(img.astype(np.int64), ky, "valid").ravel()).all()
+    # quarter turn: the moment vector turns, its length stays
+    rot = np.rot90(img).copy()
+    F0 = om.moments(img, [12], [10], 4, lib)[0]
+    # pixel (x, y) of img lands at (y, W-1-x) of rot90 (counter-clockwise)
+    F1 = om.moments(rot, [10], [27 - 1 - 12], 4, lib)[0]
+    assert F0[0] == F1[0] and F0[1] == F1[1]
+    assert F0[2] ** 2 + F0[3] ** 2 == F1[2] ** 2 + F1[3] ** 2
+    assert (F1[2], F1[3]) == (F0[3], -F0[2])
+    # tests at r = rho reduce to relative differences of the raw values
+    FT = (1000, 5000, 30, 40)  # V_T = A F2 - F1^2, M_T = 2500
+    ok = om.probe_pass((1049, 5000, 30, 40), FT, 4, 4, (5, 100, 100), 100, om.MEAN, lib)
+    assert ok and not om.probe_pass((1051, 5000, 30, 40), FT, 4, 4, (5, 100, 100), 100, om.MEAN,
+                                    lib)
+    assert om.probe_pass((1000, 5000, 30, 40), FT, 4, 4, (0, 0, 0), 1, 7, lib)
+    assert om.probe_pass((1000, 5000, 40, 30), FT, 4, 4, (0, 0, 0), 1, om.MAG, lib)
+    assert not om.probe_pass((1000, 5000, 41, 30), FT, 4, 4, (0, 0, 0), 1, om.MAG, lib)
+    # magnitude 10% tolerance: |m - 50| <= 5 with m^2 = 55^2 passes, 55^2 + 1 fails
+    assert om.probe_pass((1000, 5000, 55, 0), FT, 4, 4, (0, 0, 10), 100, om.MAG, lib)
+    assert not om.probe_pass((1000, 5000, 55, 1), FT, 4, 4, (0, 0, 10), 100, om.MAG, lib)
+    # exact cuts survive at their centre with every test at P = 0
+    from synth import blob_image, make_rng, cut_patch
+    img = blob_image(90, 96, make_rng(95, 0), blobs_per_512sq=1500, sig_hi=10)
+    tm = cut_patch(img, 45, 40, 12)
+    bits = om.screen_full(img[25:56, 30:62], [(tm, 11)], [(0, 0, 11)], (0, 0, 0), 1, 7, lib)
+    assert bits[0, 40 - 25, 45 - 30] == 1 and bits.sum() < 5
+
+
 ALL_CHECKS = [check_half_width_and_area, check_golden_7x7, check_enumerator, check_correlate,
               check_closed_forms, check_d4, check_compare, check_planted_exact,
-              check_rings_brute_force, check_rings_consistency, check_region, check_alg1]
+              check_rings_brute_force, check_rings_consistency, check_region, check_alg1,
+              check_moments]

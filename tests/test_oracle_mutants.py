@@ -31,6 +31,8 @@ MUTANTS = {
     "area_factor_swapped": ("i128 x_ref = (i128)F * area_rho * c_ref;",
                             "i128 x_ref = (i128)F * area_r * c_ref;"),
     "tolerance_sign": ("i128 lhs = (i128)(Q - P) * x_t;", "i128 lhs = (i128)(Q + P) * x_t;"),
+    "moment_axes_swapped": ("mx += (int64_t)w * dx * v;", "mx += (int64_t)w * dy * v;"),
+    "moment_unweighted": ("my += (int64_t)w * dy * v;", "my += (int64_t)dy * v;"),
     "ring_radius_halved": ("rj = oracle_square_half(rj);", "rj = rj / 2;"),
     "ring_template_outer_radius": ("int rho_j = rho[t * n_rings + j];",
                                    "int rho_j = rho[t * n_rings];"),
