@@ -72,6 +72,15 @@ extern "C" {
 #define OSS_F_SQ 2u
 #define OSS_F_GRAD 4u
 #define OSS_F_ALL 7u
+/* first moments sum (i - x) I and sum (j - y) I of the star (the extended
+ * Prewitt ramps of Sec. "Patch Features"); table quantities i I and j I.
+ * A reference holds both or neither, and with them OSS_F_SUM: the feature
+ * sets with moments are SUM|XMOM|YMOM and SUM|SQ|XMOM|YMOM.  Only
+ * oss_screen_moments uses them. */
+#define OSS_F_XMOM 8u
+#define OSS_F_YMOM 16u
+#define OSS_F_MOMENTS 24u
+#define OSS_MAX_QUANTITIES 5
 
 #define OSS_MAX_SCALES 32 /* scale ids 0..31 per template (bits of a uint32) */
 
@@ -230,7 +239,8 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
 
 /*
  * Layout of the tables of `ref` (L, R and R' share it): quantity slot q
- * (feature order: sum, squares, gradient, enabled ones only) of entry
+ * (feature order: sum, squares, gradient, x and y moments, enabled ones
+ * only) of entry
  * (x, y) is the bits[q]-wide value (32: stored modulo 2^32, 64: two's
  * complement) at byte ((y+1) * pitch_entries + (x+1)) * entry_stride +
  * offset[q] of the table; slots q >= nq get offset -1, width 0.  Interleaved
@@ -239,8 +249,8 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
  * quantities at 8 and 12); planar tables (OSS_OPT_TABLE_PLANAR) have
  * entry_stride 4 and one plane per quantity at offset q * plane bytes.
  */
-int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[3],
-                   int32_t bits[3]);
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
+                   int32_t bits[OSS_MAX_QUANTITIES]);
 
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the
@@ -398,6 +408,48 @@ typedef struct oss_alg1_params {
 int oss_alg1_probes(const void *host_pixels, const oss_image_desc *desc, int32_t t,
                     const oss_alg1_params *params, oss_interval_probe *out, int32_t cap,
                     int32_t *n_out);
+
+/* ------------------------------------------------------------------------
+ * The paper's own features (Sec. "Patch Features": mean, Eq. S_sigma
+ * variance, gradients as inner products with the extended Prewitt ramps;
+ * Sec. "Rotation Invariance": the gradient magnitude), over the star.
+ * ------------------------------------------------------------------------ */
+#define OSS_T_MEAN 1u
+#define OSS_T_VAR 2u
+#define OSS_T_MAG 4u
+
+/* Star sums at the template centre (as oss_template_features): F1 = sum w I,
+ * F2 = sum w I^2, Sx = sum w (i - x) I, Sy = sum w (j - y) I, radius rho. */
+typedef struct oss_template_mom {
+    int64_t F1, F2, Sx, Sy;
+    int32_t rho, pad;
+} oss_template_mom;
+
+/* Template moments at radius rho (rho < 0: the largest that fits).  Host,
+ * synchronous. */
+int oss_template_moments(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
+                         oss_template_mom *out);
+
+/*
+ * Screen with the paper's features: a position passes probe (t, k, r) where
+ * the radius-r star fits and each test in `tests` passes, with A = the
+ * star's weighted area, N(r) = r A(r), V = A F2 - F1^2 (A^2 times the
+ * variance) and M = Sx^2 + Sy^2 (the squared gradient magnitude), rho the
+ * template's radius and P = tol->P[0..2] for mean, variance, magnitude:
+ *   OSS_T_MEAN  (Q-P) FT1 A(r)     <= Q F1 A(rho)     <= (Q+P) FT1 A(r)
+ *   OSS_T_VAR   (Q-P) VT A(r)^2    <= Q V A(rho)^2    <= (Q+P) VT A(r)^2
+ *   OSS_T_MAG   (Q-P)^2 MT N(r)^2  <= Q^2 M N(rho)^2  <= (Q+P)^2 MT N(r)^2
+ * (the magnitude's lower bound is void when P > Q), all exact.  The
+ * reference must hold OSS_F_SUM and the moments, and OSS_F_SQ for the
+ * variance.  OSS_E_OVERFLOW when a magnitude bound exceeds 128 bits.
+ * Outputs, ownership and errors otherwise as oss_screen (one launch per
+ * template).
+ */
+int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_template_mom *tmpl,
+                       int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                       const oss_tolerance *tol, uint32_t tests, uint8_t *dev_mask,
+                       oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                       void *stream);
 
 #define OSS_TUNE_MAX 64
 /* Autotuner result: the chosen shape, its time, and every candidate tried

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liboss.so")
 OSS_OK, OSS_E_ARG, OSS_E_NOMEM, OSS_E_OVERFLOW, OSS_E_DEVICE, OSS_E_STATE = 0, -1, -2, -3, -4, -5
 OSS_U8, OSS_U16 = 0, 1
 OSS_F_SUM, OSS_F_SQ, OSS_F_GRAD, OSS_F_ALL = 1, 2, 4, 7
+OSS_F_XMOM, OSS_F_YMOM, OSS_F_MOMENTS = 8, 16, 24
+OSS_MAX_QUANTITIES = 5
+OSS_T_MEAN, OSS_T_VAR, OSS_T_MAG = 1, 2, 4
 OSS_MAX_SCALES = 32
 
 EXPORTED = [
@@ -25,7 +28,7 @@ EXPORTED = [
     "oss_ref_build", "oss_ref_release", "oss_ref_tables", "oss_template_features",
     "oss_feature_bounds", "oss_screen", "oss_ctx_profile", "oss_ctx_profile_read",
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
-    "oss_ref_layout", "oss_region", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
+    "oss_ref_layout", "oss_region", "oss_template_moments", "oss_screen_moments", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
@@ -75,6 +78,11 @@ class oss_interval_probe(C.Structure):
 class oss_alg1_params(C.Structure):
     _fields_ = [("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("beta_num", C.c_int32),
                 ("beta_den", C.c_int32), ("q", C.c_int32 * 3), ("feat_mask", C.c_uint32)]
+
+
+class oss_template_mom(C.Structure):
+    _fields_ = [("F1", C.c_int64), ("F2", C.c_int64), ("Sx", C.c_int64), ("Sy", C.c_int64),
+                ("rho", C.c_int32), ("pad", C.c_int32)]
 
 
 class oss_server_config(C.Structure):
@@ -155,6 +163,11 @@ def load(path: str | None = None):
     lib.oss_alg1_probes.argtypes = [vp, C.POINTER(oss_image_desc), i32,
                                     C.POINTER(oss_alg1_params), C.POINTER(oss_interval_probe),
                                     i32, C.POINTER(i32)]
+    lib.oss_template_moments.argtypes = [vp, C.POINTER(oss_image_desc), i32,
+                                         C.POINTER(oss_template_mom)]
+    lib.oss_screen_moments.argtypes = [vp, vp, C.POINTER(oss_template_mom), i32,
+                                       C.POINTER(oss_probe), i32, C.POINTER(oss_tolerance), u32,
+                                       vp, vp, i64, vp, vp]
     lib.oss_region.argtypes = [vp, i32, i32, i32, C.POINTER(oss_probe), i32, vp, i64, vp, vp, vp]
     lib.oss_template_features_rings.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32, i32,
                                                 C.POINTER(oss_template_feat)]
@@ -297,10 +310,10 @@ def oss_ref_release(ref: int):
 def oss_ref_layout(ref: int):
     """(entry_stride, [(offset, bits) per quantity slot])."""
     eb = C.c_int32()
-    off = (C.c_int64 * 3)()
-    bits = (C.c_int32 * 3)()
+    off = (C.c_int64 * OSS_MAX_QUANTITIES)()
+    bits = (C.c_int32 * OSS_MAX_QUANTITIES)()
     _check(load().oss_ref_layout(ref, C.byref(eb), off, bits), "oss_ref_layout")
-    return eb.value, [(off[q], bits[q]) for q in range(3) if bits[q]]
+    return eb.value, [(off[q], bits[q]) for q in range(OSS_MAX_QUANTITIES) if bits[q]]
 
 
 def oss_ref_tables(ref: int):
@@ -501,3 +514,30 @@ def oss_screen_intervals(ctx: int, ref: int, n_tmpl: int, probes, feat_mask: int
     _check(load().oss_screen_intervals(ctx, ref, int(n_tmpl), pa, npb, int(feat_mask),
                                        _ptr(mask), _ptr(cand_list), int(list_cap), _ptr(count),
                                        _stream(stream)), "oss_screen_intervals")
+
+
+# --- the paper's own features ---------------------------------------------------------
+
+def oss_template_moments(pixels, rho: int, bit_depth: int | None = None) -> oss_template_mom:
+    a = np.ascontiguousarray(pixels)
+    out = oss_template_mom()
+    d = desc_of(a, bit_depth)
+    _check(load().oss_template_moments(a.ctypes.data, C.byref(d), int(rho), C.byref(out)),
+           "oss_template_moments")
+    return out
+
+
+def oss_screen_moments(ctx: int, ref: int, tmpl, probes, tol, tests: int, mask=None,
+                       cand_list=None, list_cap: int = 0, count=None, stream=None):
+    nt = len(tmpl)
+    ta = (oss_template_mom * nt)(*tmpl)
+    npb = len(probes)
+    pa = (oss_probe * max(1, npb))(*[oss_probe(int(t), int(k), int(r)) for t, k, r in probes])
+    if not isinstance(tol, oss_tolerance):
+        P0, P1, P2, Q = tol
+        tol = oss_tolerance((C.c_int32 * 3)(int(P0), int(P1), int(P2)), int(Q))
+    if count is None:
+        raise ValueError("count tensor required")
+    _check(load().oss_screen_moments(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(tests),
+                                     _ptr(mask), _ptr(cand_list), int(list_cap), _ptr(count),
+                                     _stream(stream)), "oss_screen_moments")

@@ -216,6 +216,13 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int p
                                    (__int128)2 * R * R + 2 * (__int128)R + 1);
     auto fits = [&](uint32_t m) { return max_quantity(d, m) * area < ((__int128)1 << 32); };
     const int nq = popc(fm);
+    if (fm & OSS_F_MOMENTS) {
+        // a region's first moment sum (i - x) I is at most maxv R |region| in
+        // magnitude: stored modulo 2^32 when that stays below 2^31
+        const __int128 maxv = ((__int128)1 << d->bit_depth) - 1;
+        const bool m32 = maxv * R * area < ((__int128)1 << 31);
+        return make_geom(d->H, d->W, nq, (fits(fm & OSS_F_ALL) && m32) ? 4 : 8);
+    }
     if (fits(fm))
         return make_geom(d->H, d->W, nq, 4, -1, planar);
     if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ))
@@ -223,9 +230,22 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int p
     return make_geom(d->H, d->W, nq, 8);
 }
 
+}  // extern "C"
+
+// Feature sets a reference may hold: any non-empty subset of sum, squares
+// and gradient, or the sum and both first moments (with or without squares).
+static bool ref_fm_ok(uint32_t fm)
+{
+    if (fm & OSS_F_MOMENTS)
+        return fm == (OSS_F_SUM | OSS_F_MOMENTS) || fm == (OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS);
+    return fm != 0 && !(fm & ~OSS_F_ALL);
+}
+
+extern "C" {
+
 int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_radius, size_t *out)
 {
-    if (!out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+    if (!out || !desc_ok(desc) || !ref_fm_ok(feat_mask))
         return OSS_E_ARG;
     // the larger of the interleaved and the planar layout
     const int32_t R = resolve_max_radius(desc, max_radius);
@@ -238,7 +258,7 @@ int oss_ref_bytes(const oss_image_desc *desc, uint32_t feat_mask, int32_t max_ra
 int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
                    int32_t max_radius, oss_ref **out)
 {
-    if (!ctx || !out || !desc_ok(desc) || feat_mask == 0 || (feat_mask & ~OSS_F_ALL))
+    if (!ctx || !out || !desc_ok(desc) || !ref_fm_ok(feat_mask))
         return OSS_E_ARG;
     *out = nullptr;
     if (!overflow_ok(desc, feat_mask))
@@ -320,14 +340,15 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
     return OSS_OK;
 }
 
-int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[3], int32_t bits[3])
+int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
+                   int32_t bits[OSS_MAX_QUANTITIES])
 {
     if (!ref || !entry_stride || !offset || !bits)
         return OSS_E_ARG;
     const BuildGeom &g = ref->geom;
     *entry_stride = g.tab_es;
     int j = 0;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < OSS_MAX_QUANTITIES; ++q) {
         offset[q] = -1;
         bits[q] = 0;
     }
@@ -648,7 +669,7 @@ static int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_templat
         return OSS_E_ARG;
     if (ref->ctx != ctx)
         return OSS_E_STATE;
-    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask))
+    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask) || (ref->feat_mask & OSS_F_MOMENTS))
         return OSS_E_ARG;
     if (tol->Q <= 0)
         return OSS_E_ARG;
@@ -1254,7 +1275,7 @@ extern "C" int oss_screen_intervals(oss_ctx *ctx, const oss_ref *ref, int32_t n_
         return OSS_E_ARG;
     if (ref->ctx != ctx)
         return OSS_E_STATE;
-    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask))
+    if (feat_mask == 0 || (feat_mask & ~ref->feat_mask) || (ref->feat_mask & OSS_F_MOMENTS))
         return OSS_E_ARG;
     BatchHostPlan bp;
     int rc = make_interval_plan(ref, n_tmpl, probes, n_probes, feat_mask, ctx->batch_bucket, bp);
@@ -1430,5 +1451,203 @@ extern "C" int oss_alg1_probes(const void *host_pixels, const oss_image_desc *de
     if ((int64_t)res.size() > cap)
         return OSS_E_NOMEM;
     std::copy(res.begin(), res.end(), out);
+    return OSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own features: template moments and the moments screen.
+// ---------------------------------------------------------------------------
+extern "C" int oss_template_moments(const void *host_pixels, const oss_image_desc *desc,
+                                    int32_t rho, oss_template_mom *out)
+{
+    if (!host_pixels || !out || !desc_ok(desc))
+        return OSS_E_ARG;
+    const int H = desc->H, W = desc->W;
+    const int cx = (W - 1) / 2, cy = (H - 1) / 2;
+    const int rmax = std::min(std::min(cx, W - 1 - cx), std::min(cy, H - 1 - cy));
+    if (rho < 0)
+        rho = rmax;
+    if (rho > rmax)
+        return OSS_E_ARG;
+    const unsigned char *base = static_cast<const unsigned char *>(host_pixels);
+    auto pix = [&](int x, int y) -> int64_t {
+        const unsigned char *row = base + (int64_t)y * desc->pitch_bytes;
+        if (desc->dtype == OSS_U8)
+            return row[x];
+        uint16_t v;
+        std::memcpy(&v, row + 2 * (int64_t)x, 2);
+        return v;
+    };
+    int64_t f1 = 0, f2 = 0, mx = 0, my = 0;
+    auto span = [&](int dy, int h) {  // the row cy + dy, columns cx - h .. cx + h
+        for (int dx = -h; dx <= h; ++dx) {
+            const int64_t v = pix(cx + dx, cy + dy);
+            f1 += v;
+            f2 += v * v;
+            mx += dx * v;
+            my += dy * v;
+        }
+    };
+    const int s = square_half(rho);
+    for (int dy = -s; dy <= s; ++dy)
+        span(dy, s);
+    for (int dy = -rho; dy <= rho; ++dy)
+        span(dy, rho - (dy < 0 ? -dy : dy));
+    out->F1 = f1;
+    out->F2 = f2;
+    out->Sx = mx;
+    out->Sy = my;
+    out->rho = rho;
+    out->pad = 0;
+    return OSS_OK;
+}
+
+namespace {
+
+using u128 = unsigned __int128;
+
+int64_t ceil_div_i128(__int128 a, __int128 b)  // b > 0
+{
+    __int128 q = a / b;
+    if (a % b != 0 && a > 0)
+        ++q;
+    return (int64_t)std::max<__int128>(INT64_MIN, std::min<__int128>(INT64_MAX, q));
+}
+
+int64_t floor_div_i128(__int128 a, __int128 b)  // b > 0
+{
+    __int128 q = a / b;
+    if (a % b != 0 && a < 0)
+        --q;
+    return (int64_t)std::max<__int128>(INT64_MIN, std::min<__int128>(INT64_MAX, q));
+}
+
+// a * b * c with a 128-bit overflow check (false on overflow)
+bool mul3(u128 a, u128 b, u128 c, u128 *out)
+{
+    const long double est = (long double)a * (long double)b * (long double)c;
+    if (est > 1.7e38L)
+        return false;
+    *out = a * b * c;
+    return true;
+}
+
+void put128(uint64_t w[2], u128 v)
+{
+    w[0] = (uint64_t)v;
+    w[1] = (uint64_t)(v >> 64);
+}
+
+}  // namespace
+
+extern "C" int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_template_mom *tmpl,
+                                  int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                                  const oss_tolerance *tol, uint32_t tests, uint8_t *dev_mask,
+                                  oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                                  void *stream)
+{
+    if (!ctx || !ref || !tmpl || n_tmpl <= 0 || n_probes < 0 || (n_probes > 0 && !probes) ||
+        !tol || !dev_count || list_cap < 0 || (list_cap > 0 && !dev_list))
+        return OSS_E_ARG;
+    if (ref->ctx != ctx)
+        return OSS_E_STATE;
+    if (!(ref->feat_mask & OSS_F_MOMENTS) || tests == 0 || (tests & ~7u) ||
+        ((tests & OSS_T_VAR) && !(ref->feat_mask & OSS_F_SQ)) || tol->Q <= 0)
+        return OSS_E_ARG;
+    for (int f = 0; f < 3; ++f)
+        if ((tests & (1u << f)) && tol->P[f] < 0)
+            return OSS_E_ARG;
+    for (int t = 0; t < n_tmpl; ++t)
+        if (tmpl[t].rho < 0 || tmpl[t].F1 < 0 || tmpl[t].F2 < 0)
+            return OSS_E_ARG;
+    std::vector<DevMomPlan> plans(n_tmpl, DevMomPlan{});
+    std::vector<std::vector<oss_probe>> per(n_tmpl);
+    for (int i = 0; i < n_probes; ++i) {
+        const oss_probe &p = probes[i];
+        if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
+            p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
+            return OSS_E_ARG;
+        per[p.template_id].push_back(p);
+        if ((int)per[p.template_id].size() > OSS_MAX_SCALES)
+            return OSS_E_ARG;
+    }
+    const __int128 Q = tol->Q;
+    for (int t = 0; t < n_tmpl; ++t) {
+        auto &v = per[t];
+        std::stable_sort(v.begin(), v.end(),
+                         [](const oss_probe &a, const oss_probe &b) { return a.r < b.r; });
+        const oss_template_mom &T = tmpl[t];
+        const __int128 A_rho = star_area(T.rho);
+        const __int128 VT = A_rho * T.F2 - (__int128)T.F1 * T.F1;
+        const u128 MT = (u128)((__int128)T.Sx * T.Sx) + (u128)((__int128)T.Sy * T.Sy);
+        const u128 N_rho = (u128)T.rho * (u128)A_rho;
+        DevMomPlan &pl = plans[t];
+        int nr = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            const int r = v[i].r;
+            if (nr == 0 || pl.radii[nr - 1].r != r) {
+                pl.radii[nr].r = r;
+                pl.radii[nr].s = square_half(r);
+                pl.radii[nr].first = (int32_t)i;
+                pl.radii[nr].count = 0;
+                ++nr;
+            }
+            pl.radii[nr - 1].count++;
+            DevMomProbe &dp = pl.probes[i];
+            dp.k = v[i].scale_id;
+            dp.tests = (int32_t)tests;
+            const __int128 A_r = star_area(r);
+            feature_bounds(0, T.F1, r, T.rho, tol->P[0], tol->Q, &dp.lo1, &dp.hi1);
+            // variance: (Q-P) VT A(r)^2 <= Q V A(rho)^2 <= (Q+P) VT A(r)^2
+            const __int128 den_v = Q * A_rho * A_rho;
+            dp.loV = ceil_div_i128((Q - tol->P[1]) * VT * A_r * A_r, den_v);
+            dp.hiV = floor_div_i128((Q + tol->P[1]) * VT * A_r * A_r, den_v);
+            // magnitude: (Q-P)^2 MT N(r)^2 <= Q^2 M N(rho)^2 <= (Q+P)^2 MT N(r)^2
+            const u128 N_r = (u128)r * (u128)A_r;
+            const u128 qp = (u128)(Q + tol->P[2]), qm = Q >= tol->P[2] ? (u128)(Q - tol->P[2]) : 0;
+            u128 hi_num = 0, lo_num = 0;
+            if (!mul3(qp * qp, MT, N_r * N_r, &hi_num) || !mul3(qm * qm, MT, N_r * N_r, &lo_num))
+                return OSS_E_OVERFLOW;
+            const long double den_est = (long double)(Q * Q) * (long double)N_rho *
+                                        (long double)N_rho;
+            if (den_est > 1.7e38L)
+                return OSS_E_OVERFLOW;
+            const u128 den_m = (u128)(Q * Q) * N_rho * N_rho;
+            if (den_m == 0) {
+                // rho = 0: the middle term is 0 whatever M is
+                const bool ok = lo_num == 0;
+                put128(dp.loM, ok ? 0 : 1);
+                put128(dp.hiM, ok ? ~(u128)0 : 0);
+            } else {
+                put128(dp.loM, lo_num / den_m + (lo_num % den_m != 0 ? 1 : 0));
+                put128(dp.hiM, hi_num / den_m);
+            }
+        }
+        pl.n_radii = nr;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return OSS_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BuildGeom &g = ref->geom;
+    const int64_t hw = (int64_t)g.H * g.W;
+    int rc = screen_workspace(ctx, hw * n_tmpl);
+    if (rc != OSS_OK)
+        return rc;
+    PlanSlot *slot = nullptr;
+    rc = upload_plan(ctx, plans.data(), plans.size() * sizeof(DevMomPlan), st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    const DevMomPlan *dplan = static_cast<const DevMomPlan *>(slot->dev);
+    const StarSweep sw = make_sweep(g.H, g.W, ctx->star_strip, ctx->star_blocks_per_xcd);
+    for (int t = 0; t < n_tmpl; ++t)
+        if (launch_star_moments(g, ref->feat_mask, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
+                                ctx->bits + hw * t, sw, st, &ctx->prof) != hipSuccess)
+            return OSS_E_DEVICE;
+    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
+                       ctx->cws, st, &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
     return OSS_OK;
 }

@@ -65,7 +65,8 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
 
 template <unsigned FM>
 struct Feat {
-    static constexpr int NQ = ((FM >> 0) & 1) + ((FM >> 1) & 1) + ((FM >> 2) & 1);
+    static constexpr int NQ = ((FM >> 0) & 1) + ((FM >> 1) & 1) + ((FM >> 2) & 1) +
+                              ((FM >> 3) & 1) + ((FM >> 4) & 1);
 };
 
 // ---------------------------------------------------------------------------
@@ -123,11 +124,12 @@ __device__ __forceinline__ uint64_t lane63<uint64_t>(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// q values of a pixel inside the image, in feature-bit order, from the
-// pixel c, its left / right neighbours l, r and the pixels above / below u,
-// d (neighbour indices clamped to the image).
+// q values of the pixel (x, y) inside the image, in feature-bit order, from
+// the pixel c, its left / right neighbours l, r and the pixels above / below
+// u, d (neighbour indices clamped to the image); the first moments' column
+// and row weights x c, y c are taken in T (modulo 2^32 for 32-bit tables).
 template <unsigned FM, typename T>
-__device__ __forceinline__ void quantities(int c, int l, int r, int u, int d, T *q)
+__device__ __forceinline__ void quantities(int c, int l, int r, int u, int d, int x, int y, T *q)
 {
     int slot = 0;
     if (FM & OSS_F_SUM)
@@ -138,6 +140,10 @@ __device__ __forceinline__ void quantities(int c, int l, int r, int u, int d, T 
         const int gx = r - l, gy = d - u;
         q[slot++] = (T)((gx < 0 ? -gx : gx) + (gy < 0 ? -gy : gy));
     }
+    if (FM & OSS_F_XMOM)
+        q[slot++] = (T)((uint64_t)x * (uint64_t)c);
+    if (FM & OSS_F_YMOM)
+        q[slot++] = (T)((uint64_t)y * (uint64_t)c);
 }
 
 template <typename Pix, unsigned FM, typename T>
@@ -155,7 +161,7 @@ __device__ __forceinline__ void load_q(const Pix *__restrict__ img, int64_t pitc
         u = img[(int64_t)yu * pitch + x];
         d = img[(int64_t)yd * pitch + x];
     }
-    quantities<FM, T>(c, l, r, u, d, q);
+    quantities<FM, T>(c, l, r, u, d, x, y, q);
 }
 
 // base P_y(X0 - 1) of a tile whose threads start at column X0 (a multiple of 64)
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
             const int yd = y + 1 < H ? y + 1 : H - 1;
             const Pix *nrow = img + (int64_t)yd * pitch;
             const int nl = nrow[xl], nc = nrow[x], nr = nrow[xr];
-            quantities<FM, T>(pc, pl, pr, pu, nc, s);
+            quantities<FM, T>(pc, pl, pr, pu, nc, x, y, s);
             pu = pc;
             pl = nl;
             pc = nc;
@@ -729,6 +735,8 @@ static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint
         }
     }
     switch (fm) {
+    case 25: return build_t<Pix, 25, T>(g, px, pb, bb, st, pr);
+    case 27: return build_t<Pix, 27, T>(g, px, pb, bb, st, pr);
     case 1: return build_t<Pix, 1, T>(g, px, pb, bb, st, pr);
     case 2: return build_t<Pix, 2, T>(g, px, pb, bb, st, pr);
     case 3: return build_t<Pix, 3, T>(g, px, pb, bb, st, pr);

@@ -148,6 +148,7 @@ enum KernelId {
     K_COMPACT_COUNT,
     K_COMPACT_SCAN,
     K_COMPACT_WRITE,
+    K_STAR_MOM,
     K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
@@ -226,6 +227,27 @@ hipError_t launch_region_scatter(const oss_candidate *list, int64_t list_cap,
                                  int pad, int64_t wp, uint8_t *ind, hipStream_t st);
 hipError_t launch_region_or(const uint32_t *hit, int H, int W, int pad, int64_t wp,
                             uint8_t *region, hipStream_t st);
+
+// The paper's own features (mean, variance, first-moment magnitude) per
+// probe: bounds on F1, on V = A(r) F2 - F1^2 and on M = Sx^2 + Sy^2 (128-bit
+// unsigned, low word first); tests = which of the three apply.
+struct DevMomProbe {
+    int64_t lo1, hi1;
+    int64_t loV, hiV;
+    uint64_t loM[2], hiM[2];
+    int32_t k, tests;
+};
+
+struct DevMomPlan {
+    int32_t n_radii;
+    int32_t pad;
+    DevRadius radii[OSS_MAX_SCALES];
+    DevMomProbe probes[OSS_MAX_SCALES];
+};
+
+hipError_t launch_star_moments(const BuildGeom &g, uint32_t fm, const void *L, const void *R,
+                               const void *Rp, const DevMomPlan *plan, uint32_t *bits,
+                               const StarSweep &sw, hipStream_t stream, Profiler *prof);
 
 hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
                           oss_candidate *list, int64_t list_cap, int64_t *count, void *workspace,

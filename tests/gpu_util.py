@@ -24,6 +24,12 @@ def quantities(img: np.ndarray, fm: int):
         out.append(a * a)
     if fm & 4:
         out.append(oc.gradient(img).astype(np.int64))
+    H, W = img.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    if fm & 8:
+        out.append(xx.astype(np.int64) * a)   # first-moment quantity i I
+    if fm & 16:
+        out.append(yy.astype(np.int64) * a)   # j I
     return out
 
 

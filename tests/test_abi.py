@@ -218,3 +218,26 @@ def test_alg1_argument_errors(lib):
             lib.oss_alg1_probes(img, 0, kw["alpha"], kw["beta"], kw["q"], 7)
     with pytest.raises(lib.OssError):
         lib.oss_alg1_probes(np.zeros((9, 8), np.uint8), 0, Fr(1, 2), Fr(2), (1, 1, 1), 7)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_template_moments_match_oracle(lib, seed):
+    from oracle import moments as om
+    rng = np.random.default_rng(70 + seed)
+    h, w = int(rng.integers(5, 40)), int(rng.integers(5, 40))
+    depth = (8, 12)[seed]
+    img = rng.integers(0, 2 ** depth, (h, w)).astype(np.uint8 if depth == 8 else np.uint16)
+    rmax = min((w - 1) // 2, w - 1 - (w - 1) // 2, (h - 1) // 2, h - 1 - (h - 1) // 2)
+    for rho in range(rmax + 1):
+        got = lib.oss_template_moments(img, rho, bit_depth=depth)
+        assert (got.F1, got.F2, got.Sx, got.Sy) == om.template_moments(img, rho)
+        assert got.rho == rho
+
+
+def test_moment_feature_sets(lib):
+    d = lib.image_desc(256, 256)
+    for fm in (25, 27):
+        assert lib.oss_ref_bytes(d, fm, 20) > 0
+    for fm in (8, 16, 24, 9, 17, 29, 31, 32):
+        with pytest.raises(lib.OssError):
+            lib.oss_ref_bytes(d, fm, 20)

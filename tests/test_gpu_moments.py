@@ -1,0 +1,79 @@
+"""GPU parity of the screen with the paper's own features (mean, variance,
+first-moment gradient magnitude; oss_screen_moments) with the oracle,
+element by element, on 8-bit (32-bit tables) and 12-bit (64-bit tables)
+workloads and for each test alone."""
+import numpy as np
+import pytest
+
+import oracle.core as oc
+from gpu_util import Runner, say
+from oracle import moments as om
+from synth import blob_image, cut_patch, make_rng, make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def runner():
+    r = Runner()
+    yield r
+    r.close()
+
+
+def _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r):
+    L = runner.L
+    torch = runner.torch
+    ref = runner.ctx.reference(L.device_image(img, runner.dev), fm, depth, max_radius=max_r)
+    tm = [L.oss_template_moments(px, rho, bit_depth=depth) for px, rho in templates]
+    T = len(tm)
+    H, W = img.shape
+    mask = torch.empty((T, H, W), dtype=torch.uint8, device=runner.dev)
+    cap = T * H * W
+    cands = torch.empty((cap, 4), dtype=torch.int32, device=runner.dev)
+    count = torch.zeros(1, dtype=torch.int64, device=runner.dev)
+    L.oss_screen_moments(runner.ctx.handle, ref.handle, tm, probes, tol, tests, mask, cands, cap,
+                         count)
+    torch.cuda.synchronize()
+    n = int(count.item())
+    c = cands[:n].cpu().numpy().astype(np.int64)
+    c[:, 3] &= 0xFFFFFFFF
+    out = mask.cpu().numpy(), c, n, ref.value_bits
+    ref.release()
+    return out
+
+
+def _check(runner, img, templates, probes, tol, tests, fm, depth, max_r):
+    mask, lst, n, vb = _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r)
+    want = om.screen_full(img, templates, probes, tol[:3], tol[3], tests)
+    wmask, wlist = oc.mask_and_list(want)
+    say(f"  moments tests={tests} fm={fm} {vb}-bit: {n} candidates (oracle {len(wlist)})")
+    assert n == len(wlist) and np.array_equal(mask, wmask) and np.array_equal(lst, wlist)
+    return n
+
+
+@pytest.mark.parametrize("tests", [1, 2, 4, 7])
+def test_moments_cfg2(runner, tests):
+    w = make_workload(2, 2, H=150, W=170, blobs_per_512sq=1200, sig_hi=20)
+    tms = [(t.pixels, t.rho) for t in w.templates]
+    probes = [p for p in w.probes if 2 * p[2] + 1 <= 150]
+    n = _check(runner, w.ref, tms, probes, (6, 30, 40, 100), tests, 27, 8,
+               max(p[2] for p in probes))
+    assert n > 0
+
+
+def test_moments_cfg5_64bit(runner):
+    w = make_workload(5, 3, H=230, W=250, n_templates=2, blobs_per_512sq=1200, sig_hi=20)
+    tms = [(t.pixels, t.rho) for t in w.templates]
+    probes = [p for p in w.probes if p[2] <= 60]
+    _check(runner, w.ref, tms, probes, (8, 40, 50, 100), 7, 27, 12, max(p[2] for p in probes))
+
+
+def test_moments_mean_and_magnitude_only(runner):
+    """Sum and moments only (no squares), exact cuts at P = 0 survive."""
+    img = blob_image(120, 140, make_rng(94, 0), blobs_per_512sq=1500, sig_hi=10)
+    tms = [(cut_patch(img, 60, 55, 12), 11), (cut_patch(img, 90, 70, 9, quarter_turns=1), 8)]
+    probes = [(0, 0, 11), (0, 1, 9), (1, 0, 8), (1, 2, 12)]
+    mask, lst, n, _ = _screen(runner, img, tms, probes, (0, 0, 0, 1), 5, 25, 8, 12)
+    want = om.screen_full(img, tms, probes, (0, 0, 0), 1, 5)
+    assert np.array_equal(lst, oc.mask_and_list(want)[1])
+    assert mask[0, 55, 60] == 1 and mask[1, 70, 90] == 1
