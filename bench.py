@@ -42,6 +42,7 @@ KERNEL_SOURCES = {
     "carry": "paper_1707_05647_amd/csrc/builder.hip",
     "star_plain": "paper_1707_05647_amd/csrc/star.hip",
     "star_batch": "paper_1707_05647_amd/csrc/batched.hip",
+    "star_moments": "paper_1707_05647_amd/csrc/moments.hip",
     "compact_count": "paper_1707_05647_amd/csrc/compact.hip",
     "compact_scan": "paper_1707_05647_amd/csrc/compact.hip",
     "compact_write": "paper_1707_05647_amd/csrc/compact.hip",
@@ -469,6 +470,9 @@ def main():
     ap.add_argument("--evaluate", type=int, default=-1,
                     help="1: preserved region, overlap with the planted ground truth and the 90%% "
                          "success criterion after the timed steps (default: on for workload 2)")
+    ap.add_argument("--moments", type=int, default=0,
+                    help="1: screen with the paper's own features (mean, variance, first-moment "
+                         "gradient magnitude) instead of sum / squares / gradient sum")
     ap.add_argument("--alg1", type=int, default=0,
                     help="1: screen with Algorithm 1 taken literally (sqrt 2 scale bands over "
                          "[1/2, 2], quantised membership) instead of the probe radii")
@@ -532,7 +536,8 @@ def main():
         max_r = max(p.r for t, tp in enumerate(w.templates)
                     for p in L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2),
                                                (1, 1, 1), w.feat_mask, bit_depth=w.depth))
-    ref = ctx.reference(img, w.feat_mask, w.depth, build=False, max_radius=max_r)
+    ref_fm = (L.OSS_F_SUM | L.OSS_F_SQ | L.OSS_F_MOMENTS) if args.moments else w.feat_mask
+    ref = ctx.reference(img, ref_fm, w.depth, build=False, max_radius=max_r)
     T = len(w.templates)
     # room for every candidate, so the sampled check sees a complete list
     cap = min(T * w.H * w.W, 1 << 22 if not big else 1_600_000_000)
@@ -566,8 +571,18 @@ def main():
             L.oss_screen_intervals(ctx.handle, ref.handle, T, pr, w.feat_mask, mask, cands, cap,
                                    count, stream)
 
+        MOM_TOL = (5, 30, 40, 100)
+
+        def step_moments():
+            tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
+            ref.build(stream)
+            L.oss_screen_moments(ctx.handle, ref.handle, tm, w.probes, MOM_TOL, 7, mask, cands,
+                                 cap, count, stream)
+
         if args.alg1:
             return step_alg1
+        if args.moments:
+            return step_moments
 
         def step():
             tm = tfeat()
@@ -619,6 +634,7 @@ def main():
     eb = ref.entry_bytes
     abytes = algorithmic_bytes(w.H, w.W, T, 2 if w.depth > 8 else 1, eb)
     abytes["star_batch"] = abytes["star_plain"]
+    abytes["star_moments"] = abytes["star_plain"]
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
             for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
@@ -677,6 +693,7 @@ def main():
             "launch": "batched" if (big or args.rings > 1) else "plain",
             "rings": args.rings,
             "alg1": bool(args.alg1),
+            "moments": bool(args.moments),
         },
         "roofline": roof,
         "kernels": kern,
@@ -686,7 +703,7 @@ def main():
     out.update(extra)
     if args.evaluate == 1 or (args.evaluate < 0 and args.workload == 2):
         out["evaluation"] = evaluate_regions(w, ctx, L, torch, dev, cands, count, cap)
-    if not args.no_cpu_baseline and not args.alg1:
+    if not args.no_cpu_baseline and not args.alg1 and not args.moments:
         out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds, args.rings)
     ref.release()
     ctx.close()
