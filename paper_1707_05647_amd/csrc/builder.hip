@@ -111,17 +111,36 @@ __device__ __forceinline__ T from_right(T v)
     return dpp<0x130, 0xf, false>(v);  // wave_shl:1
 }
 
+// value of lane `src` (wave-uniform) for every lane
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int src)
+{
+    return (T)__builtin_amdgcn_readlane((int)v, src);
+}
+template <>
+__device__ __forceinline__ uint64_t read_lane<uint64_t>(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T lane63(T v)
 {
-    return (T)__builtin_amdgcn_readlane((int)v, 63);
+    return read_lane(v, 63);
 }
-template <>
-__device__ __forceinline__ uint64_t lane63<uint64_t>(uint64_t v)
+
+// Sum of the first `n` (wave-uniform, 0 <= n <= 8) of eight per-wave values:
+// lane i < 8 holds value i (the others 0); a three-step prefix inside the
+// first row of 16 lanes, then lane n-1's prefix.  Every lane must be active.
+template <typename T>
+__device__ __forceinline__ T first_n_sum(T v_lane, int n)
 {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
-    return ((uint64_t)hi << 32) | lo;
+    v_lane += dpp<0x111, 0xf, true>(v_lane);  // row_shr:1
+    v_lane += dpp<0x112, 0xf, true>(v_lane);  // row_shr:2
+    v_lane += dpp<0x114, 0xf, true>(v_lane);  // row_shr:4
+    return n > 0 ? read_lane(v_lane, n - 1) : (T)0;
 }
 
 // q values of the pixel (x, y) inside the image, in feature-bit order, from
@@ -538,6 +557,7 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     constexpr int NQ = Feat<FM>::NQ;
     const int64_t plane_e = g.plane / (int64_t)sizeof(T);
     constexpr int NW = BAND_THREADS / 64;
+    static_assert(NW == 8, "first_n_sum adds eight wave totals");
     __shared__ T s_wt[2][NW][NQ];
     __shared__ T s_eta[2][NW][NQ];
     __shared__ T s_etd[2][NW][NQ];
@@ -608,9 +628,10 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
         T ta_r[NQ], td_l[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            T off = base ? base[q] : (T)0;
-            for (int w = 0; w < NW; ++w)
-                off += (w < wid) ? s_wt[buf][w][q] : (T)0;
+            // the row prefix of the tile start plus the totals of the waves
+            // to the left of this one
+            const T wt = lane < NW ? s_wt[buf][lane & (NW - 1)][q] : (T)0;
+            const T off = (base ? base[q] : (T)0) + first_n_sum(wt, wid);
             const T P = off + s[q];
             ta_r[q] = from_right(TA[q]);
             td_l[q] = from_left(TD[q]);
