@@ -146,13 +146,22 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                radii per pass (0: all radii of a template
  *                                group in one pass; default 0)
  *   OSS_OPT_TABLE_PLANAR         1: references created afterwards store each
- *                                quantity in a table plane of its own when
- *                                every quantity fits 32-bit storage, instead
- *                                of side by side in one entry; default 0
+ *                                quantity in a table plane of its own
+ *                                (default); 0: side by side in one entry.
+ *                                References with first moments are always
+ *                                interleaved
  *   OSS_OPT_STAR_PIPE            1: oss_screen's star pass issues the next
  *                                radius' lookups before comparing the
  *                                current one (software pipelining); the LDS
  *                                option takes precedence; default 0
+ *   OSS_OPT_STAR_STAGED          1: on planar tables the star passes of
+ *                                oss_screen, oss_screen_batched and the
+ *                                server look up the first feature quantity
+ *                                alone and the others only where some probe
+ *                                (batched: the radius' interval hull) admits
+ *                                it (default); 0: every quantity at every
+ *                                lookup.  The LDS and pipelining options
+ *                                take precedence
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
@@ -160,6 +169,7 @@ int oss_ctx_destroy(oss_ctx *ctx);
 #define OSS_OPT_BATCH_BUCKET 4
 #define OSS_OPT_TABLE_PLANAR 5
 #define OSS_OPT_STAR_PIPE 6
+#define OSS_OPT_STAR_STAGED 7
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 
@@ -246,11 +256,14 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
  * offset[q] of the table; slots q >= nq get offset -1, width 0.  Interleaved
  * entries are 4 * nq bytes (all 32-bit), 8 * nq bytes (all 64-bit) or 16
  * bytes when only the squares need 64 bits (squares at offset 0, the other
- * quantities at 8 and 12); planar tables (OSS_OPT_TABLE_PLANAR) have
- * entry_stride 4 and one plane per quantity at offset q * plane bytes.
+ * quantities at 8 and 12).  Planar tables (OSS_OPT_TABLE_PLANAR) hold one
+ * quantity per plane, *plane_bytes apart (0 for interleaved tables), with
+ * entry_stride = the value width; when only the squares need 64 bits every
+ * plane holds 32-bit values (entry_stride 4) and the squares take two: the
+ * low words at offset[q], the high words at offset[q] + *plane_bytes.
  */
 int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
-                   int32_t bits[OSS_MAX_QUANTITIES]);
+                   int32_t bits[OSS_MAX_QUANTITIES], int64_t *plane_bytes);
 
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the

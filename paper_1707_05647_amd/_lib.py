@@ -34,6 +34,7 @@ EXPORTED = [
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_OPT_TABLE_PLANAR = 5
 OSS_OPT_STAR_PIPE = 6
+OSS_OPT_STAR_STAGED = 7
 OSS_MAX_RINGS = 4
 OSS_TUNE_MAX = 64
 
@@ -146,7 +147,8 @@ def load(path: str | None = None):
     lib.oss_ref_tables.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                    C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(i32)]
-    lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]
+    lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
+                                   C.POINTER(i64)]
     lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
@@ -308,12 +310,14 @@ def oss_ref_release(ref: int):
 
 
 def oss_ref_layout(ref: int):
-    """(entry_stride, [(offset, bits) per quantity slot])."""
+    """(entry_stride, [(offset, bits) per quantity slot], plane_bytes)."""
     eb = C.c_int32()
     off = (C.c_int64 * OSS_MAX_QUANTITIES)()
     bits = (C.c_int32 * OSS_MAX_QUANTITIES)()
-    _check(load().oss_ref_layout(ref, C.byref(eb), off, bits), "oss_ref_layout")
-    return eb.value, [(off[q], bits[q]) for q in range(OSS_MAX_QUANTITIES) if bits[q]]
+    plane = C.c_int64()
+    _check(load().oss_ref_layout(ref, C.byref(eb), off, bits, C.byref(plane)), "oss_ref_layout")
+    return (eb.value, [(off[q], bits[q]) for q in range(OSS_MAX_QUANTITIES) if bits[q]],
+            plane.value)
 
 
 def oss_ref_tables(ref: int):

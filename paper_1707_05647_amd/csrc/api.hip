@@ -207,8 +207,10 @@ static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
 
 // A quantity can be stored modulo 2^32 when every square and every diamond
 // sum of it up to the maximum radius stays below 2^32.  All quantities fit:
-// 32-bit entries (interleaved, or planar on request).  Only the squares do
-// not: mixed 16-byte entries (squares in 64 bits).  Otherwise 64-bit entries.
+// 32-bit values.  Only the squares do not: the squares in 64 bits, the others
+// in 32.  Otherwise 64-bit values.  Planar (the default) or interleaved
+// entries as the context asks; references with first moments are always
+// interleaved.
 static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int planar)
 {
     const __int128 s = square_half(R);
@@ -226,8 +228,8 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int p
     if (fits(fm))
         return make_geom(d->H, d->W, nq, 4, -1, planar);
     if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ))
-        return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0);
-    return make_geom(d->H, d->W, nq, 8);
+        return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0, planar);
+    return make_geom(d->H, d->W, nq, 8, -1, planar);
 }
 
 }  // extern "C"
@@ -341,19 +343,23 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
 }
 
 int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
-                   int32_t bits[OSS_MAX_QUANTITIES])
+                   int32_t bits[OSS_MAX_QUANTITIES], int64_t *plane_bytes)
 {
-    if (!ref || !entry_stride || !offset || !bits)
+    if (!ref || !entry_stride || !offset || !bits || !plane_bytes)
         return OSS_E_ARG;
     const BuildGeom &g = ref->geom;
     *entry_stride = g.tab_es;
+    *plane_bytes = g.plane;
     int j = 0;
     for (int q = 0; q < OSS_MAX_QUANTITIES; ++q) {
         offset[q] = -1;
         bits[q] = 0;
     }
     for (int q = 0; q < g.nq; ++q) {
-        if (g.planar) {
+        if (g.planar && g.sqi >= 0) {
+            offset[q] = (q <= g.sqi ? q : q + 1) * g.plane;
+            bits[q] = q == g.sqi ? 64 : 32;
+        } else if (g.planar) {
             offset[q] = q * g.plane;
             bits[q] = 8 * g.ebytes;
         } else if (g.sqi < 0) {
@@ -485,6 +491,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->star_pipe = value;
         return OSS_OK;
+    case OSS_OPT_STAR_STAGED:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->star_staged = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -501,6 +512,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_BATCH_BUCKET: *value = ctx->batch_bucket; return OSS_OK;
     case OSS_OPT_TABLE_PLANAR: *value = ctx->table_planar; return OSS_OK;
     case OSS_OPT_STAR_PIPE: *value = ctx->star_pipe; return OSS_OK;
+    case OSS_OPT_STAR_STAGED: *value = ctx->star_staged; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }
@@ -728,7 +740,7 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
         }
         hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
                                          ctx->bits + hw * t, sw, smax, rmax,
-                                         ctx->star_lds ? 1 : (ctx->star_pipe ? 2 : 0), st,
+                                         ctx->star_lds ? 1 : ctx->star_pipe ? 2 : ctx->star_staged ? 3 : 0, st,
                                          &ctx->prof);
         if (e != hipSuccess)
             return OSS_E_DEVICE;
@@ -806,10 +818,10 @@ static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
             for (int q = 0; q < 3; ++q) {
                 dp.lo[q] = e.lo[q];
                 dp.hi[q] = e.hi[q];
-                // a central-star test must run (and may fail) wherever the
-                // radius is evaluated: no hull skip at radii that carry one
-                cur.lo[q] = std::min(cur.lo[q], e.ring ? INT64_MIN : dp.lo[q]);
-                cur.hi[q] = std::max(cur.hi[q], e.ring ? INT64_MAX : dp.hi[q]);
+                // outside the hull every entry fails (central-star entries
+                // then record their failure without the probe loop)
+                cur.lo[q] = std::min(cur.lo[q], dp.lo[q]);
+                cur.hi[q] = std::max(cur.hi[q], dp.hi[q]);
             }
             bp.probes.push_back(dp);
         }
@@ -960,8 +972,8 @@ int oss::batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, i
         return rc;
     const BuildGeom &g = ref->geom;
     const StarSweep sw = make_sweep(g.H, g.W, strip, blocks);
-    if (launch_star_batch(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dev, ctx->bits, sw, st,
-                          &ctx->prof) != hipSuccess)
+    if (launch_star_batch(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dev, ctx->bits, sw,
+                          ctx->star_staged != 0, st, &ctx->prof) != hipSuccess)
         return OSS_E_DEVICE;
     return OSS_OK;
 }

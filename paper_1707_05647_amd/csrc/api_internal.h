@@ -35,8 +35,9 @@ struct oss_ctx {
     int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
     int star_lds = 0;              // OSS_OPT_STAR_LDS
     int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
-    int table_planar = 0;          // OSS_OPT_TABLE_PLANAR
+    int table_planar = 1;          // OSS_OPT_TABLE_PLANAR
     int star_pipe = 0;             // OSS_OPT_STAR_PIPE
+    int star_staged = 1;           // OSS_OPT_STAR_STAGED
     void *rws = nullptr;           // preserved-region workspace (tables of the padded
     size_t rws_cap = 0;            // indicator image, the image, the star pass output)
 };

@@ -11,8 +11,9 @@
 // compared against every probe of every template of the group at that
 // radius.  The scale bits of the group's templates live in registers
 // (indexed by the probe's uniform template slot).  Each radius also carries
-// the hull of its probes' intervals: a wave none of whose positions lies in
-// the hull skips the probe loop (every probe would fail there).
+// the hull of its entries' intervals: a position outside it fails every
+// entry, so it skips the probe loop (central-star entries record the
+// failure), and a wave with no position inside skips the loop altogether.
 //
 // A group's distinct radii are split into buckets of consecutive radii.
 // A pass = (group, bucket); the launch walks all passes in order, each pass a
@@ -27,7 +28,11 @@
 
 namespace oss {
 
-template <typename Tab, int MT, bool RINGS>
+// STAGED (planar layouts): per radius the wave first looks up the first
+// quantity alone and tests it against the hull; the other quantities are
+// looked up only where it lies inside (the plain screen's staged form).
+
+template <typename Tab, int MT, bool RINGS, bool STAGED>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
     int64_t pitch_e, int64_t plane, int H, int W, const DevBatchPass *__restrict__ passes,
@@ -69,16 +74,59 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 const int r = rd.r, s = rd.s;
                 if (y < r || y > H - 1 - r)
                     continue;
-                if (x >= r && x <= W - 1 - r) {
-                    int64_t F[NQ];
-                    star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
-                    bool in = true;
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
-                    // skip the probe loop when no lane of the wave lies in the hull
-                    if (__builtin_amdgcn_ballot_w64(in) == 0)
+                const bool xv = x >= r && x <= W - 1 - r;
+                // a valid position outside the radius' hull fails every entry
+                // of the radius: central-star entries record that failure
+                auto fail_all = [&]() {
+                    if constexpr (RINGS) {
+                        if (xv)
+                            for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                                const DevBatchProbe &pr = probes[p];
+                                if (pr.ring)
+                                    fail[pr.t] |= 1u << pr.k;
+                            }
+                    }
+                };
+                int64_t F[NQ];
+                if constexpr (STAGED && Tab::STAGE && NQ > 1) {
+                    constexpr int C = Tab::C;
+                    const StarAddr ad = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
+                    bool in_c = false;
+                    if (xv) {
+                        F[C] = star_sum_c<Tab>(ad, plane);
+                        in_c = (F[C] >= rd.lo[C]) & (F[C] <= rd.hi[C]);
+                    }
+                    if (__builtin_amdgcn_ballot_w64(in_c) == 0) {
+                        fail_all();
                         continue;
+                    }
+                    if (in_c)
+                        star_sums_rest<Tab>(ad, plane, F);
+                    bool in = in_c;
+                    if (in_c) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
+                    }
+                    if (__builtin_amdgcn_ballot_w64(in) == 0 || !in) {
+                        fail_all();
+                        continue;
+                    }
+                } else {
+                    bool in = xv;
+                    if (xv) {
+                        star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
+                    }
+                    // skip the probe loop when no lane of the wave lies in the hull
+                    if (__builtin_amdgcn_ballot_w64(in) == 0 || !in) {
+                        fail_all();
+                        continue;
+                    }
+                }
+                {
                     for (int p = rd.first; p < rd.first + rd.count; ++p) {
                         const DevBatchProbe pr = probes[p];
                         bool pass = true;
@@ -112,55 +160,60 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     }
 }
 
-template <typename Tab>
-static void batch_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                         const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                         hipStream_t st)
+template <typename Tab, bool STAGED>
+static void batch_launch_s(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                           const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                           hipStream_t st)
 {
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+#define OSS_BATCH_LAUNCH(MT, RINGS)                                                               \
+    hipLaunchKernelGGL((star_batch_kernel<Tab, MT, RINGS, STAGED>), grid, block, 0, st, L, R, Rp, \
+                       g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, \
+                       bp.probes, bits, sw)
     if (bp.rings > 1) {
         if (bp.max_group <= 8)
-            hipLaunchKernelGGL((star_batch_kernel<Tab, 8, true>), grid, block, 0, st, L, R, Rp,
-                               g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,
-                               bp.radii, bp.probes, bits, sw);
+            OSS_BATCH_LAUNCH(8, true);
         else
-            hipLaunchKernelGGL((star_batch_kernel<Tab, 32, true>), grid, block, 0, st, L, R, Rp,
-                               g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,
-                               bp.radii, bp.probes, bits, sw);
-        return;
+            OSS_BATCH_LAUNCH(32, true);
+    } else if (bp.max_group <= 8) {
+        OSS_BATCH_LAUNCH(8, false);
+    } else if (bp.max_group <= 16) {
+        OSS_BATCH_LAUNCH(16, false);
+    } else {
+        OSS_BATCH_LAUNCH(32, false);
     }
-    if (bp.max_group <= 8)
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 8, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
-                           bits, sw);
-    else if (bp.max_group <= 16)
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 16, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
-                           bits, sw);
+#undef OSS_BATCH_LAUNCH
+}
+
+template <typename Tab>
+static void batch_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                         const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw, bool staged,
+                         hipStream_t st)
+{
+    if (staged && Tab::STAGE)
+        batch_launch_s<Tab, true>(g, L, R, Rp, bp, bits, sw, st);
     else
-        hipLaunchKernelGGL((star_batch_kernel<Tab, 32, false>), grid, block, 0, st, L, R, Rp, g.pitch_e,
-                           g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, bp.probes,
-                           bits, sw);
+        batch_launch_s<Tab, false>(g, L, R, Rp, bp, bits, sw, st);
 }
 
 template <typename T>
 static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                           const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                          hipStream_t st)
+                          bool staged, hipStream_t st)
 {
     if (g.planar) {
         switch (g.nq) {
-        case 1: batch_launch<TabP<T, 1>>(g, L, R, Rp, bp, bits, sw, st); break;
-        case 2: batch_launch<TabP<T, 2>>(g, L, R, Rp, bp, bits, sw, st); break;
-        case 3: batch_launch<TabP<T, 3>>(g, L, R, Rp, bp, bits, sw, st); break;
+        case 1: batch_launch<TabP<T, 1>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
+        case 2: batch_launch<TabP<T, 2>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
+        case 3: batch_launch<TabP<T, 3>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     switch (g.nq) {
-    case 1: batch_launch<TabU<T, 1>>(g, L, R, Rp, bp, bits, sw, st); break;
-    case 2: batch_launch<TabU<T, 2>>(g, L, R, Rp, bp, bits, sw, st); break;
-    case 3: batch_launch<TabU<T, 3>>(g, L, R, Rp, bp, bits, sw, st); break;
+    case 1: batch_launch<TabU<T, 1>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
+    case 2: batch_launch<TabU<T, 2>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
+    case 3: batch_launch<TabU<T, 3>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -168,14 +221,25 @@ static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, cons
 
 static hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                             const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                            hipStream_t st)
+                            bool staged, hipStream_t st)
 {
+    if (g.planar) {
+        if (g.nq == 3 && g.sqi == 1)
+            batch_launch<TabPS<3, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        else if (g.nq == 2 && g.sqi == 1)
+            batch_launch<TabPS<2, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        else if (g.nq == 2 && g.sqi == 0)
+            batch_launch<TabPS<2, 0>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (g.nq == 3 && g.sqi == 1)
-        batch_launch<TabMix<3, 1>>(g, L, R, Rp, bp, bits, sw, st);
+        batch_launch<TabMix<3, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
     else if (g.nq == 2 && g.sqi == 1)
-        batch_launch<TabMix<2, 1>>(g, L, R, Rp, bp, bits, sw, st);
+        batch_launch<TabMix<2, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
     else if (g.nq == 2 && g.sqi == 0)
-        batch_launch<TabMix<2, 0>>(g, L, R, Rp, bp, bits, sw, st);
+        batch_launch<TabMix<2, 0>>(g, L, R, Rp, bp, bits, sw, staged, st);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -183,17 +247,17 @@ static hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, co
 
 hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                             hipStream_t stream, Profiler *prof)
+                             bool staged, hipStream_t stream, Profiler *prof)
 {
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
         bp.max_group > BATCH_GROUP)
         return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_BATCH, stream);
     if (g.sqi >= 0)
-        return batch_mix(g, L, R, Rp, bp, bits, sw, stream);
+        return batch_mix(g, L, R, Rp, bp, bits, sw, staged, stream);
     if (g.ebytes == 4)
-        return batch_t<uint32_t>(g, L, R, Rp, bp, bits, sw, stream);
-    return batch_t<uint64_t>(g, L, R, Rp, bp, bits, sw, stream);
+        return batch_t<uint32_t>(g, L, R, Rp, bp, bits, sw, staged, stream);
+    return batch_t<uint64_t>(g, L, R, Rp, bp, bits, sw, staged, stream);
 }
 
 }  // namespace oss

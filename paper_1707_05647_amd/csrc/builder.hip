@@ -39,12 +39,12 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
     g.nq = nq;
     g.ebytes = ebytes;
     g.sqi = sqi;
-    g.planar = (planar && sqi < 0) ? 1 : 0;
+    g.planar = planar ? 1 : 0;
     g.pitch_e = ((int64_t)W + 1 + 15) / 16 * 16;
     if (g.planar) {
-        g.tab_es = ebytes;
-        g.plane = ((int64_t)(H + 1) * g.pitch_e * ebytes + 255) / 256 * 256;
-        g.tab_bytes = g.plane * nq;
+        g.tab_es = sqi >= 0 ? 4 : ebytes;
+        g.plane = ((int64_t)(H + 1) * g.pitch_e * g.tab_es + 255) / 256 * 256;
+        g.tab_bytes = g.plane * (sqi >= 0 ? nq + 1 : nq);
     } else {
         g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
         g.plane = 0;
@@ -519,19 +519,34 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__rest
 //   advance:        L += P, T_ad = ta_r + P, T_d = td_l + P
 // The last row is stored after one more barrier.
 // ---------------------------------------------------------------------------
-// Entry e of a table: NQ values of T side by side (MIX == -1), one value in
-// each of NQ planes plane_e values apart (MIX == -2), or the 16-byte mixed
-// entry (64-bit squares from slot MIX, the other quantities modulo 2^32)
-// written as one 16-byte store.
-template <typename T, int NQ, int MIX>
+// Entry e of a table, by layout LAY: NQ values of T side by side
+// (LAY_INTER), one value in each of NQ planes (LAY_PLANAR), the 16-byte mixed
+// entry (64-bit squares from slot SQI, the other quantities modulo 2^32,
+// written as one 16-byte store; LAY_MIX), or 32-bit planes with the squares
+// split into a low-word and a high-word plane (LAY_PLANAR_MIX).  plane_b is
+// the byte distance between planes.
+enum { LAY_INTER = 0, LAY_PLANAR = 1, LAY_MIX = 2, LAY_PLANAR_MIX = 3 };
+
+template <typename T, int NQ, int LAY, int SQI>
 __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v,
-                                            int64_t plane_e)
+                                            int64_t plane_b)
 {
-    if constexpr (MIX == -2) {  // planar
+    if constexpr (LAY == LAY_PLANAR) {
+        const int64_t pe = plane_b / (int64_t)sizeof(T);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            tab[q * plane_e + e] = v[q];
-    } else if constexpr (MIX < 0) {
+            tab[q * pe + e] = v[q];
+    } else if constexpr (LAY == LAY_PLANAR_MIX) {
+        uint32_t *t32 = reinterpret_cast<uint32_t *>(tab);
+        const int64_t pe = plane_b / 4;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int pl = q <= SQI ? q : q + 1;  // plane of quantity q
+            t32[pl * pe + e] = (uint32_t)v[q];
+            if (q == SQI)
+                t32[(pl + 1) * pe + e] = (uint32_t)((uint64_t)v[q] >> 32);
+        }
+    } else if constexpr (LAY == LAY_INTER) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             tab[e * NQ + q] = v[q];
@@ -540,22 +555,22 @@ __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, cons
         int j = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            if (q != MIX)
+            if (q != SQI)
                 o[j++] = (uint32_t)v[q];
-        const uint64_t sq = (uint64_t)v[MIX];
+        const uint64_t sq = (uint64_t)v[SQI];
         *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(tab) + e * 16) =
             make_uint4((uint32_t)sq, (uint32_t)(sq >> 32), o[0], o[1]);
     }
 }
 
-template <typename Pix, unsigned FM, typename T, int MIX>
+template <typename Pix, unsigned FM, typename T, int LAY, int SQI>
 __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const T *__restrict__ bp,
     const T *__restrict__ cL, const T *__restrict__ cAD, const T *__restrict__ cD,
     T *__restrict__ tL, T *__restrict__ tR, T *__restrict__ tRp)
 {
     constexpr int NQ = Feat<FM>::NQ;
-    const int64_t plane_e = g.plane / (int64_t)sizeof(T);
+    const int64_t plane_b = g.plane;
     constexpr int NW = BAND_THREADS / 64;
     static_assert(NW == 8, "first_n_sum adds eight wave totals");
     __shared__ T s_wt[2][NW][NQ];
@@ -649,9 +664,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
                 r[q] = TA[q] - td_l[q];
                 rp[q] = ta_r[q] - td_l[q];
             }
-            store_entry<T, NQ, MIX>(tL, e, Lc, plane_e);
-            store_entry<T, NQ, MIX>(tR, e, r, plane_e);
-            store_entry<T, NQ, MIX>(tRp, e, rp, plane_e);
+            store_entry<T, NQ, LAY, SQI>(tL, e, Lc, plane_b);
+            store_entry<T, NQ, LAY, SQI>(tR, e, r, plane_b);
+            store_entry<T, NQ, LAY, SQI>(tRp, e, rp, plane_b);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -686,13 +701,13 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     }
     if (store) {
         const int64_t e = (int64_t)(ys + rows) * g.pitch_e + (x + 1);
-        store_entry<T, NQ, MIX>(tL, e, Lc, plane_e);
-        store_entry<T, NQ, MIX>(tR, e, r, plane_e);
-        store_entry<T, NQ, MIX>(tRp, e, rp, plane_e);
+        store_entry<T, NQ, LAY, SQI>(tL, e, Lc, plane_b);
+        store_entry<T, NQ, LAY, SQI>(tR, e, r, plane_b);
+        store_entry<T, NQ, LAY, SQI>(tRp, e, rp, plane_b);
     }
 }
 
-template <typename Pix, unsigned FM, typename T, int MIX = -1>
+template <typename Pix, unsigned FM, typename T, int LAY = LAY_INTER, int SQI = -1>
 static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_bytes,
                           const BuildBuffers &bb, hipStream_t st, Profiler *prof)
 {
@@ -722,7 +737,7 @@ static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_
     }
     {
         ProfScope ps(prof, K_BAND_FINAL, st);
-        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, MIX>), dim3(g.nfin, g.nb),
+        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, LAY, SQI>), dim3(g.nfin, g.nb),
                            dim3(BAND_THREADS), 0, st, img, pitch, g, bp, cL, cAD, cD,
                            static_cast<T *>(bb.L), static_cast<T *>(bb.R),
                            static_cast<T *>(bb.Rp));
@@ -734,24 +749,32 @@ template <typename Pix, typename T>
 static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint32_t fm,
                             const BuildBuffers &bb, hipStream_t st, Profiler *pr)
 {
-    if (g.planar) {
+    if (g.sqi >= 0) {
+        // 64-bit accumulation, the squares stored in 64 bits
+        if (g.planar) {
+            switch (fm) {
+            case 3: return build_t<Pix, 3, uint64_t, LAY_PLANAR_MIX, 1>(g, px, pb, bb, st, pr);
+            case 6: return build_t<Pix, 6, uint64_t, LAY_PLANAR_MIX, 0>(g, px, pb, bb, st, pr);
+            case 7: return build_t<Pix, 7, uint64_t, LAY_PLANAR_MIX, 1>(g, px, pb, bb, st, pr);
+            default: return hipErrorInvalidValue;
+            }
+        }
         switch (fm) {
-        case 1: return build_t<Pix, 1, T, -2>(g, px, pb, bb, st, pr);
-        case 2: return build_t<Pix, 2, T, -2>(g, px, pb, bb, st, pr);
-        case 3: return build_t<Pix, 3, T, -2>(g, px, pb, bb, st, pr);
-        case 4: return build_t<Pix, 4, T, -2>(g, px, pb, bb, st, pr);
-        case 5: return build_t<Pix, 5, T, -2>(g, px, pb, bb, st, pr);
-        case 6: return build_t<Pix, 6, T, -2>(g, px, pb, bb, st, pr);
-        case 7: return build_t<Pix, 7, T, -2>(g, px, pb, bb, st, pr);
+        case 3: return build_t<Pix, 3, uint64_t, LAY_MIX, 1>(g, px, pb, bb, st, pr);
+        case 6: return build_t<Pix, 6, uint64_t, LAY_MIX, 0>(g, px, pb, bb, st, pr);
+        case 7: return build_t<Pix, 7, uint64_t, LAY_MIX, 1>(g, px, pb, bb, st, pr);
         default: return hipErrorInvalidValue;
         }
     }
-    if (g.sqi >= 0) {
-        // mixed entries: 64-bit accumulation, the squares stored in 64 bits
+    if (g.planar) {
         switch (fm) {
-        case 3: return build_t<Pix, 3, uint64_t, 1>(g, px, pb, bb, st, pr);
-        case 6: return build_t<Pix, 6, uint64_t, 0>(g, px, pb, bb, st, pr);
-        case 7: return build_t<Pix, 7, uint64_t, 1>(g, px, pb, bb, st, pr);
+        case 1: return build_t<Pix, 1, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 2: return build_t<Pix, 2, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 3: return build_t<Pix, 3, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 4: return build_t<Pix, 4, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 5: return build_t<Pix, 5, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 6: return build_t<Pix, 6, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 7: return build_t<Pix, 7, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
         default: return hipErrorInvalidValue;
         }
     }

@@ -44,9 +44,9 @@ struct BuildGeom {
     int H, W, nq;
     int ebytes;        // bytes per accumulated quantity: 4 (mod 2^32) or 8
     int sqi;           // mixed entries: slot of the squares among the quantities, else -1
-    int planar;        // 1: one plane per quantity (entry stride ebytes)
+    int planar;        // 1: one plane per quantity (entry stride ebytes; 4 with sqi >= 0)
     int tab_es;        // entry stride in bytes: nq * ebytes, 16 (mixed) or ebytes (planar)
-    int64_t plane;     // planar: bytes from one quantity's plane to the next, else 0
+    int64_t plane;     // planar: bytes from one plane to the next, else 0
     int64_t tab_bytes; // bytes of one table
     int64_t pitch_e;   // table entries per row (>= W+1)
     int nb;            // bands
@@ -59,8 +59,9 @@ struct BuildGeom {
 // Table entries hold the nq quantities in feature order, each in ebytes
 // bytes; with sqi >= 0 (ebytes 8) an entry is 16 bytes instead: the squares
 // (quantity slot sqi) as 64 bits, then the other quantities in feature order
-// as 32 bits each (modulo 2^32), zero padded.  planar (sqi < 0 only): each
-// quantity in a plane of its own, planes 256-byte aligned.
+// as 32 bits each (modulo 2^32), zero padded.  planar: each quantity in a
+// plane of its own, planes 256-byte aligned; with sqi >= 0 every plane holds
+// 32-bit values and the squares take two planes, low word then high word.
 BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1, int planar = 0);
 
 // ---------------------------------------------------------------------------
@@ -210,15 +211,19 @@ StarSweep make_sweep(int H, int W, int strip, int blocks_per_xcd);
 constexpr size_t STAR_LDS_MAX = 64 * 1024;
 size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax);
 // variant: 0 one radius at a time, 1 LDS-staged rows (32/64-bit
-// interleaved entries only), 2 software-pipelined radii
+// interleaved entries only), 2 software-pipelined radii, 3 staged lookups
+// on planar tables (the first quantity alone, the others only where it
+// passes)
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
                              int smax, int rmax, int variant, hipStream_t stream,
                              Profiler *prof);
 
+// staged: look up the first quantity alone and the others only where it
+// lies in the radius' hull (as variant 3 of the plain screen)
 hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                              const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                             hipStream_t stream, Profiler *prof);
+                             bool staged, hipStream_t stream, Profiler *prof);
 
 // compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
 size_t compact_workspace_bytes(int64_t n);

@@ -35,7 +35,17 @@
 
 namespace oss {
 
-template <typename Tab>
+// STAGED (planar layouts with more than one quantity): per radius a wave
+// first looks up quantity Tab::C alone (one load of 64 consecutive values
+// per lookup) and compares it with the radius' probes; only if some
+// position of the wave passes does it look up the other quantities, and
+// only for the positions that passed.  A position fails a probe when any
+// feature fails, so the result is the same; the saving is the table reads of
+// the quantities that are never needed (most positions fail the first
+// feature: the screen's premise).  Interleaved entries are never staged: a
+// lone quantity is then a strided read that costs about as much as the
+// whole entry.
+template <typename Tab, bool STAGED>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
     int64_t pitch_e, int64_t plane, int H, int W, const DevTemplatePlan *__restrict__ plan,
@@ -65,7 +75,33 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
             const int r = rd.r, s = rd.s;
             if (y < r || y > H - 1 - r)
                 continue;
-            if (x >= r && x <= W - 1 - r) {
+            const bool xv = x >= r && x <= W - 1 - r;
+            if constexpr (STAGED && Tab::STAGE && NQ > 1) {
+                constexpr int C = Tab::C;
+                const StarAddr ad = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
+                int64_t F[NQ];
+                bool maybe = false;
+                if (xv) {
+                    F[C] = star_sum_c<Tab>(ad, plane);
+                    for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                        const DevProbe pr = plan->probes[p];
+                        maybe = maybe | ((F[C] >= pr.lo[C]) & (F[C] <= pr.hi[C]));
+                    }
+                }
+                if (__builtin_amdgcn_ballot_w64(maybe) == 0)
+                    continue;
+                if (maybe) {
+                    star_sums_rest<Tab>(ad, plane, F);
+                    for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                        const DevProbe pr = plan->probes[p];
+                        bool pass = true;
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                        acc |= pass ? (1u << pr.k) : 0u;
+                    }
+                }
+            } else if (xv) {
                 int64_t F[NQ];
                 star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
                 for (int p = rd.first; p < rd.first + rd.count; ++p) {
@@ -321,28 +357,37 @@ static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T 
 template <typename Tab>
 static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                               const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                              hipStream_t stream, bool pipe)
+                              hipStream_t stream, int variant)
 {
-    if (pipe)
-        hipLaunchKernelGGL((star_pipe_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), 0,
-                           stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
-    else
-        hipLaunchKernelGGL((star_plain_kernel<Tab>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip),
-                           0, stream, L, R, Rp, g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+    if (variant == 2) {
+        hipLaunchKernelGGL((star_pipe_kernel<Tab>), grid, block, 0, stream, L, R, Rp, g.pitch_e,
+                           g.plane, g.H, g.W, plan, bits, sw);
+        return;
+    }
+    if constexpr (Tab::STAGE && Tab::NQ > 1) {
+        if (variant == 3) {
+            hipLaunchKernelGGL((star_plain_kernel<Tab, true>), grid, block, 0, stream, L, R, Rp,
+                               g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((star_plain_kernel<Tab, false>), grid, block, 0, stream, L, R, Rp,
+                       g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
 }
 
 template <typename T>
 static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                          const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                         int smax, int rmax, bool lds, bool pipe, hipStream_t stream)
+                         int smax, int rmax, bool lds, int variant, hipStream_t stream)
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
     if (g.planar) {
         switch (g.nq) {
-        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
-        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
-        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -357,25 +402,36 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
         return hipGetLastError();
     }
     switch (g.nq) {
-    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
-    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
-    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, pipe); break;
+    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// Mixed 16-byte entries (the squares in 64 bits): no LDS variant.
+// 64-bit squares (mixed 16-byte entries or split planes): no LDS variant.
 static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
                            const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
-                           hipStream_t stream, bool pipe)
+                           hipStream_t stream, int variant)
 {
+    if (g.planar) {
+        if (g.nq == 3 && g.sqi == 1)
+            star_plain_launch<TabPS<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        else if (g.nq == 2 && g.sqi == 1)
+            star_plain_launch<TabPS<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        else if (g.nq == 2 && g.sqi == 0)
+            star_plain_launch<TabPS<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (g.nq == 3 && g.sqi == 1)
-        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
+        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
     else if (g.nq == 2 && g.sqi == 1)
-        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
+        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
     else if (g.nq == 2 && g.sqi == 0)
-        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, pipe);
+        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, variant);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -387,17 +443,16 @@ hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, c
                              Profiler *prof)
 {
     bool lds = variant == 1;
-    const bool pipe = variant == 2;
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1)
         return hipErrorInvalidValue;
     if (lds && star_lds_bytes(sw.strip, g.nq, g.ebytes, smax, rmax) > STAR_LDS_MAX)
         lds = false;
     ProfScope ps(prof, K_STAR, stream);
     if (g.sqi >= 0)
-        return star_mix(g, L, R, Rp, plan, bits, sw, stream, pipe);
+        return star_mix(g, L, R, Rp, plan, bits, sw, stream, variant);
     if (g.ebytes == 4)
-        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, pipe, stream);
-    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, pipe, stream);
+        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, variant, stream);
+    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, variant, stream);
 }
 
 }  // namespace oss

@@ -32,6 +32,7 @@ template <typename T, int NQ_>
 struct TabU {
     static constexpr int NQ = NQ_;
     static constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
+    static constexpr bool STAGE = false;  // no narrow load of one quantity pays off
     using E = Entry<T, NQ>;
     __device__ static __forceinline__ E load(const char *p, int64_t)
     {
@@ -57,6 +58,7 @@ template <int NQ_, int SQI>
 struct TabMix {
     static constexpr int NQ = NQ_;
     static constexpr int64_t ES = 16;
+    static constexpr bool STAGE = false;
     using E = MixEntry;
     __device__ static __forceinline__ E load(const char *p, int64_t)
     {
@@ -86,6 +88,7 @@ template <typename T, int NQ_>
 struct TabP {
     static constexpr int NQ = NQ_;
     static constexpr int64_t ES = (int64_t)sizeof(T);
+    static constexpr bool STAGE = true;
     using E = Entry<T, NQ>;
     __device__ static __forceinline__ E load(const char *p, int64_t plane)
     {
@@ -101,6 +104,114 @@ struct TabP {
     {
         TabU<T, NQ>::reduce(a, b, c, d, e, f, h, k, F);
     }
+    // Staged lookup: quantity C (plane 0) alone, then the other planes.
+    static constexpr int C = 0;
+    using V = T;
+    struct Rest {
+        T v[NQ > 1 ? NQ - 1 : 1];
+    };
+    __device__ static __forceinline__ V load_c(const char *p, int64_t)
+    {
+        return *reinterpret_cast<const T *>(p);
+    }
+    __device__ static __forceinline__ Rest load_rest(const char *p, int64_t plane)
+    {
+        Rest e;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            e.v[q - 1] = *reinterpret_cast<const T *>(p + q * plane);
+        return e;
+    }
+    __device__ static __forceinline__ void reduce_rest(const Rest &a, const Rest &b, const Rest &c,
+                                                       const Rest &d, const Rest &e, const Rest &f,
+                                                       const Rest &h, const Rest &k, int64_t *F)
+    {
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            F[q] = widen((T)(a.v[q - 1] - b.v[q - 1] - c.v[q - 1] + d.v[q - 1])) +
+                   widen((T)(e.v[q - 1] - f.v[q - 1] - h.v[q - 1] + k.v[q - 1]));
+    }
+};
+
+// Planar tables whose squares need 64 bits: every plane holds 32-bit values
+// and the squares (slot SQI) take two planes, low word then high word, so a
+// wave's lookup of one quantity is 64 consecutive 32-bit words.  The other
+// quantities are exact modulo 2^32 as in TabMix.
+template <int NQ_, int SQI>
+struct TabPS {
+    static constexpr int NQ = NQ_;
+    static constexpr int64_t ES = 4;
+    static constexpr bool STAGE = true;
+    static constexpr int NP = NQ + 1;  // planes
+    struct E {
+        uint32_t v[NP];
+    };
+    // plane of quantity q (the squares: this plane and the next)
+    static constexpr int pl(int q) { return q <= SQI ? q : q + 1; }
+    __device__ static __forceinline__ uint32_t word(const char *p, int64_t plane, int i)
+    {
+        return *reinterpret_cast<const uint32_t *>(p + i * plane);
+    }
+    __device__ static __forceinline__ E load(const char *p, int64_t plane)
+    {
+        E e;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            e.v[i] = word(p, plane, i);
+        return e;
+    }
+    __device__ static __forceinline__ uint64_t sq(const E &e)
+    {
+        return (uint64_t)e.v[SQI] | ((uint64_t)e.v[SQI + 1] << 32);
+    }
+    // F[q] for every quantity q != skip
+    __device__ static __forceinline__ void reduce_skip(const E &a, const E &b, const E &c,
+                                                       const E &d, const E &e, const E &f,
+                                                       const E &h, const E &k, int64_t *F,
+                                                       int skip)
+    {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q == skip)
+                continue;
+            if (q == SQI) {
+                F[q] = widen((uint64_t)(sq(a) - sq(b) - sq(c) + sq(d))) +
+                       widen((uint64_t)(sq(e) - sq(f) - sq(h) + sq(k)));
+            } else {
+                const int i = pl(q);
+                F[q] = widen((uint32_t)(a.v[i] - b.v[i] - c.v[i] + d.v[i])) +
+                       widen((uint32_t)(e.v[i] - f.v[i] - h.v[i] + k.v[i]));
+            }
+        }
+    }
+    __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
+                                                  const E &e, const E &f, const E &h, const E &k,
+                                                  int64_t *F)
+    {
+        reduce_skip(a, b, c, d, e, f, h, k, F, -1);
+    }
+    // Staged lookup: the first 32-bit quantity alone, then the other planes.
+    static constexpr int C = SQI == 0 ? 1 : 0;
+    using V = uint32_t;
+    using Rest = E;
+    __device__ static __forceinline__ V load_c(const char *p, int64_t plane)
+    {
+        return word(p, plane, pl(C));
+    }
+    __device__ static __forceinline__ Rest load_rest(const char *p, int64_t plane)
+    {
+        E e;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            e.v[i] = i == pl(C) ? 0u : word(p, plane, i);
+        return e;
+    }
+    __device__ static __forceinline__ void reduce_rest(const Rest &a, const Rest &b, const Rest &c,
+                                                       const Rest &d, const Rest &e, const Rest &f,
+                                                       const Rest &h, const Rest &k, int64_t *F)
+    {
+        reduce_skip(a, b, c, d, e, f, h, k, F, C);
+    }
 };
 
 // Entry at a wave-uniform row base plus this lane's byte offset.
@@ -110,17 +221,21 @@ __device__ __forceinline__ E entry_at(const char *row, uint32_t lane_off)
     return *reinterpret_cast<const E *>(row + lane_off);
 }
 
-// Star feature sums at (x0 + lane, y) for radius r (square half-width s):
-// the square by 4 lookups into L (Eq. S_1), the diamond by 2 into R and 2
-// into R'.  Lb/Rb/Rpb point at table column x0 (the lane adds lane_off =
-// (lane + 1) entries: table column = image column + 1); table row = image
-// row + 1.  Only called for positions where the star fits.
+// Addresses of the 8 lookups of the star at (x0 + lane, y) for radius r
+// (square half-width s): the square by 4 lookups into L (Eq. S_1), the
+// diamond by 2 into R and 2 into R'.  Lb/Rb/Rpb point at table column x0
+// (the lane adds lane_off = (lane + 1) entries: table column = image column
+// + 1); table row = image row + 1.  Only used for positions where the star
+// fits.
+struct StarAddr {
+    const char *a, *b, *c, *d, *e, *f, *h, *k;
+};
+
 template <typename Tab>
-__device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
-                                          int64_t row_bytes, uint32_t lane_off, int y, int r,
-                                          int s, int64_t *F, int64_t plane)
+__device__ __forceinline__ StarAddr star_addr(const char *Lb, const char *Rb, const char *Rpb,
+                                              int64_t row_bytes, uint32_t lane_off, int y, int r,
+                                              int s)
 {
-    using E = typename Tab::E;
     constexpr int64_t ES = Tab::ES;
     const char *l_top = Lb + (int64_t)(y - s) * row_bytes;      // row y-s-1
     const char *l_bot = Lb + (int64_t)(y + s + 1) * row_bytes;  // row y+s
@@ -129,15 +244,51 @@ __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const 
     const char *rp_mid = Rpb + (int64_t)y * row_bytes;           // row y-1
     const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
     const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
-    const E a = Tab::load(l_bot + ds + lane_off, plane);    // L(x+s,   y+s)
-    const E b = Tab::load(l_bot - ds1 + lane_off, plane);   // L(x-s-1, y+s)
-    const E c = Tab::load(l_top + ds + lane_off, plane);    // L(x+s,   y-s-1)
-    const E d = Tab::load(l_top - ds1 + lane_off, plane);   // L(x-s-1, y-s-1)
-    const E e = Tab::load(r_bot + lane_off, plane);         // R(x, y+r)
-    const E f = Tab::load(rp_mid - dr1 + lane_off, plane);  // R'(x-r-1, y-1)
-    const E h = Tab::load(rp_mid + dr + lane_off, plane);   // R'(x+r, y-1)
-    const E k = Tab::load(r_top + lane_off, plane);         // R(x, y-r-1)
-    Tab::reduce(a, b, c, d, e, f, h, k, F);
+    StarAddr o;
+    o.a = l_bot + ds + lane_off;    // L(x+s,   y+s)
+    o.b = l_bot - ds1 + lane_off;   // L(x-s-1, y+s)
+    o.c = l_top + ds + lane_off;    // L(x+s,   y-s-1)
+    o.d = l_top - ds1 + lane_off;   // L(x-s-1, y-s-1)
+    o.e = r_bot + lane_off;         // R(x, y+r)
+    o.f = rp_mid - dr1 + lane_off;  // R'(x-r-1, y-1)
+    o.h = rp_mid + dr + lane_off;   // R'(x+r, y-1)
+    o.k = r_top + lane_off;         // R(x, y-r-1)
+    return o;
+}
+
+// Star feature sums of every quantity.
+template <typename Tab>
+__device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
+                                          int64_t row_bytes, uint32_t lane_off, int y, int r,
+                                          int s, int64_t *F, int64_t plane)
+{
+    const StarAddr p = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
+    Tab::reduce(Tab::load(p.a, plane), Tab::load(p.b, plane), Tab::load(p.c, plane),
+                Tab::load(p.d, plane), Tab::load(p.e, plane), Tab::load(p.f, plane),
+                Tab::load(p.h, plane), Tab::load(p.k, plane), F);
+}
+
+// Staged form (planar layouts, Tab::STAGE): the feature sum of quantity
+// Tab::C alone (one load of 64 consecutive values per wave and lookup), and,
+// for the positions that pass its compare, the others.
+template <typename Tab>
+__device__ __forceinline__ int64_t star_sum_c(const StarAddr &p, int64_t plane)
+{
+    using V = typename Tab::V;
+    const V a = Tab::load_c(p.a, plane), b = Tab::load_c(p.b, plane);
+    const V c = Tab::load_c(p.c, plane), d = Tab::load_c(p.d, plane);
+    const V e = Tab::load_c(p.e, plane), f = Tab::load_c(p.f, plane);
+    const V h = Tab::load_c(p.h, plane), k = Tab::load_c(p.k, plane);
+    return widen((V)(a - b - c + d)) + widen((V)(e - f - h + k));
+}
+
+template <typename Tab>
+__device__ __forceinline__ void star_sums_rest(const StarAddr &p, int64_t plane, int64_t *F)
+{
+    Tab::reduce_rest(Tab::load_rest(p.a, plane), Tab::load_rest(p.b, plane),
+                     Tab::load_rest(p.c, plane), Tab::load_rest(p.d, plane),
+                     Tab::load_rest(p.e, plane), Tab::load_rest(p.f, plane),
+                     Tab::load_rest(p.h, plane), Tab::load_rest(p.k, plane), F);
 }
 
 // Position of sweep item `it` of XCD `xcd`: image row y and the strip's first

@@ -36,7 +36,7 @@ class Reference:
         self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask, max_radius)
         info = L.oss_ref_tables(self.handle)
         self.value_bits, self.max_radius = info[5], info[6]
-        self.entry_bytes, self.slots = L.oss_ref_layout(self.handle)
+        self.entry_bytes, self.slots, self.plane_bytes = L.oss_ref_layout(self.handle)
         if build:
             self.build(stream)
 
@@ -69,18 +69,27 @@ class Reference:
         n = H1 * pitch
         # bytes the table spans on the device, and a host buffer that also
         # holds the reshaped views' unused tails
-        used = max(off + (n - 1) * es + bits // 8 for off, bits in self.slots)
-        span = max(off for off, _ in self.slots) + n * es
+        # 64-bit values in 4-byte planes: low word at off, high word one plane on
+        words = [((off, off + self.plane_bytes) if (bits == 64 and es == 4) else (off,), bits)
+                 for off, bits in self.slots]
+        used = max(o + (n - 1) * es + min(bits // 8, es) for offs, bits in words for o in offs)
+        span = max(o for offs, _ in words for o in offs) + n * es
         out = []
         for p in (Lp, Rp_, Rpp):
             raw = np.zeros(span, np.uint8)
             _hip_memcpy_d2h(raw[:used], p)
             t = np.empty((H1, self.W + 1, nq), np.int64)
-            for q, (off, bits) in enumerate(self.slots):
-                nb = bits // 8
+
+            def plane_values(off, nb):
                 v = raw[off:off + n * es].reshape(H1, pitch, es)[:, :self.W + 1, :nb]
-                v = np.ascontiguousarray(v).view(np.uint32 if nb == 4 else np.int64)[..., 0]
-                t[..., q] = v.astype(np.int64)
+                return np.ascontiguousarray(v).view(np.uint32 if nb == 4 else np.int64)[..., 0]
+            for q, (offs, bits) in enumerate(words):
+                if len(offs) == 2:
+                    lo = plane_values(offs[0], 4).astype(np.uint64)
+                    hi = plane_values(offs[1], 4).astype(np.uint64)
+                    t[..., q] = (lo | (hi << np.uint64(32))).view(np.int64)
+                else:
+                    t[..., q] = plane_values(offs[0], bits // 8).astype(np.int64)
             out.append(t)
         return out
 

@@ -7,8 +7,8 @@ runs of ``bench.py --copy-probe-mb COPY_MIB`` with ``--pmc FETCH_SIZE`` and
 ``--pmc WRITE_SIZE`` (KiB per dispatch).  The plain copy kernel in the same
 run moves COPY_MIB MiB each way; its counter readings give the scale factor
 (bytes per counted KiB) applied to every kernel.  Writes OUT_JSON with, per
-library kernel, the mean scaled read and write bytes per launch and the
-sha of the source file the kernel was built from.
+library kernel, the mean scaled read and write bytes per launch and a
+hash of the sources the kernel was built from.
 """
 from __future__ import annotations
 
@@ -37,9 +37,17 @@ KERNELS = {
 }
 
 
-def _sha(path):
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+# headers every kernel source includes (a change there can change the kernel)
+SHARED = ("paper_1707_05647_amd/csrc/oss_internal.h", "paper_1707_05647_amd/csrc/star_common.h")
+
+
+def kernel_sha(short: str) -> str:
+    """Hash of the source file a kernel is built from and the shared headers."""
+    h = hashlib.sha256()
+    for path in (KERNELS[short][1], *SHARED):
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_counter(path, counter):
@@ -67,7 +75,7 @@ def main(fetch_csv, write_csv, copy_mib, out_json):
     w_scale = copy_bytes / max(write["copy"])
     res = {"copy_mib": copy_mib, "fetch_bytes_per_unit": f_scale,
            "write_bytes_per_unit": w_scale, "kernels": {}}
-    for short, (_, src) in KERNELS.items():
+    for short in KERNELS:
         if short == "copy" or short not in fetch:
             continue
         fv, wv = fetch[short], write.get(short, [0.0])
@@ -75,7 +83,7 @@ def main(fetch_csv, write_csv, copy_mib, out_json):
         wr = w_scale * sum(wv) / len(wv)
         res["kernels"][short] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
                                  "hbm_bytes_per_launch": rd + wr, "dispatches": len(fv),
-                                 "source_sha": _sha(src)}
+                                 "source_sha": kernel_sha(short)}
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))

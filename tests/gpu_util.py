@@ -83,7 +83,7 @@ class Runner:
 
     def screen(self, img: np.ndarray, templates, probes, fm: int, P, Q: int, *,
                bit_depth=None, list_cap=None, pitch_pad: int = 0, tm_fm=None,
-               max_radius: int = -1):
+               max_radius: int = -1, batched: bool = False):
         torch = self.torch
         if pitch_pad:
             wide = np.zeros((img.shape[0], img.shape[1] + pitch_pad), img.dtype)
@@ -96,11 +96,13 @@ class Runner:
         ref = self.ctx.reference(t_img, fm, bit_depth, max_radius=max_radius)
         self.last_value_bits = ref.value_bits
         self.last_entry_bytes = ref.entry_bytes
+        self.last_slots = ref.slots
+        self.last_plane_bytes = ref.plane_bytes
         tm = [self.L.oss_template_features(px, rho, tm_fm or fm, bit_depth=bit_depth)
               for px, rho in templates]
         H, W = img.shape
         cap = list_cap if list_cap is not None else len(templates) * H * W
-        res = self.ctx.screen(ref, tm, probes, (*P, Q), fm, list_cap=cap)
+        res = self.ctx.screen(ref, tm, probes, (*P, Q), fm, list_cap=cap, batched=batched)
         torch.cuda.synchronize()
         mask, cands, n = res.host()
         ref.release()

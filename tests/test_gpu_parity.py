@@ -59,10 +59,16 @@ def test_tables_match_definitions(runner, case, planar):
     try:
         ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
     finally:
-        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 0)
+        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
     torch.cuda.synchronize()
-    if planar and ref.value_bits == 32 and not fm & 24:  # moments stay interleaved
-        assert ref.entry_bytes == 4 and len(ref.slots) == bin(fm).count("1")
+    assert len(ref.slots) == bin(fm).count("1")
+    if planar and not fm & 24:  # moments stay interleaved
+        assert ref.plane_bytes > 0
+        widths = {b for _, b in ref.slots}
+        # 32-bit planes, also when the squares alone take two of them
+        assert ref.entry_bytes == (8 if widths == {64} else 4)
+    else:
+        assert ref.plane_bytes == 0
     got = ref.tables_host()
     slots = ref.slots
     ref.release()
@@ -81,7 +87,7 @@ def test_tables_match_definitions(runner, case, planar):
 
 
 # max radius -> storage: the probes' own maximum (32-bit entries unless the
-# sums need more), 200 (64-bit squares in mixed 16-byte entries for 8- and
+# sums need more), 200 (64-bit squares beside 32-bit sums and gradients for 8- and
 # 12-bit pixels), 2^20 (64-bit entries)
 WIDTHS = pytest.mark.parametrize("max_r", [-2, 200, 1 << 20], ids=["w32", "wmix", "w64"])
 
@@ -196,7 +202,8 @@ def test_32bit_storage_near_its_limit(runner):
     want = oc.screen_full(img, tm, probes, 7, P, Q)
     assert np.array_equal(cands, oc.mask_and_list(want)[1]) and n > 0
     mask, cands, n = runner.screen(img, tm, probes, 7, P, Q, bit_depth=12, max_radius=11)
-    assert runner.last_value_bits == 64 and runner.last_entry_bytes == 16  # 64-bit squares only
+    assert runner.last_value_bits == 64  # 64-bit squares only
+    assert [b for _, b in runner.last_slots] == [32, 64, 32]
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
 
 
@@ -258,39 +265,38 @@ def test_cfg2_full_size_sampled(runner):
     assert bits[0, t.cy, t.cx] & (1 << 2)
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
-def test_planar_tables_same_results(runner, cfg):
-    """Planar 32-bit tables (one plane per quantity): plain and batched
-    screens equal the oracle (workload 3 keeps its probes of radius <= 40,
-    where squares of 8-bit pixels still fit 32 bits)."""
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+@WIDTHS
+def test_interleaved_tables_same_results(runner, cfg, max_r):
+    """Interleaved tables (OSS_OPT_TABLE_PLANAR = 0: the quantities of an
+    entry side by side, 32-bit, mixed 16-byte or 64-bit entries): plain and
+    batched screens equal the oracle."""
     kw = {1: {},
           2: dict(H=230, W=270, blobs_per_512sq=800, sig_hi=24),
-          3: dict(H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20)}[cfg]
+          3: dict(H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20),
+          5: dict(H=224, W=240, n_templates=3, blobs_per_512sq=1200, sig_hi=20)}[cfg]
     w = make_workload(cfg, 1, **kw)
-    if cfg == 3:
-        w.probes = [p for p in w.probes if p[2] <= 40]
-    max_r = max(p[2] for p in w.probes)
     L = runner.L
-    L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
+    assert L.oss_ctx_get_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR) == 1
+    L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 0)
     try:
         _screen_and_compare(runner, w, max_r)
-        assert runner.last_entry_bytes == 4
-        img = L.device_image(w.ref, runner.dev)
-        ref = runner.ctx.reference(img, w.feat_mask, w.depth, max_radius=max_r)
-        tm = [L.oss_template_features(t.pixels, t.rho, w.feat_mask, bit_depth=w.depth)
-              for t in w.templates]
-        res = runner.ctx.screen(ref, tm, w.probes, (*w.tol_P, w.tol_Q), w.feat_mask,
-                                list_cap=len(tm) * w.H * w.W, batched=True)
-        runner.torch.cuda.synchronize()
-        got = res.host()
-        ref.release()
+        assert runner.last_plane_bytes == 0
+        _screen_and_compare(runner, w, max_r, batched=True)
     finally:
-        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 0)
-    want = oc.screen_full(w.ref, [(t.pixels, t.rho) for t in w.templates], w.probes,
-                          w.feat_mask, w.tol_P, w.tol_Q)
-    wmask, wlist = oc.mask_and_list(want)
-    assert got[2] == len(wlist) and np.array_equal(got[0], wmask)
-    assert np.array_equal(got[1], wlist)
+        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
+
+
+def test_default_tables_are_planar(runner):
+    """The default layout is planar for 32-bit storage, for 64-bit squares
+    beside 32-bit sums and gradients (split planes), and for 64-bit storage."""
+    w = make_workload(2, 0, H=200, W=230, blobs_per_512sq=800, sig_hi=24)
+    want = {-2: [32, 32, 32], 200: [32, 64, 32], 1 << 20: [64, 64, 64]}
+    for max_r, bits in want.items():
+        _screen_and_compare(runner, w, max_r)
+        assert runner.last_plane_bytes > 0
+        assert [b for _, b in runner.last_slots] == bits
+        assert runner.last_entry_bytes == (8 if bits == [64, 64, 64] else 4)
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3, 5])
@@ -312,4 +318,29 @@ def test_pipelined_star_same_results(runner, cfg, max_r):
         _screen_and_compare(runner, w, max_r, pitch_pad=5)
     finally:
         L.oss_ctx_set_option(h, L.OSS_OPT_STAR_PIPE, 0)
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STRIP, 512)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+@WIDTHS
+def test_unstaged_star_same_results(runner, cfg, max_r):
+    """With staged lookups off (OSS_OPT_STAR_STAGED = 0: every quantity at
+    every lookup) the plain and the batched star passes equal the oracle on
+    every workload shape and entry layout, also with narrow strips."""
+    kw = {1: {},
+          2: dict(H=230, W=270, blobs_per_512sq=800, sig_hi=24),
+          3: dict(H=200, W=260, n_templates=5, blobs_per_512sq=1200, sig_hi=20),
+          5: dict(H=224, W=240, n_templates=3, blobs_per_512sq=1200, sig_hi=20)}[cfg]
+    w = make_workload(cfg, 6, **kw)
+    L = runner.L
+    h = runner.ctx.handle
+    assert L.oss_ctx_get_option(h, L.OSS_OPT_STAR_STAGED) == 1
+    L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STAGED, 0)
+    try:
+        _screen_and_compare(runner, w, max_r)
+        _screen_and_compare(runner, w, max_r, batched=True)
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STRIP, 64)
+        _screen_and_compare(runner, w, max_r, pitch_pad=5)
+    finally:
+        L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STAGED, 1)
         L.oss_ctx_set_option(h, L.OSS_OPT_STAR_STRIP, 512)
