@@ -170,6 +170,81 @@ WORKLOAD_TEXT = {
 }
 
 
+def run_pipelined(lanes, make_lane, steps, warmup, L, torch):
+    """Steps dealt round-robin to `lanes` lanes (a context, a stream, tables
+    and outputs each): step i runs on lane i mod lanes, so the builder of one
+    batch can run beside the star pass of the previous one.  Returns seconds
+    per step and the lanes' summed kernel profiles."""
+    ls = [make_lane() for _ in range(lanes)]
+    for i in range(warmup * lanes):
+        ls[i % lanes]["step"]()
+    torch.cuda.synchronize()
+    for ln in ls:
+        L.oss_ctx_profile(ln["ctx"].handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ls[i % lanes]["step"]()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    for ln in ls:
+        L.oss_ctx_profile(ln["ctx"].handle, False)
+        for k, v in L.oss_ctx_profile_read(ln["ctx"].handle).items():
+            a = prof.setdefault(k, [0, 0.0, 0.0])
+            a[0] += v[0]
+            a[1] += v[1]
+            a[2] = max(a[2], v[2])
+    return (t1 - t0) / steps, prof, ls
+
+
+OPTIONS = ("OSS_OPT_STAR_STRIP", "OSS_OPT_STAR_BLOCKS_PER_XCD", "OSS_OPT_STAR_LDS",
+           "OSS_OPT_BATCH_BUCKET", "OSS_OPT_TABLE_PLANAR", "OSS_OPT_STAR_PIPE",
+           "OSS_OPT_STAR_STAGED")
+
+
+def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, tol, cap, big, tfeat,
+              tfeat_rings, n, mask, cands):
+    """The same steps over `n_lanes` lanes (contexts with the main context's
+    options, own streams, tables and outputs).  Returns seconds per step, the
+    lanes' kernel profile and whether every lane's last result equals the
+    single-lane run's."""
+    from paper_1707_05647_amd.screen import Context
+
+    def make_lane():
+        c = Context(0)
+        for o in OPTIONS:
+            L.oss_ctx_set_option(c.handle, getattr(L, o),
+                                 L.oss_ctx_get_option(ctx.handle, getattr(L, o)))
+        st = torch.cuda.Stream(device=dev)
+        r = c.reference(img, ref_fm, w.depth, build=False, max_radius=max_r)
+        m = torch.empty_like(mask)
+        cd = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+        cn = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def step():
+            if args.rings > 1:
+                tm = tfeat_rings()
+                r.build(st)
+                L.oss_screen_rings(c.handle, r.handle, tm, w.probes, tol, w.feat_mask, m, cd,
+                                   cap, cn, st)
+            else:
+                tm = tfeat()
+                r.build(st)
+                L.oss_screen(c.handle, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn,
+                             st, batched=big)
+        return {"ctx": c, "ref": r, "step": step, "mask": m, "cands": cd, "count": cn}
+
+    sec, prof, lanes = run_pipelined(n_lanes, make_lane, args.steps, args.warmup, L, torch)
+    k = min(n, cap)
+    same = all(int(ln["count"].item()) == n and torch.equal(ln["mask"], mask)
+               and torch.equal(ln["cands"][:k], cands[:k]) for ln in lanes)
+    for ln in lanes:
+        ln["ref"].release()
+        ln["ctx"].close()
+    return sec, prof, same
+
+
 def run_steps(step, steps, warmup, ctx, L, torch):
     for _ in range(warmup):
         step()
@@ -442,7 +517,7 @@ def evaluate_regions(w, ctx, L, torch, dev, cands, count, cap):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
@@ -470,6 +545,10 @@ def main():
                     help="star kernel persistent blocks per XCD; 0 = library default")
     ap.add_argument("--pipe", type=int, default=-1,
                     help="1/0: software-pipelined / one-radius-at-a-time star pass; -1 = default")
+    ap.add_argument("--pipeline", type=int, default=-1,
+                    help="time the steps round-robin over this many lanes (a context, stream, "
+                         "tables and outputs each: consecutive batches overlap); 1 = one lane; "
+                         "-1 = 2 for workload 2 (also with rings), else 1")
     ap.add_argument("--staged", type=int, default=-1,
                     help="1/0: staged lookups (first quantity alone, the rest where it passes) / "
                          "every quantity at every lookup; -1 = library default")
@@ -624,6 +703,19 @@ def main():
         ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
     n = int(count.item())
+    lanes = args.pipeline if args.pipeline >= 1 else (2 if args.workload == 2 else 1)
+    if args.alg1 or args.moments:
+        lanes = 1
+    if lanes >= 2:
+        # the timed figures below are the lanes' run; the single lane's are kept
+        extra["single_lane"] = {
+            "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
+                        for k, v in prof.items()}}
+        sec, prof, same = pipelined(args, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, tol,
+                                    cap, big, tfeat, tfeat_rings, n, mask, cands)
+        extra["lanes_identical_to_single_lane"] = same
+        value = ps / sec / 1e9
     eb = sum(b // 8 for _, b in ref.slots)  # table bytes per position, all quantities
     staged = (ref.plane_bytes > 0 and len(ref.slots) > 1 and not args.moments
               and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED) == 1
@@ -694,6 +786,7 @@ def main():
             "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if (big or args.rings > 1) else "plain",
+            "lanes": lanes,
             "rings": args.rings,
             "alg1": bool(args.alg1),
             "moments": bool(args.moments),
