@@ -597,19 +597,54 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
             TD[q] = cD[e + q];
         }
     }
-    // pixels: rolling window of the current row (left, centre, right) and
-    // the centre of the row above
-    const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < W ? x + 1 : W - 1;
-    int pl = 0, pc = 0, pr = 0, pu = 0;
-    if (inside) {
-        const int y0 = ys < 0 ? 0 : ys;
-        const int yu0 = y0 > 0 ? y0 - 1 : 0;
-        const Pix *row = img + (int64_t)y0 * pitch;
-        pl = row[xl];
-        pc = row[x];
-        pr = row[xr];
-        pu = img[(int64_t)yu0 * pitch + x];
+    // The band's pixels (rows ys-1 .. ys+rows, columns X0-1 .. X0+512, both
+    // clamped into the image) and row-prefix bases are staged in LDS first,
+    // so the row loop issues no global loads: a global load consumed while
+    // the previous rows' table stores are in flight would wait for those
+    // stores too (loads and stores share one counter), one store round trip
+    // per row.
+    constexpr int PXW = BAND_THREADS + 2;
+    __shared__ Pix s_px[KBAND + 2][PXW];
+    __shared__ T s_base[KBAND][NQ];
+    {
+        // every row's load in flight together (no branch between them; rows
+        // past the band are clamped reads that nothing uses): thread tid
+        // stages LDS column tid, threads 0 and 1 also columns 512 and 513
+        static_assert(PXW - BAND_THREADS == 2, "two extra staged columns");
+        int xa = X0 - 1 + tid;
+        xa = xa < 0 ? 0 : (xa > W - 1 ? W - 1 : xa);
+        int va[KBAND + 2];
+#pragma unroll
+        for (int rr = 0; rr < KBAND + 2; ++rr) {
+            int yy = ys - 1 + rr;
+            yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+            va[rr] = img[(int64_t)yy * pitch + xa];
+        }
+#pragma unroll
+        for (int rr = 0; rr < KBAND + 2; ++rr)
+            s_px[rr][tid] = (Pix)va[rr];
+        if (tid < PXW - BAND_THREADS) {
+            int xb = X0 - 1 + BAND_THREADS + tid;
+            xb = xb < 0 ? 0 : (xb > W - 1 ? W - 1 : xb);
+            int vb[KBAND + 2];
+#pragma unroll
+            for (int rr = 0; rr < KBAND + 2; ++rr) {
+                int yy = ys - 1 + rr;
+                yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+                vb[rr] = img[(int64_t)yy * pitch + xb];
+            }
+#pragma unroll
+            for (int rr = 0; rr < KBAND + 2; ++rr)
+                s_px[rr][BAND_THREADS + tid] = (Pix)vb[rr];
+        }
     }
+    if (tid < rows * NQ) {
+        const int k = tid / NQ, q = tid - k * NQ;
+        const int y = ys + k;
+        s_base[k][q] = y >= 0 ? tile_base(bp, g, y, X0, NQ)[q] : (T)0;
+    }
+    __syncthreads();
+    const int cx = x - X0 + 1;  // LDS column of image column x
 
     for (int k = 0; k < rows; ++k) {
         const int y = ys + k;
@@ -618,14 +653,10 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
         for (int q = 0; q < NQ; ++q)
             s[q] = 0;
         if (y >= 0 && inside) {
-            const int yd = y + 1 < H ? y + 1 : H - 1;
-            const Pix *nrow = img + (int64_t)yd * pitch;
-            const int nl = nrow[xl], nc = nrow[x], nr = nrow[xr];
-            quantities<FM, T>(pc, pl, pr, pu, nc, x, y, s);
-            pu = pc;
-            pl = nl;
-            pc = nc;
-            pr = nr;
+            // LDS row k + 1 holds image row y; rows k and k + 2 the clamped
+            // rows above and below; columns cx -+ 1 the clamped neighbours
+            quantities<FM, T>(s_px[k + 1][cx], s_px[k + 1][cx - 1], s_px[k + 1][cx + 1],
+                              s_px[k][cx], s_px[k + 2][cx], x, y, s);
         }
         const int buf = k & 1;
 #pragma unroll
@@ -639,14 +670,13 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
                 s_eta[buf][wid][q] = TA[q];
         }
         __syncthreads();
-        const T *base = y >= 0 ? tile_base(bp, g, y, X0, NQ) : nullptr;
         T ta_r[NQ], td_l[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             // the row prefix of the tile start plus the totals of the waves
             // to the left of this one
             const T wt = lane < NW ? s_wt[buf][lane & (NW - 1)][q] : (T)0;
-            const T off = (base ? base[q] : (T)0) + first_n_sum(wt, wid);
+            const T off = s_base[k][q] + first_n_sum(wt, wid);
             const T P = off + s[q];
             ta_r[q] = from_right(TA[q]);
             td_l[q] = from_left(TD[q]);
