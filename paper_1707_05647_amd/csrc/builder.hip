@@ -198,6 +198,7 @@ __device__ __forceinline__ const T *tile_base(const T *__restrict__ bp, const Bu
 // the row total.  One block per row; a wave reduces 64-column chunks.
 // ---------------------------------------------------------------------------
 constexpr int RB_THREADS = 256;
+constexpr int RB_MU = 4;  // chunks whose loads a wave has in flight together
 
 template <typename Pix, unsigned FM, typename T>
 __global__ __launch_bounds__(RB_THREADS) void row_base_kernel(const Pix *__restrict__ img,
@@ -220,21 +221,32 @@ __global__ __launch_bounds__(RB_THREADS) void row_base_kernel(const Pix *__restr
         for (int q = 0; q < NQ; ++q)
             out[q] = 0;
     }
+    constexpr int NWV = RB_THREADS / 64;
     for (int m0 = 0; m0 < nch; m0 += RB_THREADS) {
-        // chunk sums for chunks m0 .. m0 + 255
-        for (int m = m0 + wid; m < min(m0 + RB_THREADS, nch); m += RB_THREADS / 64) {
-            const int x = m * 64 + lane;
-            T q[NQ];
+        // chunk sums for chunks m0 .. m0 + 255; a wave loads RB_MU chunks
+        // before it scans any (clamped reads, out-of-range values zeroed)
+        const int mend = min(m0 + RB_THREADS, nch);
+        for (int mb = m0 + wid; mb < mend; mb += NWV * RB_MU) {
+            T q[RB_MU][NQ];
 #pragma unroll
-            for (int k = 0; k < NQ; ++k)
-                q[k] = 0;
-            if (x < g.W)
-                load_q<Pix, FM, T>(img, pitch, g.H, g.W, x, y, q);
+            for (int u = 0; u < RB_MU; ++u) {
+                const int m = mb + NWV * u;
+                const int x = m * 64 + lane;
+                const bool ok = m < mend && x < g.W;
+                load_q<Pix, FM, T>(img, pitch, g.H, g.W, ok ? x : g.W - 1, y, q[u]);
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) {
-                const T s = lane63(wave_scan(q[k]));
-                if (lane == 0)
-                    s_chunk[k][m - m0] = s;
+                for (int k = 0; k < NQ; ++k)
+                    q[u][k] = ok ? q[u][k] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < RB_MU; ++u) {
+                const int m = mb + NWV * u;
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    const T s = lane63(wave_scan(q[u][k]));
+                    if (lane == 0 && m < mend)
+                        s_chunk[k][m - m0] = s;
+                }
             }
         }
         __syncthreads();
@@ -261,6 +273,50 @@ __global__ __launch_bounds__(RB_THREADS) void row_base_kernel(const Pix *__restr
             carry[k] = tot;
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A band tile's pixels in LDS: px[rr][cc] = image pixel (clamped row
+// ys - 1 + rr, clamped column X0 - 1 + cc) for rr < KBAND + 2, cc < PXW, so
+// pixel (x, y) of the band and its clamped neighbours are px[y - ys + 1]
+// [x - X0 + 1 +- 1] and the rows above and below.  Every row's load is in
+// flight together (no branch between them; rows past the band are clamped
+// reads that nothing uses).  Followed by a barrier in the caller.
+// ---------------------------------------------------------------------------
+constexpr int PXW = BAND_THREADS + 2;
+
+template <typename Pix>
+__device__ __forceinline__ void stage_band_pixels(Pix (*px)[PXW], const Pix *__restrict__ img,
+                                                  int64_t pitch, int X0, int ys, int H, int W)
+{
+    static_assert(PXW - BAND_THREADS == 2, "two extra staged columns");
+    const int tid = threadIdx.x;
+    int xa = X0 - 1 + tid;
+    xa = xa < 0 ? 0 : (xa > W - 1 ? W - 1 : xa);
+    int va[KBAND + 2];
+#pragma unroll
+    for (int rr = 0; rr < KBAND + 2; ++rr) {
+        int yy = ys - 1 + rr;
+        yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+        va[rr] = img[(int64_t)yy * pitch + xa];
+    }
+#pragma unroll
+    for (int rr = 0; rr < KBAND + 2; ++rr)
+        px[rr][tid] = (Pix)va[rr];
+    if (tid < PXW - BAND_THREADS) {  // columns 512 and 513
+        int xb = X0 - 1 + BAND_THREADS + tid;
+        xb = xb < 0 ? 0 : (xb > W - 1 ? W - 1 : xb);
+        int vb[KBAND + 2];
+#pragma unroll
+        for (int rr = 0; rr < KBAND + 2; ++rr) {
+            int yy = ys - 1 + rr;
+            yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+            vb[rr] = img[(int64_t)yy * pitch + xb];
+        }
+#pragma unroll
+        for (int rr = 0; rr < KBAND + 2; ++rr)
+            px[rr][BAND_THREADS + tid] = (Pix)vb[rr];
     }
 }
 
@@ -341,18 +397,30 @@ __global__ __launch_bounds__(BAND_THREADS) void band_agg_kernel(
         B[q] = 0;
     }
     const bool inside = x >= 0 && x < g.W;
+    // the band's pixels and row-prefix bases in LDS first: no global load
+    // waits inside the row loop
+    __shared__ Pix s_px[KBAND + 2][PXW];
+    __shared__ T s_base[KBAND][NQ];
+    stage_band_pixels<Pix>(s_px, img, pitch, X0, ys, g.H, g.W);
+    if (tid < rows * NQ) {
+        const int k = tid / NQ, q = tid - k * NQ;
+        const int y = ys + k;
+        s_base[k][q] = y >= 0 ? tile_base(bp, g, y, X0, NQ)[q] : (T)0;
+    }
+    __syncthreads();
+    const int cx = x - X0 + 1;  // LDS column of image column x
     for (int k = 0; k < rows; ++k) {
         const int y = ys + k;
         if (y < 0)
             continue;
-        const T *base = tile_base(bp, g, y, X0, NQ);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            B[q] += base[q];
+            B[q] += s_base[k][q];
         if (!inside)
             continue;
         T qv[NQ];
-        load_q<Pix, FM, T>(img, pitch, g.H, g.W, x, y, qv);
+        quantities<FM, T>(s_px[k + 1][cx], s_px[k + 1][cx - 1], s_px[k + 1][cx + 1],
+                          s_px[k][cx], s_px[k + 2][cx], x, y, qv);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             col[q] += qv[q];
@@ -603,41 +671,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     // the previous rows' table stores are in flight would wait for those
     // stores too (loads and stores share one counter), one store round trip
     // per row.
-    constexpr int PXW = BAND_THREADS + 2;
     __shared__ Pix s_px[KBAND + 2][PXW];
     __shared__ T s_base[KBAND][NQ];
-    {
-        // every row's load in flight together (no branch between them; rows
-        // past the band are clamped reads that nothing uses): thread tid
-        // stages LDS column tid, threads 0 and 1 also columns 512 and 513
-        static_assert(PXW - BAND_THREADS == 2, "two extra staged columns");
-        int xa = X0 - 1 + tid;
-        xa = xa < 0 ? 0 : (xa > W - 1 ? W - 1 : xa);
-        int va[KBAND + 2];
-#pragma unroll
-        for (int rr = 0; rr < KBAND + 2; ++rr) {
-            int yy = ys - 1 + rr;
-            yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
-            va[rr] = img[(int64_t)yy * pitch + xa];
-        }
-#pragma unroll
-        for (int rr = 0; rr < KBAND + 2; ++rr)
-            s_px[rr][tid] = (Pix)va[rr];
-        if (tid < PXW - BAND_THREADS) {
-            int xb = X0 - 1 + BAND_THREADS + tid;
-            xb = xb < 0 ? 0 : (xb > W - 1 ? W - 1 : xb);
-            int vb[KBAND + 2];
-#pragma unroll
-            for (int rr = 0; rr < KBAND + 2; ++rr) {
-                int yy = ys - 1 + rr;
-                yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
-                vb[rr] = img[(int64_t)yy * pitch + xb];
-            }
-#pragma unroll
-            for (int rr = 0; rr < KBAND + 2; ++rr)
-                s_px[rr][BAND_THREADS + tid] = (Pix)vb[rr];
-        }
-    }
+    stage_band_pixels<Pix>(s_px, img, pitch, X0, ys, H, W);
     if (tid < rows * NQ) {
         const int k = tid / NQ, q = tid - k * NQ;
         const int y = ys + k;
