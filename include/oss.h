@@ -303,7 +303,8 @@ int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl, 
  * Same contract and outputs as oss_screen, with all templates and probes in
  * one persistent launch over the reference's tables (Algorithm 1's patch
  * loop for every template and scale together).  Templates are sorted by
- * radius and taken in groups of 32; within a group the star features of
+ * radius and taken in groups of 64 (32 by oss_screen_rings); within a
+ * group the star features of
  * each distinct radius are computed once per position and compared with
  * every probe of the group at that radius.  A group's radii are walked in
  * passes of at most OSS_OPT_BATCH_BUCKET distinct radii.  Results are

@@ -758,7 +758,8 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
 // ---------------------------------------------------------------------------
 // Batched screen.
 // ---------------------------------------------------------------------------
-// Templates sorted by radius and cut into groups of BATCH_GROUP; each group's
+// Templates sorted by radius and cut into groups of BATCH_GROUP (with rings
+// BATCH_GROUP_RINGS); each group's
 // probes sorted by reference radius; every run of at most `bucket` distinct
 // radii (0: all) becomes one pass.
 // One entry of a template's part of a batched plan: a test at radius r
@@ -768,14 +769,16 @@ struct PlanEntry {
     int64_t lo[3], hi[3];
 };
 
-// Groups of at most BATCH_GROUP templates in `order`, each group's entries
-// sorted by radius, passes over runs of at most `bucket` distinct radii.
+// Groups of at most BATCH_GROUP (with rings BATCH_GROUP_RINGS) templates in
+// `order`, each group's entries sorted by radius, passes over runs of at most
+// `bucket` distinct radii.  bp.rings must be set.
 static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
                          const std::vector<int> &order, int bucket, BatchHostPlan &bp)
 {
     const int n_tmpl = (int)order.size();
-    for (int g0 = 0; g0 < n_tmpl; g0 += BATCH_GROUP) {
-        const int nt = std::min(BATCH_GROUP, n_tmpl - g0);
+    const int gmax = bp.rings > 1 ? BATCH_GROUP_RINGS : BATCH_GROUP;
+    for (int g0 = 0; g0 < n_tmpl; g0 += gmax) {
+        const int nt = std::min(gmax, n_tmpl - g0);
         DevBatchGroup grp{};
         grp.n_t = nt;
         struct Item {

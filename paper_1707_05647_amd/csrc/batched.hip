@@ -61,14 +61,24 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
             const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
             const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
             const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
-            uint32_t acc[MT];            // scale bits whose own star passes
-            uint32_t fail[RINGS ? MT : 1];  // scale bits a central star fails
+            // Scale bits per template slot: whose own star passes (acc) and
+            // which a central star fails (fail).  An array indexed by the
+            // wave-uniform slot stays in registers up to 32 entries, so a
+            // group of 64 (no rings) keeps a second half, picked by a
+            // uniform branch.
+            static_assert(!RINGS || MT <= 32, "groups with rings hold at most 32 templates");
+            uint32_t acc[MT > 32 ? 32 : MT];
+            uint32_t acc_hi[MT > 32 ? MT - 32 : 1];
+            uint32_t fail[RINGS ? MT : 1];
 #pragma unroll
-            for (int t = 0; t < MT; ++t) {
+            for (int t = 0; t < (MT > 32 ? 32 : MT); ++t) {
                 acc[t] = 0;
                 if constexpr (RINGS)
                     fail[t] = 0;
             }
+#pragma unroll
+            for (int t = 0; t < (MT > 32 ? MT - 32 : 1); ++t)
+                acc_hi[t] = 0;
             for (int jr = ps.j0; jr < ps.j1; ++jr) {
                 const DevBatchRadius &rd = radii[jr];
                 const int r = rd.r, s = rd.s;
@@ -133,13 +143,19 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
                             pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                        const uint32_t bit = pass ? (1u << pr.k) : 0u;
                         if constexpr (RINGS) {
                             if (pr.ring)
                                 fail[pr.t] |= pass ? 0u : (1u << pr.k);
                             else
-                                acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                                acc[pr.t] |= bit;
+                        } else if constexpr (MT > 32) {
+                            if (pr.t < 32)
+                                acc[pr.t] |= bit;
+                            else
+                                acc_hi[pr.t - 32] |= bit;
                         } else {
-                            acc[pr.t] |= pass ? (1u << pr.k) : 0u;
+                            acc[pr.t] |= bit;
                         }
                     }
                 }
@@ -149,7 +165,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 for (int t = 0; t < MT; ++t) {
                     if (t < nt) {
                         uint32_t *w = bits + (int64_t)grp->tmap[t] * hw + (int64_t)y * W + x;
-                        uint32_t v = acc[t];
+                        uint32_t v = t < 32 ? acc[t < 32 ? t : 0] : acc_hi[t >= 32 ? t - 32 : 0];
                         if constexpr (RINGS)
                             v &= ~fail[t];  // one pass per group: final here
                         *w = ps.first ? v : (*w | v);
@@ -179,8 +195,10 @@ static void batch_launch_s(const BuildGeom &g, const void *L, const void *R, con
         OSS_BATCH_LAUNCH(8, false);
     } else if (bp.max_group <= 16) {
         OSS_BATCH_LAUNCH(16, false);
-    } else {
+    } else if (bp.max_group <= 32) {
         OSS_BATCH_LAUNCH(32, false);
+    } else {
+        OSS_BATCH_LAUNCH(64, false);
     }
 #undef OSS_BATCH_LAUNCH
 }
@@ -250,7 +268,7 @@ hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, c
                              bool staged, hipStream_t stream, Profiler *prof)
 {
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
-        bp.max_group > BATCH_GROUP)
+        bp.max_group > (bp.rings > 1 ? BATCH_GROUP_RINGS : BATCH_GROUP))
         return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_BATCH, stream);
     if (g.sqi >= 0)

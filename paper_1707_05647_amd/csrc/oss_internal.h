@@ -87,7 +87,8 @@ struct DevTemplatePlan {
 };
 
 // Batched plan (all templates of a screen in one persistent launch).
-constexpr int BATCH_GROUP = 32;  // templates per group (scale bits kept in registers)
+constexpr int BATCH_GROUP = 64;        // templates per group (scale bits kept in registers)
+constexpr int BATCH_GROUP_RINGS = 32;  // with central-star rings (pass and fail bits)
 
 struct DevBatchProbe {
     int64_t lo[3];

@@ -59,9 +59,11 @@ def test_batched_equals_oracle_cfg3(runner, bucket):
     assert np.array_equal(got[1], wlist)
 
 
-def test_batched_equals_plain_many_templates(runner):
-    """40 templates: two groups of the register-resident scale bits."""
-    w = make_workload(3, 2, H=192, W=224, n_templates=40, blobs_per_512sq=1500, sig_hi=16)
+@pytest.mark.parametrize("n_t", [40, 70])
+def test_batched_equals_plain_many_templates(runner, n_t):
+    """40 templates: one group, its slots 32.. in the second register half;
+    70: two groups (64 + 6)."""
+    w = make_workload(3, 2, H=192, W=224, n_templates=n_t, blobs_per_512sq=1500, sig_hi=16)
     say(f"batched vs plain: {len(w.templates)} templates, {len(w.probes)} probes")
     a = _screen(runner, w, False)
     for opts in ({}, {runner.L.OSS_OPT_BATCH_BUCKET: 2},
