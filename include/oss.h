@@ -139,9 +139,10 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *   OSS_OPT_STAR_BLOCKS_PER_XCD  persistent star blocks per XCD, about the
  *                                rows of one strip an XCD has in flight
  *                                (default 64)
- *   OSS_OPT_STAR_LDS             1: stage the table rows that several
- *                                lookups share in LDS; 0: load every lookup
- *                                directly (default)
+ *   OSS_OPT_STAR_LDS             1: oss_screen stages the table rows that
+ *                                several lookups share in LDS (interleaved
+ *                                tables with one value width only); 0: load
+ *                                every lookup directly (default)
  *   OSS_OPT_BATCH_BUCKET         oss_screen_batched: at most this many distinct
  *                                radii per pass (0: all radii of a template
  *                                group in one pass; default 0)
@@ -160,8 +161,8 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                alone and the others only where some probe
  *                                (batched: the radius' interval hull) admits
  *                                it (default); 0: every quantity at every
- *                                lookup.  The LDS and pipelining options
- *                                take precedence
+ *                                lookup.  The pipelining option takes
+ *                                precedence
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
