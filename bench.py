@@ -688,9 +688,23 @@ def main():
                 "bucket_radii": tr.bucket_radii, "ms": tr.ms,
                 "tried": [[tr.tried[i][0], tr.tried[i][1], tr.tried[i][2], tr.tried_ms[i]]
                           for i in range(tr.n_tried)]}
-        plain_s, plain_prof = run_steps(make_step(False), max(1, args.steps // 4), 1, ctx, L,
-                                        torch)
+        # the per-template launches at their own best shape (strip 512,
+        # 32 / 64 / 128 blocks per XCD), then the batched shape again
+        tuned = [L.oss_ctx_get_option(ctx.handle, o)
+                 for o in (L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD)]
+        best = None
+        for blocks in (32, 64, 128):
+            L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, 512)
+            L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, blocks)
+            plain_s, plain_prof = run_steps(make_step(False), max(1, args.steps // 4), 1, ctx, L,
+                                            torch)
+            if best is None or plain_s < best[0]:
+                best = (plain_s, plain_prof, blocks)
+        for o, v in zip((L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD), tuned):
+            L.oss_ctx_set_option(ctx.handle, o, v)
+        plain_s, plain_prof, blocks = best
         extra["plain_ms_per_step"] = plain_s * 1e3
+        extra["plain_shape"] = {"strip": 512, "blocks_per_xcd": blocks}
         extra["plain_kernels"] = {k: v[1] / max(v[0], 1) for k, v in plain_prof.items()}
     sec, prof = run_steps(make_step(big or args.rings > 1), args.steps, args.warmup, ctx, L,
                           torch)
