@@ -148,9 +148,7 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                group in one pass; default 0)
  *   OSS_OPT_TABLE_PLANAR         1: references created afterwards store each
  *                                quantity in a table plane of its own
- *                                (default); 0: side by side in one entry.
- *                                References with first moments are always
- *                                interleaved
+ *                                (default); 0: side by side in one entry
  *   OSS_OPT_STAR_PIPE            1: oss_screen's star pass issues the next
  *                                radius' lookups before comparing the
  *                                current one (software pipelining); the LDS

@@ -209,8 +209,7 @@ static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
 // sum of it up to the maximum radius stays below 2^32.  All quantities fit:
 // 32-bit values.  Only the squares do not: the squares in 64 bits, the others
 // in 32.  Otherwise 64-bit values.  Planar (the default) or interleaved
-// entries as the context asks; references with first moments are always
-// interleaved.
+// entries as the context asks.
 static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int planar)
 {
     const __int128 s = square_half(R);
@@ -223,7 +222,7 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int p
         // magnitude: stored modulo 2^32 when that stays below 2^31
         const __int128 maxv = ((__int128)1 << d->bit_depth) - 1;
         const bool m32 = maxv * R * area < ((__int128)1 << 31);
-        return make_geom(d->H, d->W, nq, (fits(fm & OSS_F_ALL) && m32) ? 4 : 8);
+        return make_geom(d->H, d->W, nq, (fits(fm & OSS_F_ALL) && m32) ? 4 : 8, -1, planar);
     }
     if (fits(fm))
         return make_geom(d->H, d->W, nq, 4, -1, planar);

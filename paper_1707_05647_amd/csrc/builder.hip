@@ -841,6 +841,8 @@ static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint
         case 5: return build_t<Pix, 5, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
         case 6: return build_t<Pix, 6, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
         case 7: return build_t<Pix, 7, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 25: return build_t<Pix, 25, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
+        case 27: return build_t<Pix, 27, T, LAY_PLANAR>(g, px, pb, bb, st, pr);
         default: return hipErrorInvalidValue;
         }
     }

@@ -13,6 +13,9 @@
 //   magnitude: loM <= M = Sx^2 + Sy^2 <= hiM             (128-bit)
 // with the bounds solved on the host from the template's features and the
 // tolerance.  Same persistent XCD-aware strip sweep as the plain screen.
+// With planar tables the lookups are staged as in the plain screen: the sum
+// plane first (the mean test), the other planes only for the positions where
+// some probe of the radius passes it.
 #include "star_common.h"
 
 namespace oss {
@@ -20,16 +23,17 @@ namespace oss {
 __device__ __forceinline__ int64_t sext(uint32_t v) { return (int64_t)(int32_t)v; }
 __device__ __forceinline__ int64_t sext(uint64_t v) { return (int64_t)v; }
 
-template <typename T, unsigned FM>
+template <typename T, unsigned FM, bool PLANAR>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_moments_kernel(
     const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
-    int H, int W, const DevMomPlan *__restrict__ plan, uint32_t *__restrict__ bits, StarSweep sw)
+    int64_t plane, int H, int W, const DevMomPlan *__restrict__ plan,
+    uint32_t *__restrict__ bits, StarSweep sw)
 {
     constexpr bool HAS_SQ = (FM & OSS_F_SQ) != 0;
     constexpr int NQ = HAS_SQ ? 4 : 3;
     constexpr int XM = NQ - 2, YM = NQ - 1;
     using E = Entry<T, NQ>;
-    constexpr int64_t ES = (int64_t)sizeof(E);
+    constexpr int64_t ES = PLANAR ? (int64_t)sizeof(T) : (int64_t)sizeof(E);
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int units = (sw.n_units - xcd + 7) / 8;
     const int items = units * sw.rows_per_part;
@@ -60,15 +64,41 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_moments_kernel(
             const char *rp_mid = Rpb + (int64_t)y * row_bytes;
             const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
             const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
-            const E a = entry_at<E>(l_bot + ds, lane_off), b = entry_at<E>(l_bot - ds1, lane_off);
-            const E c = entry_at<E>(l_top + ds, lane_off), d = entry_at<E>(l_top - ds1, lane_off);
-            const E e = entry_at<E>(r_bot, lane_off), f = entry_at<E>(rp_mid - dr1, lane_off);
-            const E h = entry_at<E>(rp_mid + dr, lane_off), k = entry_at<E>(r_top, lane_off);
             T sq[NQ], dm[NQ];
+            if constexpr (PLANAR) {
+                // quantity q of a lookup: plane q at the same entry offset
+                const char *pa = l_bot + ds + lane_off, *pb = l_bot - ds1 + lane_off;
+                const char *pc = l_top + ds + lane_off, *pd = l_top - ds1 + lane_off;
+                const char *pe = r_bot + lane_off, *pf = rp_mid - dr1 + lane_off;
+                const char *ph = rp_mid + dr + lane_off, *pk = r_top + lane_off;
+                auto at = [&](const char *p, int q) {
+                    return *reinterpret_cast<const T *>(p + q * plane);
+                };
+                sq[0] = (T)(at(pa, 0) - at(pb, 0) - at(pc, 0) + at(pd, 0));
+                dm[0] = (T)(at(pe, 0) - at(pf, 0) - at(ph, 0) + at(pk, 0));
+                const int64_t F1 = (int64_t)sq[0] + (int64_t)dm[0];
+                bool maybe = false;
+                for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                    const DevMomProbe &pr = plan->probes[p];
+                    maybe = maybe | !(pr.tests & 1) | ((F1 >= pr.lo1) & (F1 <= pr.hi1));
+                }
+                if (__builtin_amdgcn_ballot_w64(maybe) == 0 || !maybe)
+                    continue;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                sq[q] = (T)(a.v[q] - b.v[q] - c.v[q] + d.v[q]);
-                dm[q] = (T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]);
+                for (int q = 1; q < NQ; ++q) {
+                    sq[q] = (T)(at(pa, q) - at(pb, q) - at(pc, q) + at(pd, q));
+                    dm[q] = (T)(at(pe, q) - at(pf, q) - at(ph, q) + at(pk, q));
+                }
+            } else {
+                const E a = entry_at<E>(l_bot + ds, lane_off), b = entry_at<E>(l_bot - ds1, lane_off);
+                const E c = entry_at<E>(l_top + ds, lane_off), d = entry_at<E>(l_top - ds1, lane_off);
+                const E e = entry_at<E>(r_bot, lane_off), f = entry_at<E>(rp_mid - dr1, lane_off);
+                const E h = entry_at<E>(rp_mid + dr, lane_off), k = entry_at<E>(r_top, lane_off);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    sq[q] = (T)(a.v[q] - b.v[q] - c.v[q] + d.v[q]);
+                    dm[q] = (T)(e.v[q] - f.v[q] - h.v[q] + k.v[q]);
+                }
             }
             const int64_t F1 = (int64_t)sq[0] + (int64_t)dm[0];
             const int64_t Sx = sext((T)(sq[XM] - (T)x * sq[0])) + sext((T)(dm[XM] - (T)x * dm[0]));
@@ -109,14 +139,21 @@ static hipError_t moments_t(const BuildGeom &g, uint32_t fm, const void *L, cons
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
-    if (fm == (OSS_F_SUM | OSS_F_MOMENTS))
-        hipLaunchKernelGGL((star_moments_kernel<T, OSS_F_SUM | OSS_F_MOMENTS>), grid, block, 0, st,
-                           l, r, rp, g.pitch_e, g.H, g.W, plan, bits, sw);
-    else if (fm == (OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS))
-        hipLaunchKernelGGL((star_moments_kernel<T, OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS>), grid,
-                           block, 0, st, l, r, rp, g.pitch_e, g.H, g.W, plan, bits, sw);
+    constexpr unsigned F3 = OSS_F_SUM | OSS_F_MOMENTS, F4 = OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS;
+#define OSS_MOM_LAUNCH(FMV, PL)                                                                   \
+    hipLaunchKernelGGL((star_moments_kernel<T, FMV, PL>), grid, block, 0, st, l, r, rp, g.pitch_e, \
+                       g.plane, g.H, g.W, plan, bits, sw)
+    if (fm == F3 && g.planar)
+        OSS_MOM_LAUNCH(F3, true);
+    else if (fm == F3)
+        OSS_MOM_LAUNCH(F3, false);
+    else if (fm == F4 && g.planar)
+        OSS_MOM_LAUNCH(F4, true);
+    else if (fm == F4)
+        OSS_MOM_LAUNCH(F4, false);
     else
         return hipErrorInvalidValue;
+#undef OSS_MOM_LAUNCH
     return hipGetLastError();
 }
 
@@ -125,7 +162,7 @@ hipError_t launch_star_moments(const BuildGeom &g, uint32_t fm, const void *L, c
                                const StarSweep &sw, hipStream_t stream, Profiler *prof)
 {
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
-        g.sqi >= 0 || g.planar)
+        g.sqi >= 0)
         return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_MOM, stream);
     if (g.ebytes == 4)

@@ -20,10 +20,16 @@ def runner():
     r.close()
 
 
-def _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r):
+def _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r, planar=1):
     L = runner.L
     torch = runner.torch
-    ref = runner.ctx.reference(L.device_image(img, runner.dev), fm, depth, max_radius=max_r)
+    h = runner.ctx.handle
+    L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_PLANAR, planar)
+    try:
+        ref = runner.ctx.reference(L.device_image(img, runner.dev), fm, depth, max_radius=max_r)
+    finally:
+        L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_PLANAR, 1)
+    assert (ref.plane_bytes > 0) == bool(planar)
     tm = [L.oss_template_moments(px, rho, bit_depth=depth) for px, rho in templates]
     T = len(tm)
     H, W = img.shape
@@ -42,8 +48,9 @@ def _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r):
     return out
 
 
-def _check(runner, img, templates, probes, tol, tests, fm, depth, max_r):
-    mask, lst, n, vb = _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r)
+def _check(runner, img, templates, probes, tol, tests, fm, depth, max_r, planar=1):
+    mask, lst, n, vb = _screen(runner, img, templates, probes, tol, tests, fm, depth, max_r,
+                               planar)
     want = om.screen_full(img, templates, probes, tol[:3], tol[3], tests)
     wmask, wlist = oc.mask_and_list(want)
     say(f"  moments tests={tests} fm={fm} {vb}-bit: {n} candidates (oracle {len(wlist)})")
@@ -51,21 +58,29 @@ def _check(runner, img, templates, probes, tol, tests, fm, depth, max_r):
     return n
 
 
+PLANAR = pytest.mark.parametrize("planar", [1, 0], ids=["planar", "interleaved"])
+
+
+@PLANAR
 @pytest.mark.parametrize("tests", [1, 2, 4, 7])
-def test_moments_cfg2(runner, tests):
+def test_moments_cfg2(runner, tests, planar):
+    """Planar tables take the staged lookups (the mean first; without a mean
+    test every position goes on); interleaved ones read every quantity."""
     w = make_workload(2, 2, H=150, W=170, blobs_per_512sq=1200, sig_hi=20)
     tms = [(t.pixels, t.rho) for t in w.templates]
     probes = [p for p in w.probes if 2 * p[2] + 1 <= 150]
     n = _check(runner, w.ref, tms, probes, (6, 30, 40, 100), tests, 27, 8,
-               max(p[2] for p in probes))
+               max(p[2] for p in probes), planar)
     assert n > 0
 
 
-def test_moments_cfg5_64bit(runner):
+@PLANAR
+def test_moments_cfg5_64bit(runner, planar):
     w = make_workload(5, 3, H=230, W=250, n_templates=2, blobs_per_512sq=1200, sig_hi=20)
     tms = [(t.pixels, t.rho) for t in w.templates]
     probes = [p for p in w.probes if p[2] <= 60]
-    _check(runner, w.ref, tms, probes, (8, 40, 50, 100), 7, 27, 12, max(p[2] for p in probes))
+    _check(runner, w.ref, tms, probes, (8, 40, 50, 100), 7, 27, 12, max(p[2] for p in probes),
+           planar)
 
 
 def test_moments_mean_and_magnitude_only(runner):

@@ -62,7 +62,7 @@ def test_tables_match_definitions(runner, case, planar):
         L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
     torch.cuda.synchronize()
     assert len(ref.slots) == bin(fm).count("1")
-    if planar and not fm & 24:  # moments stay interleaved
+    if planar:
         assert ref.plane_bytes > 0
         widths = {b for _, b in ref.slots}
         # 32-bit planes, also when the squares alone take two of them
