@@ -203,8 +203,8 @@ OPTIONS = ("OSS_OPT_STAR_STRIP", "OSS_OPT_STAR_BLOCKS_PER_XCD", "OSS_OPT_STAR_LD
            "OSS_OPT_STAR_STAGED")
 
 
-def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, tol, cap, big, tfeat,
-              tfeat_rings, n, mask, cands):
+def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, batched,
+              screen_step, n, mask, cands):
     """The same steps over `n_lanes` lanes (contexts with the main context's
     options, own streams, tables and outputs).  Returns seconds per step, the
     lanes' kernel profile and whether every lane's last result equals the
@@ -223,16 +223,7 @@ def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, tol, cap
         cn = torch.zeros(1, dtype=torch.int64, device=dev)
 
         def step():
-            if args.rings > 1:
-                tm = tfeat_rings()
-                r.build(st)
-                L.oss_screen_rings(c.handle, r.handle, tm, w.probes, tol, w.feat_mask, m, cd,
-                                   cap, cn, st)
-            else:
-                tm = tfeat()
-                r.build(st)
-                L.oss_screen(c.handle, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn,
-                             st, batched=big)
+            screen_step(c.handle, r, st, m, cd, cn, batched)
         return {"ctx": c, "ref": r, "step": step, "mask": m, "cands": cd, "count": cn}
 
     sec, prof, lanes = run_pipelined(n_lanes, make_lane, args.steps, args.warmup, L, torch)
@@ -548,7 +539,7 @@ def main():
     ap.add_argument("--pipeline", type=int, default=-1,
                     help="time the steps round-robin over this many lanes (a context, stream, "
                          "tables and outputs each: consecutive batches overlap); 1 = one lane; "
-                         "-1 = 2 for workload 2 (also with rings), else 1")
+                         "-1 = 2 for workload 2 (every variant), else 1")
     ap.add_argument("--staged", type=int, default=-1,
                     help="1/0: staged lookups (first quantity alone, the rest where it passes) / "
                          "every quantity at every lookup; -1 = library default")
@@ -636,38 +627,31 @@ def main():
                                      w.feat_mask, bit_depth=w.depth)
         return out
 
-    def make_step(batched):
-        def step_alg1():
-            pr = alg1_probes()
-            ref.build(stream)
-            L.oss_screen_intervals(ctx.handle, ref.handle, T, pr, w.feat_mask, mask, cands, cap,
-                                   count, stream)
+    MOM_TOL = (5, 30, 40, 100)
 
-        MOM_TOL = (5, 30, 40, 100)
-
-        def step_moments():
-            tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
-            ref.build(stream)
-            L.oss_screen_moments(ctx.handle, ref.handle, tm, w.probes, MOM_TOL, 7, mask, cands,
-                                 cap, count, stream)
-
+    def screen_step(ch, r, st, m, cd, cn, batched):
+        """One step of the chosen variant on context ch, reference r, stream
+        st, into mask m, list cd and count cn."""
         if args.alg1:
-            return step_alg1
-        if args.moments:
-            return step_moments
-
-        def step():
-            tm = tfeat()
-            ref.build(stream)
-            L.oss_screen(ctx.handle, ref.handle, tm, w.probes, tol, w.feat_mask, mask, cands, cap,
-                         count, stream, batched=batched)
-
-        def step_rings():
+            pr = alg1_probes()
+            r.build(st)
+            L.oss_screen_intervals(ch, r.handle, T, pr, w.feat_mask, m, cd, cap, cn, st)
+        elif args.moments:
+            tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
+            r.build(st)
+            L.oss_screen_moments(ch, r.handle, tm, w.probes, MOM_TOL, 7, m, cd, cap, cn, st)
+        elif args.rings > 1:
             tm = tfeat_rings()
-            ref.build(stream)
-            L.oss_screen_rings(ctx.handle, ref.handle, tm, w.probes, tol, w.feat_mask, mask,
-                               cands, cap, count, stream)
-        return step_rings if args.rings > 1 else step
+            r.build(st)
+            L.oss_screen_rings(ch, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn, st)
+        else:
+            tm = tfeat()
+            r.build(st)
+            L.oss_screen(ch, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn, st,
+                         batched=batched)
+
+    def make_step(batched):
+        return lambda: screen_step(ctx.handle, ref, stream, mask, cands, count, batched)
 
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
@@ -718,16 +702,14 @@ def main():
     value = ps / sec / 1e9
     n = int(count.item())
     lanes = args.pipeline if args.pipeline >= 1 else (2 if args.workload == 2 else 1)
-    if args.alg1 or args.moments:
-        lanes = 1
     if lanes >= 2:
         # the timed figures below are the lanes' run; the single lane's are kept
         extra["single_lane"] = {
             "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
                         for k, v in prof.items()}}
-        sec, prof, same = pipelined(args, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, tol,
-                                    cap, big, tfeat, tfeat_rings, n, mask, cands)
+        sec, prof, same = pipelined(args, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap,
+                                    big or args.rings > 1, screen_step, n, mask, cands)
         extra["lanes_identical_to_single_lane"] = same
         value = ps / sec / 1e9
     eb = sum(b // 8 for _, b in ref.slots)  # table bytes per position, all quantities
