@@ -499,13 +499,15 @@ def oss_alg1_probes(pixels, t: int, alpha, beta, q, feat_mask: int,
     prm = oss_alg1_params(a.numerator, a.denominator, b.numerator, b.denominator,
                           (C.c_int32 * 3)(*[int(v) for v in q]), int(feat_mask))
     n = C.c_int32()
-    rc = load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), None, 0,
+    cap = 256  # one call unless a template has more distinct band probes
+    out = (oss_interval_probe * cap)()
+    rc = load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), out, cap,
                                 C.byref(n))
-    if rc not in (OSS_OK, OSS_E_NOMEM):
-        _check(rc, "oss_alg1_probes")
-    out = (oss_interval_probe * max(1, n.value))()
-    _check(load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), out,
-                                  n.value, C.byref(n)), "oss_alg1_probes")
+    if rc == OSS_E_NOMEM:
+        out = (oss_interval_probe * n.value)()
+        rc = load().oss_alg1_probes(a_img.ctypes.data, C.byref(d), int(t), C.byref(prm), out,
+                                    n.value, C.byref(n))
+    _check(rc, "oss_alg1_probes")
     return list(out[:n.value])
 
 

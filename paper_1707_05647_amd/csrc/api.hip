@@ -1347,8 +1347,11 @@ int64_t ceil_sqrt2(int64_t a, int64_t d, int e)
 }
 
 // Bilinear n x n -> k x k, pixel centres aligned, edges replicated, rounded
-// half up; weights in units of 1/(2k), exact integers.
-void resize_square(const std::vector<int64_t> &src, int n, int k, std::vector<uint16_t> &dst)
+// half up; weights in units of 1/(2k), exact integers.  Only the window of
+// rows and columns [w0, w0 + ws) of the k x k result is formed, as a ws x ws
+// image.
+void resize_square(const std::vector<int64_t> &src, int n, int k, int w0, int ws,
+                   std::vector<uint16_t> &dst)
 {
     std::vector<int> i0(k), i1(k);
     std::vector<int64_t> w(k);
@@ -1368,16 +1371,16 @@ void resize_square(const std::vector<int64_t> &src, int n, int k, std::vector<ui
         i1[i] = (int)std::min<int64_t>(x0 + 1, n - 1);
         w[i] = wx;
     }
-    dst.assign((size_t)k * k, 0);
+    dst.assign((size_t)ws * ws, 0);
     const int64_t den = D * D;
-    for (int y = 0; y < k; ++y) {
-        for (int x = 0; x < k; ++x) {
+    for (int y = w0; y < w0 + ws; ++y) {
+        for (int x = w0; x < w0 + ws; ++x) {
             const int64_t t0 = (D - w[x]) * src[(size_t)i0[y] * n + i0[x]] +
                                w[x] * src[(size_t)i0[y] * n + i1[x]];
             const int64_t t1 = (D - w[x]) * src[(size_t)i1[y] * n + i0[x]] +
                                w[x] * src[(size_t)i1[y] * n + i1[x]];
             const int64_t v = (D - w[y]) * t0 + w[y] * t1;
-            dst[(size_t)y * k + x] = (uint16_t)((2 * v + den) / (2 * den));
+            dst[(size_t)(y - w0) * ws + (x - w0)] = (uint16_t)((2 * v + den) / (2 * den));
         }
     }
 }
@@ -1434,11 +1437,16 @@ extern "C" int oss_alg1_probes(const void *host_pixels, const oss_image_desc *de
         const int64_t A = star_area(r);
         const size_t band_first = res.size();
         for (int64_t k = k_lo; k <= k_hi; ++k) {
-            resize_square(px, n, (int)k, Y);
-            oss_image_desc yd{(int32_t)k, (int32_t)k, 2 * k, OSS_U16, 16};
+            // the star at the crop centre c reads [c - r, c + r] and, for the
+            // gradient, one more pixel each way (clamped to the k x k image):
+            // a window that holds those is exact, its clamping the image's
             const int c = (int)((k - m) / 2 + (m - 1) / 2);
+            const int w0 = std::max(0, c - r - 1);
+            const int ws = std::min((int)k - 1, c + r + 1) - w0 + 1;
+            resize_square(px, n, (int)k, w0, ws, Y);
+            oss_image_desc yd{ws, ws, 2 * (int64_t)ws, OSS_U16, 16};
             int64_t F[3];
-            star_feats_at(Y.data(), &yd, c, c, r, p->feat_mask, F);
+            star_feats_at(Y.data(), &yd, c - w0, c - w0, r, p->feat_mask, F);
             oss_interval_probe pr{};
             pr.template_id = t;
             pr.scale_id = b;
