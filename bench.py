@@ -539,7 +539,7 @@ def main():
     ap.add_argument("--pipeline", type=int, default=-1,
                     help="time the steps round-robin over this many lanes (a context, stream, "
                          "tables and outputs each: consecutive batches overlap); 1 = one lane; "
-                         "-1 = 2 for workload 2 (every variant), else 1")
+                         "-1 = 2")
     ap.add_argument("--staged", type=int, default=-1,
                     help="1/0: staged lookups (first quantity alone, the rest where it passes) / "
                          "every quantity at every lookup; -1 = library default")
@@ -701,7 +701,11 @@ def main():
         ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
     n = int(count.item())
-    lanes = args.pipeline if args.pipeline >= 1 else (2 if args.workload == 2 else 1)
+    lanes = args.pipeline if args.pipeline >= 1 else 2
+    if big:
+        # batched against per-template launches, one lane each
+        extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
+        extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
     if lanes >= 2:
         # the timed figures below are the lanes' run; the single lane's are kept
         extra["single_lane"] = {
@@ -749,9 +753,6 @@ def main():
     for k in kern:
         if k in abytes:
             kern[k]["achieved_GBps"] = abytes[k] / (kern[k]["avg_ms"] / 1e3) / 1e9
-    if big:
-        extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
-        extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
     out = {
         "metric": METRIC,
         "value": value,
