@@ -50,6 +50,7 @@ __global__ __launch_bounds__(CTHREADS) void compact_count_kernel(const uint32_t 
 }
 
 constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_PER = 8;  // consecutive segment counts per thread and round
 
 __global__ __launch_bounds__(SCAN_THREADS) void compact_scan_kernel(
     const int64_t *__restrict__ seg_count, int64_t nseg, int64_t *__restrict__ seg_off,
@@ -58,10 +59,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void compact_scan_kernel(
     __shared__ int64_t s_w[SCAN_THREADS / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int64_t carry = 0;
-    for (int64_t base = 0; base < nseg; base += SCAN_THREADS) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < nseg ? seg_count[i] : 0;
-        int64_t s = v;
+    for (int64_t base = 0; base < nseg; base += (int64_t)SCAN_THREADS * SCAN_PER) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_PER;
+        int64_t v[SCAN_PER], tsum = 0;
+#pragma unroll
+        for (int u = 0; u < SCAN_PER; ++u) {
+            v[u] = i0 + u < nseg ? seg_count[i0 + u] : 0;
+            tsum += v[u];
+        }
+        int64_t s = tsum;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int64_t t = __shfl_up(s, d, 64);
@@ -76,8 +82,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void compact_scan_kernel(
             off += (w < wid) ? s_w[w] : 0;
             chunk += s_w[w];
         }
-        if (i < nseg)
-            seg_off[i] = carry + off + s - v;
+        off += carry + s - tsum;  // exclusive prefix of this thread's first count
+#pragma unroll
+        for (int u = 0; u < SCAN_PER; ++u) {
+            if (i0 + u < nseg)
+                seg_off[i0 + u] = off;
+            off += v[u];
+        }
         carry += chunk;
         __syncthreads();
     }
