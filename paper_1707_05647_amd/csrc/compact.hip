@@ -4,7 +4,9 @@
 // Deterministic two-pass stream compaction over segments of CSEG words:
 //   count  one block per segment; each wave ballots 64 words at a time and
 //          popcounts the ballot
-//   scan   one block, exclusive scan of the segment counts (and the total)
+//   scan   exclusive scan of the segment counts (and the total): one block,
+//          or for many segments blocks over chunks, their totals, and the
+//          chunk offsets added back
 //   write  one block per segment; the wave offsets come from a block scan of
 //          per-wave counts, a lane's slot from the popcount of the ballot
 //          bits below it (mbcnt); the mask is written for every word
@@ -51,20 +53,26 @@ __global__ __launch_bounds__(CTHREADS) void compact_count_kernel(const uint32_t 
 
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_PER = 8;  // consecutive segment counts per thread and round
+constexpr int64_t SCAN_CHUNK = (int64_t)SCAN_THREADS * SCAN_PER;
 
+// Exclusive scan of counts[0, n) into offs, in rounds of SCAN_CHUNK; the sum
+// goes to *total.  One block; blockIdx.x selects the chunk [b * span,
+// (b + 1) * span) of a longer array when several blocks scan chunks apart.
 __global__ __launch_bounds__(SCAN_THREADS) void compact_scan_kernel(
-    const int64_t *__restrict__ seg_count, int64_t nseg, int64_t *__restrict__ seg_off,
-    int64_t *__restrict__ total)
+    const int64_t *__restrict__ counts, int64_t n, int64_t span, int64_t *__restrict__ offs,
+    int64_t *__restrict__ totals)
 {
     __shared__ int64_t s_w[SCAN_THREADS / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t first = (int64_t)blockIdx.x * span;
+    const int64_t last = min(n, first + span);
     int64_t carry = 0;
-    for (int64_t base = 0; base < nseg; base += (int64_t)SCAN_THREADS * SCAN_PER) {
+    for (int64_t base = first; base < last; base += SCAN_CHUNK) {
         const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_PER;
         int64_t v[SCAN_PER], tsum = 0;
 #pragma unroll
         for (int u = 0; u < SCAN_PER; ++u) {
-            v[u] = i0 + u < nseg ? seg_count[i0 + u] : 0;
+            v[u] = i0 + u < last ? counts[i0 + u] : 0;
             tsum += v[u];
         }
         int64_t s = tsum;
@@ -85,15 +93,25 @@ __global__ __launch_bounds__(SCAN_THREADS) void compact_scan_kernel(
         off += carry + s - tsum;  // exclusive prefix of this thread's first count
 #pragma unroll
         for (int u = 0; u < SCAN_PER; ++u) {
-            if (i0 + u < nseg)
-                seg_off[i0 + u] = off;
+            if (i0 + u < last)
+                offs[i0 + u] = off;
             off += v[u];
         }
         carry += chunk;
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        *total = carry;
+        totals[blockIdx.x] = carry;
+}
+
+// offs[i] += add[i / span]: the chunk offsets of a multi-block scan.
+__global__ __launch_bounds__(256) void compact_add_kernel(int64_t *__restrict__ offs, int64_t n,
+                                                          int64_t span,
+                                                          const int64_t *__restrict__ add)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        offs[i] += add[i / span];
 }
 
 __global__ __launch_bounds__(CTHREADS) void compact_write_kernel(
@@ -143,10 +161,15 @@ __global__ __launch_bounds__(CTHREADS) void compact_write_kernel(
     }
 }
 
+// Segments scanned by one block; more segments are scanned by blocks of
+// SCAN_SPAN each, then their totals, then the offsets are added.
+constexpr int64_t SCAN_SPAN = 4 * SCAN_CHUNK;
+
 size_t compact_workspace_bytes(int64_t n)
 {
     const int64_t nseg = (n + CSEG - 1) / CSEG;
-    return (size_t)(2 * nseg) * sizeof(int64_t);
+    const int64_t nblk = (nseg + SCAN_SPAN - 1) / SCAN_SPAN;
+    return (size_t)(2 * nseg + 2 * nblk) * sizeof(int64_t);
 }
 
 hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
@@ -156,8 +179,10 @@ hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, ui
     const int64_t hw = (int64_t)H * W;
     const int64_t n = n_tmpl * hw;
     const int64_t nseg = (n + CSEG - 1) / CSEG;
+    const int64_t nblk = (nseg + SCAN_SPAN - 1) / SCAN_SPAN;
     int64_t *seg_count = static_cast<int64_t *>(workspace);
     int64_t *seg_off = seg_count + nseg;
+    int64_t *blk_sum = seg_off + nseg, *blk_off = blk_sum + nblk;
     {
         ProfScope ps(prof, K_COMPACT_COUNT, stream);
         hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)nseg), dim3(CTHREADS), 0, stream,
@@ -165,8 +190,20 @@ hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, ui
     }
     {
         ProfScope ps(prof, K_COMPACT_SCAN, stream);
-        hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(SCAN_THREADS), 0, stream, seg_count,
-                           nseg, seg_off, count);
+        if (nblk <= 1) {
+            hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(SCAN_THREADS), 0, stream,
+                               seg_count, nseg, nseg, seg_off, count);
+        } else {
+            // chunks of SCAN_SPAN segments scanned in parallel, their totals
+            // scanned by one block (the grand total into *count), the chunk
+            // offsets added back
+            hipLaunchKernelGGL(compact_scan_kernel, dim3((unsigned)nblk), dim3(SCAN_THREADS), 0,
+                               stream, seg_count, nseg, SCAN_SPAN, seg_off, blk_sum);
+            hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(SCAN_THREADS), 0, stream,
+                               blk_sum, nblk, nblk, blk_off, count);
+            hipLaunchKernelGGL(compact_add_kernel, dim3((unsigned)((nseg + 255) / 256)), dim3(256),
+                               0, stream, seg_off, nseg, SCAN_SPAN, blk_off);
+        }
     }
     {
         ProfScope ps(prof, K_COMPACT_WRITE, stream);
