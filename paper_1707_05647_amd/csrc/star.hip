@@ -59,6 +59,17 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     // byte offset of column x0 + tid + 1 relative to column x0
     const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
     const int64_t row_bytes = pitch_e * ES;
+    // the plan (radii, probe bounds) in LDS once per block: per radius it is
+    // read there instead of through the scalar cache
+    __shared__ DevTemplatePlan s_plan;
+    {
+        const int32_t *src = reinterpret_cast<const int32_t *>(plan);
+        int32_t *dst = reinterpret_cast<int32_t *>(&s_plan);
+        for (int i = threadIdx.x; i < (int)(sizeof(DevTemplatePlan) / 4); i += blockDim.x)
+            dst[i] = src[i];
+        __syncthreads();
+        plan = &s_plan;
+    }
     const int nr = plan->n_radii;
     for (int it = j; it < items; it += sw.blocks_per_xcd) {
         int y, x0;
