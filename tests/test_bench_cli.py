@@ -1,0 +1,34 @@
+"""Host-side contract of bench.py (no GPU): a multi-GPU request is refused
+with a message, and the algorithmic byte counts of the roofline follow
+their definitions."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes():
+    H, W, T = 64, 80, 3
+    a = bench.algorithmic_bytes(H, W, T, 1, 12)
+    # the star pass reads the tables once (three tables of (H+1)(W+1)
+    # entries) and writes the scale-bit words once; the builder reads the
+    # image once and writes the tables
+    assert a["star_plain"] == 3 * (H + 1) * (W + 1) * 12 + 4 * T * H * W
+    assert a["band_final"] == 3 * (H + 1) * (W + 1) * 12 + H * W
+    assert a["compact_count"] == 4 * T * H * W
+
+
+def test_pixel_scales_count_valid_positions():
+    # a radius-r star fits at (H - 2r)(W - 2r) positions; none when 2r >= H
+    assert bench.pixel_scales(10, 12, [(0, 0, 2), (0, 1, 5)]) == 6 * 8 + 0
