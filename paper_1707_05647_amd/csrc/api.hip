@@ -2,11 +2,13 @@
 #include "api_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 
 using namespace oss;
 
@@ -1426,48 +1428,84 @@ extern "C" int oss_alg1_probes(const void *host_pixels, const oss_image_desc *de
             }
         }
     const int64_t a = (int64_t)p->beta_num * n, d = p->beta_den;  // beta n = a / d
-    std::vector<oss_interval_probe> res;
-    std::vector<uint16_t> Y;
+    // every (band, size) item: the template resized to k x k, the features of
+    // the central star of its band's radius, the probe of its quantised cell
+    struct Item {
+        int b, m, r;
+        int64_t k, A;
+    };
+    std::vector<Item> items;
     for (int b = 0; b < B; ++b) {
         const int64_t k_lo = ceil_sqrt2(a, d, b + 1), k_hi = floor_sqrt2(a, d, b);
         const int m = (int)k_lo;
         if (m < 1)
             continue;
         const int r = (m - 1) / 2;
-        const int64_t A = star_area(r);
-        const size_t band_first = res.size();
-        for (int64_t k = k_lo; k <= k_hi; ++k) {
-            // the star at the crop centre c reads [c - r, c + r] and, for the
-            // gradient, one more pixel each way (clamped to the k x k image):
-            // a window that holds those is exact, its clamping the image's
-            const int c = (int)((k - m) / 2 + (m - 1) / 2);
-            const int w0 = std::max(0, c - r - 1);
-            const int ws = std::min((int)k - 1, c + r + 1) - w0 + 1;
-            resize_square(px, n, (int)k, w0, ws, Y);
-            oss_image_desc yd{ws, ws, 2 * (int64_t)ws, OSS_U16, 16};
-            int64_t F[3];
-            star_feats_at(Y.data(), &yd, c - w0, c - w0, r, p->feat_mask, F);
-            oss_interval_probe pr{};
-            pr.template_id = t;
-            pr.scale_id = b;
-            pr.r = r;
-            for (int f = 0; f < 3; ++f) {
-                pr.lo[f] = INT64_MIN;
-                pr.hi[f] = INT64_MAX;
-                if (!(p->feat_mask & (1u << f)))
-                    continue;
-                const int64_t q = (int64_t)p->q[f] * A;
-                const int64_t c0 = F[f] / q;  // F >= 0: floor(F / q)
-                pr.lo[f] = q * c0 - q / 2;
-                pr.hi[f] = q * (c0 + 2) - q / 2 - 1;
-            }
-            bool dup = false;
-            for (size_t i = band_first; i < res.size() && !dup; ++i)
-                dup = std::memcmp(res[i].lo, pr.lo, sizeof(pr.lo)) == 0 &&
-                      std::memcmp(res[i].hi, pr.hi, sizeof(pr.hi)) == 0;
-            if (!dup)
-                res.push_back(pr);
+        for (int64_t k = k_lo; k <= k_hi; ++k)
+            items.push_back({b, m, r, k, star_area(r)});
+    }
+    std::vector<oss_interval_probe> per(items.size());
+    auto work = [&](size_t i) {
+        const Item &it = items[i];
+        const int64_t k = it.k;
+        const int m = it.m, r = it.r;
+        // the star at the crop centre c reads [c - r, c + r] and, for the
+        // gradient, one more pixel each way (clamped to the k x k image):
+        // a window that holds those is exact, its clamping the image's
+        const int c = (int)((k - m) / 2 + (m - 1) / 2);
+        const int w0 = std::max(0, c - r - 1);
+        const int ws = std::min((int)k - 1, c + r + 1) - w0 + 1;
+        std::vector<uint16_t> Y;
+        resize_square(px, n, (int)k, w0, ws, Y);
+        oss_image_desc yd{ws, ws, 2 * (int64_t)ws, OSS_U16, 16};
+        int64_t F[3];
+        star_feats_at(Y.data(), &yd, c - w0, c - w0, r, p->feat_mask, F);
+        oss_interval_probe pr{};
+        pr.template_id = t;
+        pr.scale_id = it.b;
+        pr.r = r;
+        for (int f = 0; f < 3; ++f) {
+            pr.lo[f] = INT64_MIN;
+            pr.hi[f] = INT64_MAX;
+            if (!(p->feat_mask & (1u << f)))
+                continue;
+            const int64_t q = (int64_t)p->q[f] * it.A;
+            const int64_t c0 = F[f] / q;  // F >= 0: floor(F / q)
+            pr.lo[f] = q * c0 - q / 2;
+            pr.hi[f] = q * (c0 + 2) - q / 2 - 1;
         }
+        per[i] = pr;
+    };
+    // the items on a few host threads (each writes only its own slot)
+    const size_t nthr = std::min<size_t>({items.size(), 8,
+                                          std::max(1u, std::thread::hardware_concurrency())});
+    if (nthr <= 1) {
+        for (size_t i = 0; i < items.size(); ++i)
+            work(i);
+    } else {
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> pool;
+        for (size_t w = 0; w < nthr; ++w)
+            pool.emplace_back([&]() {
+                for (size_t i = next++; i < items.size(); i = next++)
+                    work(i);
+            });
+        for (auto &th : pool)
+            th.join();
+    }
+    // in (band, size) order, one probe per distinct interval set of a band
+    std::vector<oss_interval_probe> res;
+    size_t band_first = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (i == 0 || items[i].b != items[i - 1].b)
+            band_first = res.size();
+        const oss_interval_probe &pr = per[i];
+        bool dup = false;
+        for (size_t j = band_first; j < res.size() && !dup; ++j)
+            dup = std::memcmp(res[j].lo, pr.lo, sizeof(pr.lo)) == 0 &&
+                  std::memcmp(res[j].hi, pr.hi, sizeof(pr.hi)) == 0;
+        if (!dup)
+            res.push_back(pr);
     }
     *n_out = (int32_t)res.size();
     if ((int64_t)res.size() > cap)
