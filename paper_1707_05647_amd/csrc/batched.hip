@@ -3,7 +3,8 @@
 // and scales at once).  With central-star rings (Sec. "Scale Invariance",
 // central areas of sizes n, n/lambda, n/lambda^2) each probe also has
 // entries at its central radii; a probe's bit survives where its own star
-// passes and none of its central stars fails.
+// passes and none of its central stars fails.  A wave skips a radius whose
+// probes have all failed a central star at each of its positions.
 //
 // Templates are sorted by radius and cut into groups of at most
 // BATCH_GROUP; within a group the probes are grouped by reference radius, so
@@ -85,6 +86,20 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 if (y < r || y > H - 1 - r)
                     continue;
                 const bool xv = x >= r && x <= W - 1 - r;
+                if constexpr (RINGS) {
+                    // skip the radius where every probe it serves has failed a
+                    // central star already (its bit is then 0 whatever this
+                    // radius gives); radii ascend, so a probe's central stars,
+                    // smaller than its own, come first
+                    bool need = false;
+                    if (xv)
+                        for (int p = rd.first; p < rd.first + rd.count; ++p) {
+                            const DevBatchProbe &pr = probes[p];
+                            need = need | !((fail[pr.t] >> pr.k) & 1u);
+                        }
+                    if (__builtin_amdgcn_ballot_w64(need) == 0)
+                        continue;
+                }
                 // a valid position outside the radius' hull fails every entry
                 // of the radius: central-star entries record that failure
                 auto fail_all = [&]() {
