@@ -200,7 +200,7 @@ def run_pipelined(lanes, make_lane, steps, warmup, L, torch):
 
 OPTIONS = ("OSS_OPT_STAR_STRIP", "OSS_OPT_STAR_BLOCKS_PER_XCD", "OSS_OPT_STAR_LDS",
            "OSS_OPT_BATCH_BUCKET", "OSS_OPT_TABLE_PLANAR", "OSS_OPT_STAR_PIPE",
-           "OSS_OPT_STAR_STAGED")
+           "OSS_OPT_STAR_STAGED", "OSS_OPT_BUILD_STREAM")
 
 
 def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, batched,
@@ -543,6 +543,10 @@ def main():
     ap.add_argument("--staged", type=int, default=-1,
                     help="1/0: staged lookups (first quantity alone, the rest where it passes) / "
                          "every quantity at every lookup; -1 = library default")
+    ap.add_argument("--build-stream", type=int, default=-1,
+                    help="1/0: table entries stored with / without non-temporal (streaming) "
+                         "stores; -1 = library default for the lanes, ordinary stores for the "
+                         "one-lane runs")
     ap.add_argument("--planar", type=int, default=-1,
                     help="1/0: planar / interleaved tables; -1 = library default "
                          "(interleaved for workload 3, whose tolerances are loose)")
@@ -593,6 +597,14 @@ def main():
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
     if args.staged >= 0:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STAGED, args.staged)
+    if args.build_stream >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, args.build_stream)
+    lanes = args.pipeline if args.pipeline >= 1 else 2
+    lane_stream = L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM)
+    if args.build_stream < 0:
+        # streaming table stores pay off only beside another lane's star
+        # pass: the one-lane runs use ordinary stores
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, 0)
     max_r = max(w.radii())
     if args.alg1:
         from fractions import Fraction
@@ -701,7 +713,6 @@ def main():
         ps = pixel_scales(w.H, w.W, w.probes)
     value = ps / sec / 1e9
     n = int(count.item())
-    lanes = args.pipeline if args.pipeline >= 1 else 2
     if big:
         # batched against per-template launches, one lane each
         extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
@@ -710,8 +721,10 @@ def main():
         # the timed figures below are the lanes' run; the single lane's are kept
         extra["single_lane"] = {
             "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
+            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
                         for k, v in prof.items()}}
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, lane_stream)
         sec, prof, same = pipelined(args, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap,
                                     big or args.rings > 1, screen_step, n, mask, cands)
         extra["lanes_identical_to_single_lane"] = same
@@ -781,6 +794,7 @@ def main():
             "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
             "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
             "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
+            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if (big or args.rings > 1) else "plain",
             "lanes": lanes,

@@ -161,6 +161,12 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                it (default); 0: every quantity at every
  *                                lookup.  The pipelining option takes
  *                                precedence
+ *   OSS_OPT_BUILD_STREAM         1: oss_ref_build stores the table entries
+ *                                with non-temporal (streaming) stores, so
+ *                                that a star pass running beside the build
+ *                                on another stream keeps more of its lines
+ *                                in L2 (default); 0: ordinary stores, faster
+ *                                for a build that runs alone
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
@@ -169,6 +175,7 @@ int oss_ctx_destroy(oss_ctx *ctx);
 #define OSS_OPT_TABLE_PLANAR 5
 #define OSS_OPT_STAR_PIPE 6
 #define OSS_OPT_STAR_STAGED 7
+#define OSS_OPT_BUILD_STREAM 8
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 

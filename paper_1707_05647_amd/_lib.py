@@ -35,6 +35,7 @@ OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH
 OSS_OPT_TABLE_PLANAR = 5
 OSS_OPT_STAR_PIPE = 6
 OSS_OPT_STAR_STAGED = 7
+OSS_OPT_BUILD_STREAM = 8
 OSS_MAX_RINGS = 4
 OSS_TUNE_MAX = 64
 

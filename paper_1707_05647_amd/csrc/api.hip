@@ -304,7 +304,9 @@ int oss_ref_build(oss_ref *ref, const void *dev_pixels, void *stream)
         return OSS_E_ARG;
     if (hipSetDevice(ref->ctx->device) != hipSuccess)
         return OSS_E_DEVICE;
-    return hip_status(launch_build(ref->geom, dev_pixels, ref->desc.pitch_bytes, ref->desc.dtype,
+    oss::BuildGeom g = ref->geom;
+    g.nt = ref->ctx->build_stream;
+    return hip_status(launch_build(g, dev_pixels, ref->desc.pitch_bytes, ref->desc.dtype,
                                    ref->feat_mask, ref->bb, static_cast<hipStream_t>(stream),
                                    &ref->ctx->prof));
 }
@@ -497,6 +499,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->star_staged = value;
         return OSS_OK;
+    case OSS_OPT_BUILD_STREAM:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->build_stream = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -514,6 +521,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_TABLE_PLANAR: *value = ctx->table_planar; return OSS_OK;
     case OSS_OPT_STAR_PIPE: *value = ctx->star_pipe; return OSS_OK;
     case OSS_OPT_STAR_STAGED: *value = ctx->star_staged; return OSS_OK;
+    case OSS_OPT_BUILD_STREAM: *value = ctx->build_stream; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }

@@ -38,6 +38,7 @@ struct oss_ctx {
     int table_planar = 1;          // OSS_OPT_TABLE_PLANAR
     int star_pipe = 0;             // OSS_OPT_STAR_PIPE
     int star_staged = 1;           // OSS_OPT_STAR_STAGED
+    int build_stream = 1;          // OSS_OPT_BUILD_STREAM
     void *rws = nullptr;           // preserved-region workspace (tables of the padded
     size_t rws_cap = 0;            // indicator image, the image, the star pass output)
 };

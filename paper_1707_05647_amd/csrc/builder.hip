@@ -60,6 +60,7 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
     g.agg_x0 = -128;
     g.nagg = cdiv((g.cx0 + g.cw - 1) - (g.agg_x0 + BAND_HALO) + 1, BAND_STRIDE);
     g.nbp = cdiv(W, 64) + 1;
+    g.nt = 0;
     return g;
 }
 
@@ -595,7 +596,21 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__rest
 // the byte distance between planes.
 enum { LAY_INTER = 0, LAY_PLANAR = 1, LAY_MIX = 2, LAY_PLANAR_MIX = 3 };
 
-template <typename T, int NQ, int LAY, int SQI>
+// One table value; NT: a non-temporal (streaming) store.  A compile-time
+// choice: a run-time branch between the two stores is merged by the
+// compiler into one ordinary store.
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V *p, V v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NQ, int LAY, int SQI, bool NT>
 __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, const T *v,
                                             int64_t plane_b)
 {
@@ -603,21 +618,21 @@ __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, cons
         const int64_t pe = plane_b / (int64_t)sizeof(T);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            tab[q * pe + e] = v[q];
+            put<NT>(tab + q * pe + e, v[q]);
     } else if constexpr (LAY == LAY_PLANAR_MIX) {
         uint32_t *t32 = reinterpret_cast<uint32_t *>(tab);
         const int64_t pe = plane_b / 4;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int pl = q <= SQI ? q : q + 1;  // plane of quantity q
-            t32[pl * pe + e] = (uint32_t)v[q];
+            put<NT>(t32 + pl * pe + e, (uint32_t)v[q]);
             if (q == SQI)
-                t32[(pl + 1) * pe + e] = (uint32_t)((uint64_t)v[q] >> 32);
+                put<NT>(t32 + (pl + 1) * pe + e, (uint32_t)((uint64_t)v[q] >> 32));
         }
     } else if constexpr (LAY == LAY_INTER) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            tab[e * NQ + q] = v[q];
+            put<NT>(tab + e * NQ + q, v[q]);
     } else {
         uint32_t o[2] = {0u, 0u};
         int j = 0;
@@ -626,12 +641,12 @@ __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, cons
             if (q != SQI)
                 o[j++] = (uint32_t)v[q];
         const uint64_t sq = (uint64_t)v[SQI];
-        *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(tab) + e * 16) =
-            make_uint4((uint32_t)sq, (uint32_t)(sq >> 32), o[0], o[1]);
+        const u32x4 w = {(uint32_t)sq, (uint32_t)(sq >> 32), o[0], o[1]};
+        put<NT>(reinterpret_cast<u32x4 *>(reinterpret_cast<char *>(tab) + e * 16), w);
     }
 }
 
-template <typename Pix, unsigned FM, typename T, int LAY, int SQI>
+template <typename Pix, unsigned FM, typename T, int LAY, int SQI, bool NT>
 __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     const Pix *__restrict__ img, int64_t pitch, BuildGeom g, const T *__restrict__ bp,
     const T *__restrict__ cL, const T *__restrict__ cAD, const T *__restrict__ cD,
@@ -730,9 +745,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
                 r[q] = TA[q] - td_l[q];
                 rp[q] = ta_r[q] - td_l[q];
             }
-            store_entry<T, NQ, LAY, SQI>(tL, e, Lc, plane_b);
-            store_entry<T, NQ, LAY, SQI>(tR, e, r, plane_b);
-            store_entry<T, NQ, LAY, SQI>(tRp, e, rp, plane_b);
+            store_entry<T, NQ, LAY, SQI, NT>(tL, e, Lc, plane_b);
+            store_entry<T, NQ, LAY, SQI, NT>(tR, e, r, plane_b);
+            store_entry<T, NQ, LAY, SQI, NT>(tRp, e, rp, plane_b);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -767,9 +782,9 @@ __global__ __launch_bounds__(BAND_THREADS) void band_final_kernel(
     }
     if (store) {
         const int64_t e = (int64_t)(ys + rows) * g.pitch_e + (x + 1);
-        store_entry<T, NQ, LAY, SQI>(tL, e, Lc, plane_b);
-        store_entry<T, NQ, LAY, SQI>(tR, e, r, plane_b);
-        store_entry<T, NQ, LAY, SQI>(tRp, e, rp, plane_b);
+        store_entry<T, NQ, LAY, SQI, NT>(tL, e, Lc, plane_b);
+        store_entry<T, NQ, LAY, SQI, NT>(tR, e, r, plane_b);
+        store_entry<T, NQ, LAY, SQI, NT>(tRp, e, rp, plane_b);
     }
 }
 
@@ -803,10 +818,16 @@ static hipError_t build_t(const BuildGeom &g, const void *pixels, int64_t pitch_
     }
     {
         ProfScope ps(prof, K_BAND_FINAL, st);
-        hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, LAY, SQI>), dim3(g.nfin, g.nb),
-                           dim3(BAND_THREADS), 0, st, img, pitch, g, bp, cL, cAD, cD,
-                           static_cast<T *>(bb.L), static_cast<T *>(bb.R),
-                           static_cast<T *>(bb.Rp));
+        if (g.nt)
+            hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, LAY, SQI, true>),
+                               dim3(g.nfin, g.nb), dim3(BAND_THREADS), 0, st, img, pitch, g, bp,
+                               cL, cAD, cD, static_cast<T *>(bb.L), static_cast<T *>(bb.R),
+                               static_cast<T *>(bb.Rp));
+        else
+            hipLaunchKernelGGL((band_final_kernel<Pix, FM, T, LAY, SQI, false>),
+                               dim3(g.nfin, g.nb), dim3(BAND_THREADS), 0, st, img, pitch, g, bp,
+                               cL, cAD, cD, static_cast<T *>(bb.L), static_cast<T *>(bb.R),
+                               static_cast<T *>(bb.Rp));
     }
     return hipGetLastError();
 }

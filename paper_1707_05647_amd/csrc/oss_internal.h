@@ -54,6 +54,7 @@ struct BuildGeom {
     int nagg, agg_x0;  // projection tiles
     int cx0, cw;       // carry range [cx0, cx0 + cw): the union of the final tiles' columns
     int nbp;           // row-prefix bases per row: P_y(64 j - 1), j in [0, nbp)
+    int nt;            // 1: table entries stored non-temporally (streaming)
 };
 
 // Table entries hold the nq quantities in feature order, each in ebytes

@@ -39,15 +39,19 @@ TABLE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("stream", [1, 0], ids=["streamed", "ordinary"])
 @pytest.mark.parametrize("planar", [0, 1], ids=["interleaved", "planar"])
 @pytest.mark.parametrize("case", TABLE_CASES, ids=lambda c: "x".join(map(str, c)))
-def test_tables_match_definitions(runner, case, planar):
+def test_tables_match_definitions(runner, case, planar, stream):
+    """Every table entry equals its definition, for every storage width and
+    layout, with the entries written by streaming (non-temporal, the
+    default) and by ordinary stores."""
     H, W, depth, fm, pad, max_r = case
     rng = np.random.default_rng(H * 1000 + W)
     dt = np.uint8 if depth == 8 else np.uint16
     img = rng.integers(0, 2 ** depth, (H, W)).astype(dt)
     torch = runner.torch
-    say(f"tables {case}")
+    say(f"tables {case} planar={planar} stream={stream}")
     if pad:
         wide = np.zeros((H, W + pad), dt)
         wide[:, :W] = img
@@ -55,11 +59,15 @@ def test_tables_match_definitions(runner, case, planar):
     else:
         t_img = runner.L.device_image(img, runner.dev)
     L = runner.L
-    L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, planar)
+    h = runner.ctx.handle
+    assert L.oss_ctx_get_option(h, L.OSS_OPT_BUILD_STREAM) == 1
+    L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_PLANAR, planar)
+    L.oss_ctx_set_option(h, L.OSS_OPT_BUILD_STREAM, stream)
     try:
         ref = runner.ctx.reference(t_img, fm, depth, max_radius=max_r)
     finally:
-        L.oss_ctx_set_option(runner.ctx.handle, L.OSS_OPT_TABLE_PLANAR, 1)
+        L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_PLANAR, 1)
+        L.oss_ctx_set_option(h, L.OSS_OPT_BUILD_STREAM, 1)
     torch.cuda.synchronize()
     assert len(ref.slots) == bin(fm).count("1")
     if planar:
