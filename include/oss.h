@@ -247,7 +247,8 @@ int oss_ref_release(oss_ref *ref);
  * [-1, W-1], y in [-1, H-1] (oss_ref_layout gives entry_bytes and where each
  * quantity sits in an entry); nq = number of bits in the feature mask;
  * value_bits = the accumulation width (32: every sum modulo 2^32, or 64).
- * Any output pointer may be NULL.
+ * Rows span a whole number of 128-byte lines, and entry (0, y) of every row
+ * (of every plane) starts a line.  Any output pointer may be NULL.
  */
 int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const void **Rp,
                    int64_t *pitch_entries, int32_t *nq, int32_t *value_bits,

@@ -284,9 +284,10 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
     }
     char *m = static_cast<char *>(r->mem);
     auto at = [&](int i) { return static_cast<void *>(m + off[i]); };
-    r->bb.L = at(A_L);
-    r->bb.R = at(A_R);
-    r->bb.Rp = at(A_RP);
+    const int to = r->geom.tab_off;  // entry 0 of each table (plane)
+    r->bb.L = m + off[A_L] + to;
+    r->bb.R = m + off[A_R] + to;
+    r->bb.Rp = m + off[A_RP] + to;
     r->bb.bp = at(A_BP);
     r->bb.agg_L = at(A_AGL);
     r->bb.agg_AD = at(A_AGAD);
@@ -1235,9 +1236,9 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
         return rc;
     char *m = static_cast<char *>(ctx->rws);
     BuildBuffers bb{};
-    bb.L = m + off[A_L];
-    bb.R = m + off[A_R];
-    bb.Rp = m + off[A_RP];
+    bb.L = m + off[A_L] + g.tab_off;
+    bb.R = m + off[A_R] + g.tab_off;
+    bb.Rp = m + off[A_RP] + g.tab_off;
     bb.bp = m + off[A_BP];
     bb.agg_L = m + off[A_AGL];
     bb.agg_AD = m + off[A_AGAD];

@@ -40,16 +40,22 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
     g.ebytes = ebytes;
     g.sqi = sqi;
     g.planar = planar ? 1 : 0;
-    g.pitch_e = ((int64_t)W + 1 + 15) / 16 * 16;
+    // Rows of a whole number of 128-byte lines, and entry index 0 (x = -1)
+    // TAB_LINE - tab_es bytes into each table (plane) allocation: image
+    // column 0 of every row then starts a line, so the final pass's 64-column
+    // waves store whole lines and a star pass's centre-column lookups read
+    // two lines per wave instead of three.
+    g.pitch_e = ((int64_t)W + 1 + 31) / 32 * 32;
     if (g.planar) {
         g.tab_es = sqi >= 0 ? 4 : ebytes;
-        g.plane = ((int64_t)(H + 1) * g.pitch_e * g.tab_es + 255) / 256 * 256;
+        g.plane = ((int64_t)(H + 1) * g.pitch_e * g.tab_es + TAB_LINE + 255) / 256 * 256;
         g.tab_bytes = g.plane * (sqi >= 0 ? nq + 1 : nq);
     } else {
         g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
         g.plane = 0;
-        g.tab_bytes = (int64_t)(H + 1) * g.pitch_e * g.tab_es;
+        g.tab_bytes = (int64_t)(H + 1) * g.pitch_e * g.tab_es + TAB_LINE;
     }
+    g.tab_off = TAB_LINE - g.tab_es;
     g.nb = cdiv(H + 1, KBAND);
     // final tiles: cores cover [-1, W-1]; the first core starts at -64+HALO <= -1
     g.fin_x0 = -64;

@@ -48,6 +48,7 @@ struct BuildGeom {
     int tab_es;        // entry stride in bytes: nq * ebytes, 16 (mixed) or ebytes (planar)
     int64_t plane;     // planar: bytes from one plane to the next, else 0
     int64_t tab_bytes; // bytes of one table
+    int tab_off;       // bytes from a table's (plane's) allocation start to entry 0
     int64_t pitch_e;   // table entries per row (>= W+1)
     int nb;            // bands
     int nfin, fin_x0;  // final tiles: first thread column of tile c is fin_x0 + c*BAND_STRIDE
@@ -61,8 +62,11 @@ struct BuildGeom {
 // bytes; with sqi >= 0 (ebytes 8) an entry is 16 bytes instead: the squares
 // (quantity slot sqi) as 64 bits, then the other quantities in feature order
 // as 32 bits each (modulo 2^32), zero padded.  planar: each quantity in a
-// plane of its own, planes 256-byte aligned; with sqi >= 0 every plane holds
-// 32-bit values and the squares take two planes, low word then high word.
+// plane of its own, plane allocations 256-byte aligned; with sqi >= 0 every
+// plane holds 32-bit values and the squares take two planes, low word then
+// high word.  Rows are a multiple of TAB_LINE bytes, and entry 0 of a table
+// (plane) sits tab_off = TAB_LINE - tab_es bytes into its allocation.
+constexpr int TAB_LINE = 128;
 BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1, int planar = 0);
 
 // ---------------------------------------------------------------------------

@@ -15,12 +15,6 @@ struct Entry {
 __device__ __forceinline__ int64_t widen(uint32_t v) { return (int64_t)v; }
 __device__ __forceinline__ int64_t widen(uint64_t v) { return (int64_t)v; }
 
-// Entry at a wave-uniform row base plus this lane's byte offset.
-template <typename T, int NQ>
-__device__ __forceinline__ Entry<T, NQ> at(const char *row, uint32_t lane_off)
-{
-    return *reinterpret_cast<const Entry<T, NQ> *>(row + lane_off);
-}
 
 // Table entry layouts.  TabU: NQ quantities of T in feature order.  TabMix:
 // 16-byte entries with the squares (feature slot SQI) as 64 bits and the
