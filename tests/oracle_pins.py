@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import os
 
+import itertools
+
 import numpy as np
 from scipy.signal import correlate2d
 
@@ -353,6 +355,27 @@ def check_alg1(lib):
                   alg1.quantise(f + Fr(q, 2), q)}
         assert alg1.quantise(g, q) in marked
     assert [alg1.quantise(v, 10) for v in (4, 5, 14, 15, Fr(29, 2))] == [0, 1, 1, 2, 1]
+    # the guarantee on the membership array itself: for every crop's feature
+    # vector F, every g with |g_f - F_f| < q_f / 2 in each feature is marked
+    tm = rng.integers(0, 256, (17, 17)).astype(np.uint16)
+    qbar = (1, 40, 2)
+    mem = alg1.membership(tm, Fr(1, 2), Fr(2), qbar, 7, lib)
+    for (m, lo, hi), (r, q, marked) in zip(alg1.bands(17, Fr(1, 2), Fr(2)), mem):
+        for k in range(lo, hi + 1):
+            F, _ = alg1.crop_features(tm, k, m, lib)
+            for u in itertools.product((-1, 0, 1), repeat=3):
+                g = [F[f] + u[f] * (Fr(q[f], 2) - Fr(1, 1000)) for f in range(3)]
+                assert tuple(alg1.quantise(g[f], q[f]) for f in range(3)) in marked, (k, m, u)
+    # the step is per pixel of star area: a flat template of value c against
+    # a flat reference of value c + d, d < qbar/2, is marked in every band
+    # (its star sums differ by d A(r) < q/2); d = 2 qbar is marked in none
+    # (Q(f + 2q) = Q(f) + 2, while the marked cells reach Q(f) + 1 at most)
+    for d, want in ((2, 1), (10, 0)):
+        ref = np.full((70, 70), 100 + d, np.uint16)
+        flat = np.full((25, 25), 100, np.uint16)
+        bits = alg1.screen(ref, [flat], Fr(1, 2), Fr(2), (5, 1, 1), 1, lib)
+        nb = len(alg1.bands(25, Fr(1, 2), Fr(2)))
+        assert int(bits[0, 35, 35]) == (want * ((1 << nb) - 1)), (d, int(bits[0, 35, 35]))
     # an exact cut survives at its centre in the band holding k = n
     from synth import blob_image, make_rng, cut_patch
     img = blob_image(120, 130, make_rng(97, 0), blobs_per_512sq=1500, sig_hi=10)
@@ -424,6 +447,19 @@ def check_moments(lib):
     # magnitude 10% tolerance: |m - 50| <= 5 with m^2 = 55^2 passes, 55^2 + 1 fails
     assert om.probe_pass((1000, 5000, 55, 0), FT, 4, 4, (0, 0, 10), 100, om.MAG, lib)
     assert not om.probe_pass((1000, 5000, 55, 1), FT, 4, 4, (0, 0, 10), 100, om.MAG, lib)
+    # r != rho: features built from equal normalised values (mean F1 / A,
+    # variance F2 / A - mean^2, magnitude |(Sx, Sy)| / (r A)) pass at P = 0,
+    # and one unit more in the raw sum fails
+    for r, rho in ((4, 8), (9, 5), (3, 16)):
+        A_r, A_t = oc.star_area(r, lib), oc.star_area(rho, lib)
+        mean, var, g = 10, 9, 3
+        F = (mean * A_r, (var + mean * mean) * A_r, g * r * A_r, 0)
+        T = (mean * A_t, (var + mean * mean) * A_t, g * rho * A_t, 0)
+        for test, bump in ((om.MEAN, (1, 0, 0, 0)), (om.VAR, (0, 1, 0, 0)),
+                           (om.MAG, (0, 0, 1, 0))):
+            assert om.probe_pass(F, T, r, rho, (0, 0, 0), 1, test, lib), (r, rho, test)
+            Fb = tuple(a + b for a, b in zip(F, bump))
+            assert not om.probe_pass(Fb, T, r, rho, (0, 0, 0), 1, test, lib), (r, rho, test)
     # exact cuts survive at their centre with every test at P = 0
     from synth import blob_image, make_rng, cut_patch
     img = blob_image(90, 96, make_rng(95, 0), blobs_per_512sq=1500, sig_hi=10)

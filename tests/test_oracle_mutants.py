@@ -59,3 +59,57 @@ def test_mutant_is_caught(name, tmp_path):
         except AssertionError:
             caught.append(check.__name__)
     assert caught, f"mutant {name} passed every pin"
+
+
+# Mistakes planted in the Python parts of the oracle (Algorithm 1 and the
+# paper's own features): (module, anchor, replacement, pin that must fail).
+PY_MUTANTS = {
+    "alg1_band_count_off_by_one": ("alg1", "while Fraction(2) ** B < ratio2:",
+                                   "while Fraction(2) ** B <= ratio2:"),
+    "alg1_band_low_exponent": ("alg1", "k_lo = _ceil_over_sqrt2_pow(v, b + 1)",
+                               "k_lo = _ceil_over_sqrt2_pow(v, b)"),
+    "alg1_resize_corner_aligned": ("alg1", "num = (2 * i + 1) * n - k",
+                                   "num = 2 * i * n - k"),
+    "alg1_resize_round_down": ("alg1", "return ((2 * val + den) // (2 * den))",
+                               "return ((2 * val) // (2 * den))"),
+    "alg1_quantise_floor": ("alg1", "return floor(Fraction(f) / q + Fraction(1, 2))",
+                            "return floor(Fraction(f) / q)"),
+    "alg1_mark_drop_low": ("alg1", "cells.append(sorted({quantise(F[f] - h, q[f]), "
+                                   "quantise(F[f], q[f]),",
+                           "cells.append(sorted({quantise(F[f], q[f]),"),
+    "alg1_mark_drop_high": ("alg1", "quantise(F[f] + h, q[f])}))", "quantise(F[f], q[f])}))"),
+    "alg1_step_without_area": ("alg1", "q = [qbar[f] * A for f in range(3)]",
+                               "q = [qbar[f] for f in range(3)]"),
+    "moments_mean_areas_swapped": (
+        "moments", "(Q - P[0]) * t1 * A_r <= Q * f1 * A_rho <= (Q + P[0]) * t1 * A_r",
+        "(Q - P[0]) * t1 * A_rho <= Q * f1 * A_r <= (Q + P[0]) * t1 * A_rho"),
+    "moments_var_areas_swapped": ("moments", "V, VT = A_r * f2 - f1 * f1, A_rho * t2 - t1 * t1",
+                                  "V, VT = A_rho * f2 - f1 * f1, A_r * t2 - t1 * t1"),
+    "moments_var_sign": ("moments", "V, VT = A_r * f2 - f1 * f1,", "V, VT = A_r * f2 + f1 * f1,"),
+    "moments_mag_without_lever_arm": ("moments", "N_r, N_rho = r * A_r, rho * A_rho",
+                                      "N_r, N_rho = A_r, A_rho"),
+    "moments_mag_bound_unsquared": ("moments", "(Q + P[2]) ** 2 * MT * N_r ** 2",
+                                    "(Q + P[2]) * MT * N_r ** 2"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_mutant_is_caught(name, monkeypatch, oracle_lib):
+    import sys
+    import types
+
+    import oracle
+    import oracle_pins
+    modname, old, new = PY_MUTANTS[name]
+    path = os.path.join(os.path.dirname(oc.__file__), modname + ".py")
+    src = open(path).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found once"
+    mod = types.ModuleType("oracle." + modname)
+    mod.__file__ = path
+    mod.__package__ = "oracle"
+    exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+    monkeypatch.setitem(sys.modules, "oracle." + modname, mod)
+    monkeypatch.setattr(oracle, modname, mod, raising=False)
+    check = {"alg1": oracle_pins.check_alg1, "moments": oracle_pins.check_moments}[modname]
+    with pytest.raises(AssertionError):
+        check(oracle_lib)
