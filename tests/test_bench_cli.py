@@ -32,3 +32,20 @@ def test_algorithmic_bytes():
 def test_pixel_scales_count_valid_positions():
     # a radius-r star fits at (H - 2r)(W - 2r) positions; none when 2r >= H
     assert bench.pixel_scales(10, 12, [(0, 0, 2), (0, 1, 5)]) == 6 * 8 + 0
+
+
+def test_lanes_copy_every_option():
+    """The lanes of a two-lane run are contexts that copy the main context's
+    options: every option the header defines must be in that list."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "oss.h")).read()
+    defined = set(re.findall(r"#define (OSS_OPT_\w+) \d+", hdr))
+    assert defined and set(bench.OPTIONS) == defined
+
+
+def test_binding_option_ids_match_header():
+    import re
+    from paper_1707_05647_amd import _lib as L
+    hdr = open(os.path.join(ROOT, "include", "oss.h")).read()
+    for name, val in re.findall(r"#define (OSS_OPT_\w+) (\d+)", hdr):
+        assert getattr(L, name) == int(val), name
