@@ -197,6 +197,16 @@ def check_planted_exact(lib):
     tm = cut_patch(img, cx, cy, rho + 1)
     bits = oc.screen_positions(img, [(tm, rho)], probes, 7, (0, 0, 0), 1, [cx + 3], [cy], lib)
     assert bits[0, 0] == 0
+    # an even-width, odd-height cut: its centre pixel is (floor((w-1)/2),
+    # floor((h-1)/2)), so the copy survives at the image pixel that lands
+    # there, and not one column further (a one-pixel apron around the star
+    # keeps the gradients of the cut equal to the image's)
+    w, h = 2 * rho + 4, 2 * rho + 5
+    x0, y0 = cx - (w - 1) // 2, cy - (h - 1) // 2
+    tm = img[y0:y0 + h, x0:x0 + w].copy()
+    bits = oc.screen_positions(img, [(tm, rho)], probes, 7, (0, 0, 0), 1, [cx, cx + 1],
+                               [cy, cy], lib)
+    assert bits[0, 0] == 1 and bits[0, 1] == 0
 
 
 def _py_pass(f, F, FT, r, rho, P, Q):

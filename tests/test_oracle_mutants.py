@@ -61,8 +61,8 @@ def test_mutant_is_caught(name, tmp_path):
     assert caught, f"mutant {name} passed every pin"
 
 
-# Mistakes planted in the Python parts of the oracle (Algorithm 1 and the
-# paper's own features): (module, anchor, replacement, pin that must fail).
+# Mistakes planted in the Python parts of the oracle (the template centre,
+# Algorithm 1 and the paper's own features): (module, anchor, replacement).
 PY_MUTANTS = {
     "alg1_band_count_off_by_one": ("alg1", "while Fraction(2) ** B < ratio2:",
                                    "while Fraction(2) ** B <= ratio2:"),
@@ -80,6 +80,8 @@ PY_MUTANTS = {
     "alg1_mark_drop_high": ("alg1", "quantise(F[f] + h, q[f])}))", "quantise(F[f], q[f])}))"),
     "alg1_step_without_area": ("alg1", "q = [qbar[f] * A for f in range(3)]",
                                "q = [qbar[f] for f in range(3)]"),
+    "core_template_centre_rounded_up": ("core", "cx, cy = (w - 1) // 2, (h - 1) // 2",
+                                        "cx, cy = w // 2, h // 2"),
     "moments_mean_areas_swapped": (
         "moments", "(Q - P[0]) * t1 * A_r <= Q * f1 * A_rho <= (Q + P[0]) * t1 * A_r",
         "(Q - P[0]) * t1 * A_rho <= Q * f1 * A_r <= (Q + P[0]) * t1 * A_rho"),
@@ -110,6 +112,10 @@ def test_python_mutant_is_caught(name, monkeypatch, oracle_lib):
     exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
     monkeypatch.setitem(sys.modules, "oracle." + modname, mod)
     monkeypatch.setattr(oracle, modname, mod, raising=False)
-    check = {"alg1": oracle_pins.check_alg1, "moments": oracle_pins.check_moments}[modname]
+    check = {"alg1": oracle_pins.check_alg1, "moments": oracle_pins.check_moments,
+             "core": oracle_pins.check_planted_exact}[modname]
+    if modname == "core":
+        # the pins call the oracle through the module-level name
+        monkeypatch.setattr(oracle_pins, "oc", mod)
     with pytest.raises(AssertionError):
         check(oracle_lib)
