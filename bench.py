@@ -170,6 +170,26 @@ WORKLOAD_TEXT = {
 }
 
 
+class ScreenGate:
+    """Keeps the lanes' screens from running at the same time: a lane's
+    screen waits (on the GPU, through an event) for the previous lane's
+    screen to end, while its build does not wait, so builds still overlap
+    screens but two star passes never share the L2."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.last = None
+
+    def wait(self, st):
+        if self.last is not None:
+            st.wait_event(self.last)
+
+    def record(self, st):
+        ev = self.torch.cuda.Event()
+        ev.record(st)
+        self.last = ev
+
+
 def run_pipelined(lanes, make_lane, steps, warmup, L, torch):
     """Steps dealt round-robin to `lanes` lanes (a context, a stream, tables
     and outputs each): step i runs on lane i mod lanes, so the builder of one
@@ -210,6 +230,7 @@ def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, bat
     lanes' kernel profile and whether every lane's last result equals the
     single-lane run's."""
     from paper_1707_05647_amd.screen import Context
+    gate = ScreenGate(torch) if args.serial_screens else None
 
     def make_lane():
         c = Context(0)
@@ -223,7 +244,7 @@ def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, bat
         cn = torch.zeros(1, dtype=torch.int64, device=dev)
 
         def step():
-            screen_step(c.handle, r, st, m, cd, cn, batched)
+            screen_step(c.handle, r, st, m, cd, cn, batched, gate)
         return {"ctx": c, "ref": r, "step": step, "mask": m, "cands": cd, "count": cn}
 
     sec, prof, lanes = run_pipelined(n_lanes, make_lane, args.steps, args.warmup, L, torch)
@@ -543,6 +564,9 @@ def main():
     ap.add_argument("--staged", type=int, default=-1,
                     help="1/0: staged lookups (first quantity alone, the rest where it passes) / "
                          "every quantity at every lookup; -1 = library default")
+    ap.add_argument("--serial-screens", type=int, default=0,
+                    help="1: on two or more lanes a lane's screen waits for the previous "
+                         "lane's screen (builds still overlap screens)")
     ap.add_argument("--build-stream", type=int, default=-1,
                     help="1/0: table entries stored with / without non-temporal (streaming) "
                          "stores; -1 = library default for the lanes, ordinary stores for the "
@@ -641,26 +665,27 @@ def main():
 
     MOM_TOL = (5, 30, 40, 100)
 
-    def screen_step(ch, r, st, m, cd, cn, batched):
+    def screen_step(ch, r, st, m, cd, cn, batched, gate=None):
         """One step of the chosen variant on context ch, reference r, stream
-        st, into mask m, list cd and count cn."""
+        st, into mask m, list cd and count cn; with a gate, the screen (not
+        the build) waits for the previous lane's screen."""
+        r.build(st)
+        if gate is not None:
+            gate.wait(st)
         if args.alg1:
-            pr = alg1_probes()
-            r.build(st)
-            L.oss_screen_intervals(ch, r.handle, T, pr, w.feat_mask, m, cd, cap, cn, st)
+            L.oss_screen_intervals(ch, r.handle, T, alg1_probes(), w.feat_mask, m, cd, cap, cn,
+                                   st)
         elif args.moments:
             tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
-            r.build(st)
             L.oss_screen_moments(ch, r.handle, tm, w.probes, MOM_TOL, 7, m, cd, cap, cn, st)
         elif args.rings > 1:
-            tm = tfeat_rings()
-            r.build(st)
-            L.oss_screen_rings(ch, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn, st)
+            L.oss_screen_rings(ch, r.handle, tfeat_rings(), w.probes, tol, w.feat_mask, m, cd,
+                               cap, cn, st)
         else:
-            tm = tfeat()
-            r.build(st)
-            L.oss_screen(ch, r.handle, tm, w.probes, tol, w.feat_mask, m, cd, cap, cn, st,
+            L.oss_screen(ch, r.handle, tfeat(), w.probes, tol, w.feat_mask, m, cd, cap, cn, st,
                          batched=batched)
+        if gate is not None:
+            gate.record(st)
 
     def make_step(batched):
         return lambda: screen_step(ctx.handle, ref, stream, mask, cands, count, batched)
@@ -798,6 +823,7 @@ def main():
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if (big or args.rings > 1) else "plain",
             "lanes": lanes,
+            "serial_screens": bool(args.serial_screens),
             "rings": args.rings,
             "alg1": bool(args.alg1),
             "moments": bool(args.moments),

@@ -49,3 +49,34 @@ def test_binding_option_ids_match_header():
     hdr = open(os.path.join(ROOT, "include", "oss.h")).read()
     for name, val in re.findall(r"#define (OSS_OPT_\w+) (\d+)", hdr):
         assert getattr(L, name) == int(val), name
+
+
+def test_screen_gate_orders_screens():
+    """The serial-screens gate: the first screen waits for nothing, each
+    later screen waits for the event recorded after the previous one."""
+    class Ev:
+        def __init__(self):
+            self.on = None
+
+        def record(self, st):
+            self.on = st
+
+    class FakeTorch:
+        class cuda:
+            Event = Ev
+
+    class St:
+        def __init__(self, name):
+            self.name, self.waited = name, []
+
+        def wait_event(self, ev):
+            self.waited.append(ev.on.name)
+
+    g = bench.ScreenGate(FakeTorch)
+    a, b = St("a"), St("b")
+    g.wait(a)
+    g.record(a)
+    g.wait(b)
+    g.record(b)
+    g.wait(a)
+    assert a.waited == ["b"] and b.waited == ["a"]
