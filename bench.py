@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Screening throughput on one MI355X.
 
-Workload: the rotation + scale screen, a 4096x4096 uint8 blob + noise
-reference, one template resampled at a random angle and scale, probe radii
-16..64 in steps of 8 (7 scales), features sum / sum of squares / gradient
-sum, int64 arithmetic.  One step is the whole hot path on inputs already in
-HBM: template features (host), the integral-table build, the star + compare
-kernel and the candidate compaction (mask + list).
+Default line (no --workload): the large batched screen, a 16384x16384
+12-bit blob + noise reference, one radius-48 template at 16 rotations, 32
+radii from 24 to 96 (512 probes), features sum / sum of squares / gradient
+sum, int64 arithmetic, all probes in one batched persistent launch.  One
+step is the whole hot path on inputs already in HBM: template features
+(host), the integral-table build, the star + compare pass and the candidate
+compaction (mask + list).  The same line nests a short run of the
+rotation + scale screen (4096x4096 uint8, 7 radii) under ``workload_2`` and
+of the serving loop (Poisson requests, served p50 / p99) under ``serving``.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload {2,3,4,5}]
 
-Prints one JSON line.  ``value`` is screened pixel-scales per second
-(one pixel-scale = one valid (position, probe) pair), in G/s.  ``roofline``
-reports the dominant kernel's algorithmic HBM bytes per launch over its
-average duration, timed with HIP events recorded by the library on the
-launch stream over the timed steps.  ``cpu_baseline`` times the CPU oracle
-on a bounded random sample of the same workload (and checks the GPU result
-at those positions bit for bit).
+Prints one JSON line.  ``value`` is screened pixel-scales per second (one
+pixel-scale = one valid (position, probe) pair), in G/s.  ``roofline``
+reports the dominant kernel's algorithmic HBM bytes per launch (the tables
+read once plus the method's own outputs) over its average duration, timed
+with HIP events recorded by the library on the launch stream over the
+timed steps; ``copy_peak_GBps`` is a plain device copy timed the same way.
+``cpu_baseline`` times the CPU oracle on a bounded random sample of the
+same workload (and checks the GPU result at those positions bit for bit).
 """
 from __future__ import annotations
 
@@ -33,17 +37,27 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
 L1_PEAK_GBPS = 256 * 64 * 2.4  # 256 CUs x 64 B/clk x 2.4 GHz vector L1 delivery
 METRIC = "screened pixel-scales/s (G/s) & % HBM peak; bit-exact mask; served p50/p99 ms"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# arithmetic: star sums and compares in int64; table entries stored modulo
+# 2^32 wherever every region sum they serve is provably below 2^32
+DTYPE = "int64 (sums and compares; tables mod 2^32 where exact)"
+BATCH_GROUP = 64        # templates per batched group (no rings)
+BATCH_GROUP_RINGS = 32  # templates per batched group with central-star rings
+
+
 def pixel_scales(H, W, probes):
     """Valid (position, probe) pairs."""
     return sum(max(0, H - 2 * r) * max(0, W - 2 * r) for _, _, r in probes)
 
 
-def lookup_pairs(w, batched=False, group=32, rings=1):
+def lookup_pairs(w, batched=False, group=None, rings=1):
     """Valid (position, radius) pairs whose star sums a launch evaluates, each
     8 table lookups per quantity: one per (template, distinct radius) for
     per-template launches; one per (template group, distinct radius) for the
-    batched launch (templates sorted by radius, groups of 32)."""
+    batched launch (templates sorted by radius, groups of 64, 32 with
+    rings)."""
+    if group is None:
+        group = BATCH_GROUP_RINGS if rings > 1 else BATCH_GROUP
+
     def chain(r):
         out = [r]
         for _ in range(rings - 1):  # central-star radii s(r), s(s(r)), ...
@@ -62,30 +76,45 @@ def ref_nq(feat_mask):
     return bin(feat_mask).count("1")
 
 
-def algorithmic_bytes(H, W, n_tmpl, px_bytes, entry_bytes):
-    """Minimum HBM bytes per launch of each kernel: the three tables once
-    (entry_bytes per entry), the image once, the scale-bit words once."""
+def algorithmic_bytes(H, W, n_tmpl, px_bytes, entry_bytes, n_cand=0):
+    """Minimum HBM bytes per launch of each kernel, counting only what the
+    method itself must move: the image once, the three tables once (written
+    by the build, read by the screen: entry_bytes per entry), the uint8 mask
+    (one byte per template and position) and the candidate list (16 bytes
+    per candidate).  Scratch of the implementation (scale-bit words, staged
+    candidates, segment counts) is not algorithmic."""
     table = 3 * (H + 1) * (W + 1) * entry_bytes
     hw = H * W
     return {
         # writes every table entry once, reads the image once
         "band_final": table + hw * px_bytes,
-        # reads every table entry once, writes one scale-bit word per position
-        "star_plain": table + n_tmpl * hw * 4,
-        # reads the scale-bit words
-        "compact_count": n_tmpl * hw * 4,
-        # reads the scale-bit words, writes the mask (candidates are few)
-        "compact_write": n_tmpl * hw * 5,
+        # reads every table entry once, writes the mask
+        "star_plain": table + n_tmpl * hw,
+        "star_batch": table + n_tmpl * hw,
+        "star_moments": table + n_tmpl * hw,
+        # writes the candidate list
+        "compact_write": 16 * n_cand,
+        "compact_list": 16 * n_cand,
         "row_base": hw * px_bytes,
         "band_agg": hw * px_bytes,
     }
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+# committed rocprofv3 counter summaries, per workload
+TRAFFIC_FILES = {
+    2: os.path.join(ROOT, "profiles", "traffic_4096_u8_7radii.json"),
+    5: os.path.join(ROOT, "profiles", "traffic_16384_12bit_512probes.json"),
+}
+
+
+def traffic_for(kernel: str, workload: int):
+    """HBM bytes per launch from the committed rocprofv3 counter runs of this
+    workload, if they were taken on the current kernel source."""
+    path = TRAFFIC_FILES.get(workload)
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -319,13 +348,16 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, np.float64), q)) if len(v) else None
 
 
-def run_serving(args):
+def run_serving(args, n_requests=None):
     """Workload 4.  The per-request scheme (tables built for every request,
     one launch per template, one request at a time) is timed back to back to
     find its capacity; the same Poisson stream, at 80% of that rate, is then
     served by (a) that scheme, first come first served, and (b) the server
-    (resident tables, merged batched launches, several lanes).  Latency runs
-    from a request's arrival to its result being ready."""
+    (resident tables, merged batched launches, several lanes; requests are
+    submitted as they arrive, while earlier launches run).  Latency runs from
+    a request's arrival to its result being ready.  Every served result
+    (mask and list) is compared element by element with the same request
+    screened alone.  Returns the result dict."""
     import numpy as np
     import torch
 
@@ -333,23 +365,21 @@ def run_serving(args):
     from paper_1707_05647_amd.screen import Context, Server
     from synth import serving_requests
 
+    n_req = n_requests or args.requests
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    print(f"serving: generating {args.requests} requests", file=sys.stderr, flush=True)
-    reqs, images = serving_requests(args.requests, 1.0, args.seed, device=dev)
+    print(f"serving: generating {n_req} requests", file=sys.stderr, flush=True)
+    reqs, images = serving_requests(n_req, 1.0, args.seed, device=dev)
     imgs = {k: L.device_image(v, dev) for k, v in images.items()}
     feats = [[L.oss_template_features(t.pixels, t.rho, L.OSS_F_ALL) for t in q.templates]
              for q in reqs]
     ctx = Context(0)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     cands = torch.empty((SERVE_CAP, 4), dtype=torch.int32, device=dev)
+    alone = [None] * len(reqs)
 
-    def digest(mask_t, cands_t, n):
-        m = min(n, SERVE_CAP)
-        return (n, int(mask_t.sum().item()), int(cands_t[:m].to(torch.int64).sum().item()))
-
-    def plain_one(i):
+    def plain_one(i, keep=False):
         q = reqs[i]
         ref = ctx.reference(imgs[q.ref_key], L.OSS_F_ALL, 8, stream,
                             max_radius=max([p[2] for p in q.probes] + [0]))
@@ -358,14 +388,16 @@ def run_serving(args):
                      cands, SERVE_CAP, count, stream)
         torch.cuda.synchronize()
         n = int(count.item())
-        d = digest(mask, cands, n)
+        if keep:
+            alone[i] = (mask, cands[:min(n, SERVE_CAP)].clone(), n)
         ref.release()
-        return d
 
-    # warm-up and the per-request scheme's capacity (back to back)
+    # warm-up and the per-request scheme's capacity (back to back); the
+    # results of this pass are kept as each request's screen alone
     plain_one(0)
     t0 = time.perf_counter()
-    plain_digest = [plain_one(i) for i in range(len(reqs))]
+    for i in range(len(reqs)):
+        plain_one(i, keep=True)
     plain_busy = time.perf_counter() - t0
     capacity = len(reqs) / plain_busy
     rate = 0.8 * capacity
@@ -422,19 +454,21 @@ def run_serving(args):
         hits += r.resident_hit
         mask_t = torch.empty((r.n_tmpl, r.H, r.W), dtype=torch.uint8, device=dev)
         m = min(r.count, SERVE_CAP)
-        lst = torch.empty((max(m, 1), 4), dtype=torch.int32, device=dev)
+        lst = torch.empty((m, 4), dtype=torch.int32, device=dev)
         _dev_copy(mask_t, r.dev_mask)
         if m:
-            _dev_copy(lst[:m], r.dev_list)
-        same += digest(mask_t, lst, r.count) == plain_digest[i]
+            _dev_copy(lst, r.dev_list)
+        a_mask, a_list, a_n = alone[i]
+        same += int(r.count == a_n and torch.equal(mask_t, a_mask) and torch.equal(lst, a_list))
         srv.release(rid)
     st = srv.stats()
     srv.close()
     ctx.close()
+    del alone
 
     ps = [pixel_scales(q.side, q.side, q.probes) for q in reqs]
     total_ps = float(sum(ps))
-    out = {
+    return {
         "metric": METRIC,
         "value": total_ps / span_srv / 1e9,
         "unit": "G pixel-scales/s",
@@ -445,7 +479,7 @@ def run_serving(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int64",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[4], "requests": len(reqs),
                    "distinct_references": len(images), "lanes": args.lanes, "seed": args.seed,
@@ -459,6 +493,7 @@ def run_serving(args):
             "resident_hits": hits, "launches": st["launches"], "builds": st["builds"],
             "evictions": st["evictions"], "bytes_peak": st["bytes_peak"],
             "identical_to_alone": same, "of": len(reqs),
+            "compared": "mask and candidate list element by element, and the count",
         },
         "per_request_scheme": {
             "capacity_requests_per_s": capacity,
@@ -468,7 +503,6 @@ def run_serving(args):
         },
         "offered_requests_per_s": rate,
     }
-    print(json.dumps(out), flush=True)
 
 
 def _dev_copy(dst, src_ptr: int):
@@ -526,15 +560,323 @@ def evaluate_regions(w, ctx, L, torch, dev, cands, count, cap):
     }
 
 
-def main():
+def copy_peak(torch, dev, mib=4096, reps=5):
+    """Achievable HBM rate: a plain device-to-device copy of `mib` MiB timed
+    with events (bytes read + bytes written per second, best of `reps`)."""
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": 2.0 * (mib << 20) / (best / 1e3) / 1e9, "bytes_per_copy": 2 * (mib << 20),
+            "ms": best, "kernel": "torch device copy (read + write)"}
+
+
+def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_baseline=True,
+              compare_plain=True):
+    """Workloads 2, 3 and 5: the timed steps on one lane, then on `lanes`
+    lanes (the headline figure), the batched-over-plain comparison for the
+    batched workloads, the roofline figures and the sampled CPU oracle.
+    Returns the result dict."""
+    import torch
+
+    from paper_1707_05647_amd import _lib as L
+    from paper_1707_05647_amd.screen import Context
+    from synth import make_workload
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    big = workload in (3, 5)
+    print(f"workload {workload}: generating inputs", file=sys.stderr, flush=True)
+    w = make_workload(workload, args.seed, device=dev if big else None)
+    img = L.device_image(w.ref, dev)
+    ctx = Context(0)
+    if args.star_strip:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, args.star_strip)
+    if args.star_blocks:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, args.star_blocks)
+    if args.star_lds >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_LDS, args.star_lds)
+    planar = args.planar
+    if planar < 0 and workload == 3:
+        # loose tolerances (45-80 %): most positions pass the first feature,
+        # so staged lookups on planar tables save nothing and one lookup of
+        # an interleaved entry beats several plane reads
+        planar = 0
+    if planar >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR, planar)
+    if args.pipe >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
+    if args.staged >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STAGED, args.staged)
+    if args.build_stream >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, args.build_stream)
+    lanes = args.pipeline if args.pipeline >= 1 else 2
+    lane_stream = L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM)
+    if args.build_stream < 0:
+        # streaming table stores pay off only beside another lane's star
+        # pass: the one-lane runs use ordinary stores
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, 0)
+    max_r = max(w.radii())
+    if args.alg1:
+        from fractions import Fraction
+        max_r = max(p.r for t, tp in enumerate(w.templates)
+                    for p in L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2),
+                                               (1, 1, 1), w.feat_mask, bit_depth=w.depth))
+    ref_fm = (L.OSS_F_SUM | L.OSS_F_SQ | L.OSS_F_MOMENTS) if args.moments else w.feat_mask
+    ref = ctx.reference(img, ref_fm, w.depth, build=False, max_radius=max_r)
+    T = len(w.templates)
+    mask = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    tol = (*w.tol_P, w.tol_Q)
+
+    def tfeat():
+        return [L.oss_template_features(t.pixels, t.rho, w.feat_mask, bit_depth=w.depth)
+                for t in w.templates]
+
+    def tfeat_rings():
+        return [L.oss_template_features_rings(t.pixels, t.rho, w.feat_mask, args.rings,
+                                              bit_depth=w.depth) for t in w.templates]
+
+    ALG1_Q = (4, 300, 6) if w.depth == 8 else (64, 80000, 90)
+
+    def alg1_probes():
+        from fractions import Fraction
+        out = []
+        for t, tp in enumerate(w.templates):
+            out += L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2), ALG1_Q,
+                                     w.feat_mask, bit_depth=w.depth)
+        return out
+
+    MOM_TOL = (5, 30, 40, 100)
+    state = {"cap": 0}
+
+    def screen_step(ch, r, st, m, cd, cn, batched, gate=None):
+        """One step of the chosen variant on context ch, reference r, stream
+        st, into mask m, list cd and count cn; with a gate, the screen (not
+        the build) waits for the previous lane's screen."""
+        cap = state["cap"]
+        r.build(st)
+        if gate is not None:
+            gate.wait(st)
+        if args.alg1:
+            L.oss_screen_intervals(ch, r.handle, T, alg1_probes(), w.feat_mask, m, cd, cap, cn,
+                                   st)
+        elif args.moments:
+            tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
+            L.oss_screen_moments(ch, r.handle, tm, w.probes, MOM_TOL, 7, m, cd, cap, cn, st)
+        elif args.rings > 1:
+            L.oss_screen_rings(ch, r.handle, tfeat_rings(), w.probes, tol, w.feat_mask, m, cd,
+                               cap, cn, st)
+        else:
+            L.oss_screen(ch, r.handle, tfeat(), w.probes, tol, w.feat_mask, m, cd, cap, cn, st,
+                         batched=batched)
+        if gate is not None:
+            gate.record(st)
+
+    batched_path = big or args.rings > 1
+    # list capacity: the count of a first screen (no list), so the list holds
+    # every candidate and the sampled check sees a complete list
+    screen_step(ctx.handle, ref, stream, mask, None, count, batched_path)
+    torch.cuda.synchronize()
+    n_probe = int(count.item())
+    cap = max(1, n_probe)
+    state["cap"] = cap
+    cands = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+
+    def make_step(batched):
+        return lambda: screen_step(ctx.handle, ref, stream, mask, cands, count, batched)
+
+    extra = {}
+    if big:
+        if not args.no_autotune:
+            tr = L.oss_autotune_batched(ctx.handle, ref.handle, tfeat(), w.probes, tol,
+                                        w.feat_mask, stream)
+            extra["autotune"] = {
+                "strip": tr.strip, "blocks_per_xcd": tr.blocks_per_xcd,
+                "bucket_radii": tr.bucket_radii, "ms": tr.ms,
+                "tried": [[tr.tried[i][0], tr.tried[i][1], tr.tried[i][2], tr.tried_ms[i]]
+                          for i in range(tr.n_tried)]}
+        if compare_plain:
+            # the per-template launches at their own best shape (strip 512,
+            # 32 / 64 / 128 blocks per XCD), then the batched shape again
+            print(f"workload {workload}: per-template launches", file=sys.stderr, flush=True)
+            tuned = [L.oss_ctx_get_option(ctx.handle, o)
+                     for o in (L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD)]
+            best = None
+            for blocks in (32, 64, 128):
+                L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, 512)
+                L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, blocks)
+                plain_s, plain_prof = run_steps(make_step(False), max(1, steps // 4), 1, ctx,
+                                                L, torch)
+                if best is None or plain_s < best[0]:
+                    best = (plain_s, plain_prof, blocks)
+            for o, v in zip((L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD), tuned):
+                L.oss_ctx_set_option(ctx.handle, o, v)
+            plain_s, plain_prof, blocks = best
+            extra["plain_ms_per_step"] = plain_s * 1e3
+            extra["plain_shape"] = {"strip": 512, "blocks_per_xcd": blocks}
+            extra["plain_kernels"] = {k: v[1] / max(v[0], 1) for k, v in plain_prof.items()}
+    print(f"workload {workload}: timed steps, one lane", file=sys.stderr, flush=True)
+    sec, prof = run_steps(make_step(batched_path), steps, warmup, ctx, L, torch)
+
+    if args.alg1:
+        # one pixel-scale per (valid position, template, band)
+        bands = {(p.template_id, p.scale_id, p.r) for p in alg1_probes()}
+        ps = sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, _, r in bands)
+    else:
+        ps = pixel_scales(w.H, w.W, w.probes)
+    value = ps / sec / 1e9
+    n = int(count.item())
+    if n != n_probe:
+        raise RuntimeError(f"candidate count changed between runs ({n_probe} -> {n})")
+    if big and compare_plain:
+        # batched against per-template launches, one lane each
+        extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
+        extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
+    if lanes >= 2:
+        # the timed figures below are the lanes' run; the single lane's are kept
+        extra["single_lane"] = {
+            "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
+            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
+                        for k, v in prof.items()}}
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, lane_stream)
+        print(f"workload {workload}: timed steps, {lanes} lanes", file=sys.stderr, flush=True)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = steps, warmup
+        sec, prof, same = pipelined(sub, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap,
+                                    batched_path, screen_step, n, mask, cands)
+        extra["lanes_identical_to_single_lane"] = same
+        value = ps / sec / 1e9
+    eb = sum(b // 8 for _, b in ref.slots)  # table bytes per position, all quantities
+    staged = (ref.plane_bytes > 0 and len(ref.slots) > 1 and not args.moments
+              and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED) == 1
+              and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE) == 0)
+    # table bytes per entry as stored (64-bit squares in two 32-bit planes)
+    ebs = ref.entry_bytes * (len(ref.slots) + sum(1 for _, b in ref.slots if b == 64)) \
+        if ref.plane_bytes else ref.entry_bytes
+    abytes = algorithmic_bytes(w.H, w.W, T, 2 if w.depth > 8 else 1, ebs, n_cand=n)
+    kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
+            for k, v in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][1])
+    avg_s = prof[dom][1] / prof[dom][0] / 1e3
+    achieved = abytes[dom] / avg_s / 1e9 if dom in abytes else None
+    roof = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS if achieved else None,
+        "traffic": traffic_for(dom, workload),
+        "algorithmic_bytes_per_launch": abytes.get(dom),
+        "algorithmic_unit": "tables read once (entry bytes x 3 tables x (H+1)(W+1)) + uint8 "
+                            "mask (templates x H x W)",
+        "avg_ms": avg_s * 1e3,
+        "timed_on": f"{lanes} lanes" if lanes >= 2 else "one lane",
+    }
+    if lanes >= 2 and dom in extra["single_lane"]["kernels"]:
+        one = extra["single_lane"]["kernels"][dom]["avg_ms"] / 1e3
+        roof["one_lane"] = {"avg_ms": one * 1e3, "achieved": abytes[dom] / one / 1e9,
+                            "frac": abytes[dom] / one / 1e9 / HBM_PEAK_GBPS}
+    if dom in ("star_plain", "star_batch"):
+        # the same launch against the vector-memory path that actually bounds it
+        # staged lookups read the first quantity everywhere and the others
+        # only where it passes: only the first quantity's bytes are counted
+        per = ref.entry_bytes if staged else eb
+        lookups = lookup_pairs(w, dom == "star_batch", rings=args.rings) * 8 * per
+        roof["vector_l1"] = {"achieved": lookups / avg_s / 1e9, "peak": L1_PEAK_GBPS,
+                             "unit": "GB/s", "frac": lookups / avg_s / 1e9 / L1_PEAK_GBPS,
+                             "lookup_bytes_per_launch": lookups,
+                             "counted": ("first quantity only (staged lookups)" if staged
+                                         else "every quantity")}
+    for k in kern:
+        if k in abytes and abytes[k]:
+            kern[k]["achieved_GBps"] = abytes[k] / (kern[k]["avg_ms"] / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "G pixel-scales/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE,
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD_TEXT[workload],
+            "H": w.H, "W": w.W, "radii": w.radii(), "templates": T, "probes": len(w.probes),
+            "tolerance_P_over_Q": [p / w.tol_Q for p in w.tol_P], "seed": args.seed,
+            "pixel_scales_per_step": ps,
+            "table_value_bits": ref.value_bits,
+            "table_entry_bytes": ebs,
+            "table_layout": "planar" if ref.plane_bytes else "interleaved",
+            "star_strip": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STRIP),
+            "star_blocks_per_xcd": L.oss_ctx_get_option(ctx.handle,
+                                                        L.OSS_OPT_STAR_BLOCKS_PER_XCD),
+            "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
+            "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
+            "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
+            "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
+            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
+            "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
+            "launch": "batched" if batched_path else "plain",
+            "lanes": lanes,
+            "serial_screens": bool(args.serial_screens),
+            "rings": args.rings,
+            "alg1": bool(args.alg1),
+            "moments": bool(args.moments),
+            "list_cap": cap,
+        },
+        "roofline": roof,
+        "kernels": kern,
+        "candidates": n,
+        "pruned_patch_pct": 100.0 * (1 - n / float(T * w.H * w.W)),
+    }
+    out.update(extra)
+    if evaluate:
+        out["evaluation"] = evaluate_regions(w, ctx, L, torch, dev, cands, count, cap)
+    if cpu_baseline and not args.no_cpu_baseline and not args.alg1 and not args.moments:
+        print(f"workload {workload}: CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, cpu_seconds, args.rings)
+    ref.release()
+    ctx.close()
+    del mask, cands, count, img
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def nested(res, keys):
+    return {k: res[k] for k in keys if k in res}
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
-                    help="2: the headline rotation+scale screen; 3, 5: batched workloads "
-                         "(batched launch against per-template launches); 4: serving loop")
+    ap.add_argument("--workload", type=int, default=0, choices=[0, 2, 3, 4, 5],
+                    help="0 (default): the headline line, workload 5 with workload 2 and the "
+                         "serving loop nested; 2: the rotation+scale screen alone; 3, 5: batched "
+                         "workloads alone (batched launch against per-template launches); "
+                         "4: serving loop alone")
     ap.add_argument("--evaluate", type=int, default=-1,
                     help="1: preserved region, overlap with the planted ground truth and the 90%% "
                          "success criterion after the timed steps (default: on for workload 2)")
@@ -551,6 +893,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workloads: skip the per-template comparison")
     ap.add_argument("--star-strip", type=int, default=0,
                     help="star kernel strip width (threads per block); 0 = library default")
     ap.add_argument("--star-blocks", type=int, default=0,
@@ -579,117 +923,21 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first "
                          "(a reference kernel of known size for HBM byte counters)")
-    args = ap.parse_args()
+    ap.add_argument("--copy-peak-mb", type=int, default=4096,
+                    help="size of the timed device copy that gives the achievable HBM rate "
+                         "(0: skip)")
+    return ap.parse_args(argv)
+
+
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the screen shards "
               "by row bands with no exchange on the hot path, but multi-GPU runs are not part "
               "of this build.", file=sys.stderr)
         sys.exit(2)
-
-    if args.workload == 4:
-        run_serving(args)
-        return
-
     import torch
-
-    from paper_1707_05647_amd import _lib as L
-    from paper_1707_05647_amd.screen import Context
-    from synth import make_workload
-
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    big = args.workload in (3, 5)
-    w = make_workload(args.workload, args.seed, device=dev if big else None)
-    img = L.device_image(w.ref, dev)
-    ctx = Context(0)
-    if args.star_strip:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, args.star_strip)
-    if args.star_blocks:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, args.star_blocks)
-    if args.star_lds >= 0:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_LDS, args.star_lds)
-    planar = args.planar
-    if planar < 0 and args.workload == 3:
-        # loose tolerances (45-80 %): most positions pass the first feature,
-        # so staged lookups on planar tables save nothing and one lookup of
-        # an interleaved entry beats several plane reads
-        planar = 0
-    if planar >= 0:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR, planar)
-    if args.pipe >= 0:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
-    if args.staged >= 0:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STAGED, args.staged)
-    if args.build_stream >= 0:
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, args.build_stream)
-    lanes = args.pipeline if args.pipeline >= 1 else 2
-    lane_stream = L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM)
-    if args.build_stream < 0:
-        # streaming table stores pay off only beside another lane's star
-        # pass: the one-lane runs use ordinary stores
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, 0)
-    max_r = max(w.radii())
-    if args.alg1:
-        from fractions import Fraction
-        max_r = max(p.r for t, tp in enumerate(w.templates)
-                    for p in L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2),
-                                               (1, 1, 1), w.feat_mask, bit_depth=w.depth))
-    ref_fm = (L.OSS_F_SUM | L.OSS_F_SQ | L.OSS_F_MOMENTS) if args.moments else w.feat_mask
-    ref = ctx.reference(img, ref_fm, w.depth, build=False, max_radius=max_r)
-    T = len(w.templates)
-    # room for every candidate, so the sampled check sees a complete list
-    cap = min(T * w.H * w.W, 1 << 22 if not big else 1_600_000_000)
-    mask = torch.empty((T, w.H, w.W), dtype=torch.uint8, device=dev)
-    cands = torch.empty((cap, 4), dtype=torch.int32, device=dev)
-    count = torch.zeros(1, dtype=torch.int64, device=dev)
-    tol = (*w.tol_P, w.tol_Q)
-
-    def tfeat():
-        return [L.oss_template_features(t.pixels, t.rho, w.feat_mask, bit_depth=w.depth)
-                for t in w.templates]
-
-    def tfeat_rings():
-        return [L.oss_template_features_rings(t.pixels, t.rho, w.feat_mask, args.rings,
-                                              bit_depth=w.depth) for t in w.templates]
-
-    ALG1_Q = (4, 300, 6) if w.depth == 8 else (64, 80000, 90)
-
-    def alg1_probes():
-        from fractions import Fraction
-        out = []
-        for t, tp in enumerate(w.templates):
-            out += L.oss_alg1_probes(tp.pixels, t, Fraction(1, 2), Fraction(2), ALG1_Q,
-                                     w.feat_mask, bit_depth=w.depth)
-        return out
-
-    MOM_TOL = (5, 30, 40, 100)
-
-    def screen_step(ch, r, st, m, cd, cn, batched, gate=None):
-        """One step of the chosen variant on context ch, reference r, stream
-        st, into mask m, list cd and count cn; with a gate, the screen (not
-        the build) waits for the previous lane's screen."""
-        r.build(st)
-        if gate is not None:
-            gate.wait(st)
-        if args.alg1:
-            L.oss_screen_intervals(ch, r.handle, T, alg1_probes(), w.feat_mask, m, cd, cap, cn,
-                                   st)
-        elif args.moments:
-            tm = [L.oss_template_moments(t.pixels, t.rho, bit_depth=w.depth) for t in w.templates]
-            L.oss_screen_moments(ch, r.handle, tm, w.probes, MOM_TOL, 7, m, cd, cap, cn, st)
-        elif args.rings > 1:
-            L.oss_screen_rings(ch, r.handle, tfeat_rings(), w.probes, tol, w.feat_mask, m, cd,
-                               cap, cn, st)
-        else:
-            L.oss_screen(ch, r.handle, tfeat(), w.probes, tol, w.feat_mask, m, cd, cap, cn, st,
-                         batched=batched)
-        if gate is not None:
-            gate.record(st)
-
-    def make_step(batched):
-        return lambda: screen_step(ctx.handle, ref, stream, mask, cands, count, batched)
-
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -697,149 +945,34 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    extra = {}
-    if big:
-        ref.build(stream)
-        if not args.no_autotune:
-            tr = L.oss_autotune_batched(ctx.handle, ref.handle, tfeat(), w.probes, tol,
-                                        w.feat_mask, stream)
-            extra["autotune"] = {
-                "strip": tr.strip, "blocks_per_xcd": tr.blocks_per_xcd,
-                "bucket_radii": tr.bucket_radii, "ms": tr.ms,
-                "tried": [[tr.tried[i][0], tr.tried[i][1], tr.tried[i][2], tr.tried_ms[i]]
-                          for i in range(tr.n_tried)]}
-        # the per-template launches at their own best shape (strip 512,
-        # 32 / 64 / 128 blocks per XCD), then the batched shape again
-        tuned = [L.oss_ctx_get_option(ctx.handle, o)
-                 for o in (L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD)]
-        best = None
-        for blocks in (32, 64, 128):
-            L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_STRIP, 512)
-            L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_BLOCKS_PER_XCD, blocks)
-            plain_s, plain_prof = run_steps(make_step(False), max(1, args.steps // 4), 1, ctx, L,
-                                            torch)
-            if best is None or plain_s < best[0]:
-                best = (plain_s, plain_prof, blocks)
-        for o, v in zip((L.OSS_OPT_STAR_STRIP, L.OSS_OPT_STAR_BLOCKS_PER_XCD), tuned):
-            L.oss_ctx_set_option(ctx.handle, o, v)
-        plain_s, plain_prof, blocks = best
-        extra["plain_ms_per_step"] = plain_s * 1e3
-        extra["plain_shape"] = {"strip": 512, "blocks_per_xcd": blocks}
-        extra["plain_kernels"] = {k: v[1] / max(v[0], 1) for k, v in plain_prof.items()}
-    sec, prof = run_steps(make_step(big or args.rings > 1), args.steps, args.warmup, ctx, L,
-                          torch)
-
-    if args.alg1:
-        # one pixel-scale per (valid position, template, band)
-        bands = {(p.template_id, p.scale_id, p.r) for p in alg1_probes()}
-        ps = sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, _, r in bands)
+    if args.workload == 4:
+        print(json.dumps(run_serving(args)), flush=True)
+        return
+    if args.workload in (2, 3, 5):
+        out = run_fixed(args, args.workload, steps=args.steps, warmup=args.warmup,
+                        cpu_seconds=args.cpu_seconds,
+                        evaluate=args.evaluate == 1 or (args.evaluate < 0 and args.workload == 2),
+                        compare_plain=not args.no_plain)
     else:
-        ps = pixel_scales(w.H, w.W, w.probes)
-    value = ps / sec / 1e9
-    n = int(count.item())
-    if big:
-        # batched against per-template launches, one lane each
-        extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
-        extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
-    if lanes >= 2:
-        # the timed figures below are the lanes' run; the single lane's are kept
-        extra["single_lane"] = {
-            "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
-            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
-            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
-                        for k, v in prof.items()}}
-        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, lane_stream)
-        sec, prof, same = pipelined(args, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap,
-                                    big or args.rings > 1, screen_step, n, mask, cands)
-        extra["lanes_identical_to_single_lane"] = same
-        value = ps / sec / 1e9
-    eb = sum(b // 8 for _, b in ref.slots)  # table bytes per position, all quantities
-    staged = (ref.plane_bytes > 0 and len(ref.slots) > 1 and not args.moments
-              and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED) == 1
-              and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE) == 0)
-    abytes = algorithmic_bytes(w.H, w.W, T, 2 if w.depth > 8 else 1, eb)
-    abytes["star_batch"] = abytes["star_plain"]
-    abytes["star_moments"] = abytes["star_plain"]
-    kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
-            for k, v in prof.items()}
-    dom = max(prof, key=lambda k: prof[k][1])
-    avg_s = prof[dom][1] / prof[dom][0] / 1e3
-    achieved = abytes[dom] / avg_s / 1e9 if dom in abytes else None
-    roof = {
-        "kernel": dom,
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBPS if achieved else None,
-        "traffic": traffic_for(dom) if args.workload == 2 else None,
-        "algorithmic_bytes_per_launch": abytes.get(dom),
-        "avg_ms": avg_s * 1e3,
-    }
-    if dom in ("star_plain", "star_batch"):
-        # the same launch against the vector-memory path that actually bounds it
-        # staged lookups read the first quantity everywhere and the others
-        # only where it passes: only the first quantity's bytes are counted
-        per = ref.entry_bytes if staged else eb
-        lookups = lookup_pairs(w, dom == "star_batch", rings=args.rings) * 8 * per
-        roof["vector_l1"] = {"achieved": lookups / avg_s / 1e9, "peak": L1_PEAK_GBPS,
-                             "unit": "GB/s", "frac": lookups / avg_s / 1e9 / L1_PEAK_GBPS,
-                             "lookup_bytes_per_launch": lookups,
-                             "counted": ("first quantity only (staged lookups)" if staged
-                                         else "every quantity")}
-    for k in kern:
-        if k in abytes:
-            kern[k]["achieved_GBps"] = abytes[k] / (kern[k]["avg_ms"] / 1e3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "G pixel-scales/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {
-            "workload": WORKLOAD_TEXT[args.workload],
-            "H": w.H, "W": w.W, "radii": w.radii(), "templates": T, "probes": len(w.probes),
-            "tolerance_P_over_Q": [p / w.tol_Q for p in w.tol_P], "seed": args.seed,
-            "pixel_scales_per_step": ps,
-            "table_value_bits": ref.value_bits,
-            "table_entry_bytes": eb,
-            "table_layout": "planar" if ref.plane_bytes else "interleaved",
-            "star_strip": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STRIP),
-            "star_blocks_per_xcd": L.oss_ctx_get_option(ctx.handle,
-                                                        L.OSS_OPT_STAR_BLOCKS_PER_XCD),
-            "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
-            "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
-            "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
-            "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
-            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
-            "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
-            "launch": "batched" if (big or args.rings > 1) else "plain",
-            "lanes": lanes,
-            "serial_screens": bool(args.serial_screens),
-            "rings": args.rings,
-            "alg1": bool(args.alg1),
-            "moments": bool(args.moments),
-        },
-        "roofline": roof,
-        "kernels": kern,
-        "candidates": n,
-        "pruned_patch_pct": 100.0 * (1 - n / float(T * w.H * w.W)),
-    }
-    out.update(extra)
-    if args.evaluate == 1 or (args.evaluate < 0 and args.workload == 2):
-        out["evaluation"] = evaluate_regions(w, ctx, L, torch, dev, cands, count, cap)
-    if not args.no_cpu_baseline and not args.alg1 and not args.moments:
-        out["cpu_baseline"] = sampled_check(w, cands, n, cap, mask, args.cpu_seconds, args.rings)
-    ref.release()
-    ctx.close()
+        # the headline: workload 5 (the largest single-GPU configuration),
+        # then workload 2 and the serving loop, nested in the same line
+        out = run_fixed(args, 5, steps=args.steps, warmup=args.warmup,
+                        cpu_seconds=args.cpu_seconds, evaluate=args.evaluate == 1,
+                        compare_plain=not args.no_plain)
+        w2 = run_fixed(args, 2, steps=max(args.steps, 20), warmup=args.warmup,
+                       cpu_seconds=min(args.cpu_seconds, 5.0), evaluate=args.evaluate != 0)
+        out["workload_2"] = nested(w2, ("value", "unit", "ms_per_step", "config", "roofline",
+                                        "kernels", "single_lane", "candidates",
+                                        "pruned_patch_pct", "evaluation", "cpu_baseline",
+                                        "lanes_identical_to_single_lane"))
+        print("serving loop", file=sys.stderr, flush=True)
+        sv = run_serving(args)
+        out["serving"] = nested(sv, ("value", "unit", "ms_per_step", "config", "served",
+                                     "per_request_scheme", "offered_requests_per_s"))
+    if args.copy_peak_mb:
+        cp = copy_peak(torch, dev, args.copy_peak_mb)
+        out["copy_peak_GBps"] = cp["GBps"]
+        out["roofline"]["achievable_peak"] = cp
     print(json.dumps(out), flush=True)
 
 

@@ -20,13 +20,29 @@ def test_more_than_one_gpu_is_refused():
 
 def test_algorithmic_bytes():
     H, W, T = 64, 80, 3
-    a = bench.algorithmic_bytes(H, W, T, 1, 12)
+    a = bench.algorithmic_bytes(H, W, T, 1, 12, n_cand=7)
     # the star pass reads the tables once (three tables of (H+1)(W+1)
-    # entries) and writes the scale-bit words once; the builder reads the
-    # image once and writes the tables
-    assert a["star_plain"] == 3 * (H + 1) * (W + 1) * 12 + 4 * T * H * W
+    # entries) and writes the uint8 mask; the builder reads the image once
+    # and writes the tables; the list is 16 bytes per candidate.  The
+    # implementation's own scratch (scale-bit words, staged candidates) is
+    # not counted.
+    assert a["star_plain"] == 3 * (H + 1) * (W + 1) * 12 + T * H * W
+    assert a["star_batch"] == a["star_plain"]
     assert a["band_final"] == 3 * (H + 1) * (W + 1) * 12 + H * W
-    assert a["compact_count"] == 4 * T * H * W
+    assert a["compact_list"] == 16 * 7
+
+
+def test_batch_group_matches_header():
+    """The lookup count of a batched launch uses the library's group size."""
+    import re
+    src = open(os.path.join(ROOT, "paper_1707_05647_amd", "csrc", "oss_internal.h")).read()
+    assert int(re.search(r"BATCH_GROUP = (\d+);", src).group(1)) == bench.BATCH_GROUP
+    assert int(re.search(r"BATCH_GROUP_RINGS = (\d+);", src).group(1)) == bench.BATCH_GROUP_RINGS
+
+
+def test_default_line_is_the_headline_workload():
+    a = bench.parse_args([])
+    assert a.workload == 0 and a.gpus == 1
 
 
 def test_pixel_scales_count_valid_positions():
