@@ -252,6 +252,19 @@ OPTIONS = ("OSS_OPT_STAR_STRIP", "OSS_OPT_STAR_BLOCKS_PER_XCD", "OSS_OPT_STAR_LD
            "OSS_OPT_STAR_STAGED", "OSS_OPT_BUILD_STREAM")
 
 
+_LANE_STREAMS = []
+
+
+def lane_stream(torch, dev, i):
+    """Lane i's stream, created once per process and reused by every
+    workload: HIP maps streams onto a few hardware queues in turn, so fresh
+    streams for a later workload can share a queue (and serialise) with each
+    other."""
+    while len(_LANE_STREAMS) <= i:
+        _LANE_STREAMS.append(torch.cuda.Stream(device=dev))
+    return _LANE_STREAMS[i]
+
+
 def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, batched,
               screen_step, n, mask, cands):
     """The same steps over `n_lanes` lanes (contexts with the main context's
@@ -260,13 +273,15 @@ def pipelined(args, n_lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap, bat
     single-lane run's."""
     from paper_1707_05647_amd.screen import Context
     gate = ScreenGate(torch) if args.serial_screens else None
+    made = []
 
     def make_lane():
         c = Context(0)
         for o in OPTIONS:
             L.oss_ctx_set_option(c.handle, getattr(L, o),
                                  L.oss_ctx_get_option(ctx.handle, getattr(L, o)))
-        st = torch.cuda.Stream(device=dev)
+        st = lane_stream(torch, dev, len(made))
+        made.append(st)
         r = c.reference(img, ref_fm, w.depth, build=False, max_radius=max_r)
         m = torch.empty_like(mask)
         cd = torch.empty((cap, 4), dtype=torch.int32, device=dev)
@@ -599,7 +614,9 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
     stream = torch.cuda.current_stream()
     big = workload in (3, 5)
     print(f"workload {workload}: generating inputs", file=sys.stderr, flush=True)
-    w = make_workload(workload, args.seed, device=dev if big else None)
+    cache = (os.path.join(args.ref_cache, f"reference_w{workload}_s{args.seed}.npy")
+             if args.ref_cache and big else None)
+    w = make_workload(workload, args.seed, device=dev if big else None, ref_cache=cache)
     img = L.device_image(w.ref, dev)
     ctx = Context(0)
     if args.star_strip:
@@ -728,8 +745,16 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
             extra["plain_ms_per_step"] = plain_s * 1e3
             extra["plain_shape"] = {"strip": 512, "blocks_per_xcd": blocks}
             extra["plain_kernels"] = {k: v[1] / max(v[0], 1) for k, v in plain_prof.items()}
-    print(f"workload {workload}: timed steps, one lane", file=sys.stderr, flush=True)
-    sec, prof = run_steps(make_step(batched_path), steps, warmup, ctx, L, torch)
+    lanes = args.pipeline if args.pipeline >= 1 else 2
+    if args.lanes_only and lanes >= 2:
+        # one untimed step fills this context's outputs, which the lanes'
+        # results are compared with
+        make_step(batched_path)()
+        torch.cuda.synchronize()
+        sec, prof = None, {}
+    else:
+        print(f"workload {workload}: timed steps, one lane", file=sys.stderr, flush=True)
+        sec, prof = run_steps(make_step(batched_path), steps, warmup, ctx, L, torch)
 
     if args.alg1:
         # one pixel-scale per (valid position, template, band)
@@ -737,21 +762,22 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
         ps = sum(max(0, w.H - 2 * r) * max(0, w.W - 2 * r) for _, _, r in bands)
     else:
         ps = pixel_scales(w.H, w.W, w.probes)
-    value = ps / sec / 1e9
+    value = ps / sec / 1e9 if sec else None
     n = int(count.item())
     if n != n_probe:
         raise RuntimeError(f"candidate count changed between runs ({n_probe} -> {n})")
-    if big and compare_plain:
+    if big and compare_plain and sec:
         # batched against per-template launches, one lane each
         extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
         extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
-    if lanes >= 2:
+    if lanes >= 2 and sec:
         # the timed figures below are the lanes' run; the single lane's are kept
         extra["single_lane"] = {
             "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
             "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
                         for k, v in prof.items()}}
+    if lanes >= 2:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, lane_stream)
         print(f"workload {workload}: timed steps, {lanes} lanes", file=sys.stderr, flush=True)
         sub = argparse.Namespace(**vars(args))
@@ -787,7 +813,7 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
         "avg_ms": avg_s * 1e3,
         "timed_on": f"{lanes} lanes" if lanes >= 2 else "one lane",
     }
-    if lanes >= 2 and dom in extra["single_lane"]["kernels"]:
+    if "single_lane" in extra and dom in extra["single_lane"]["kernels"]:
         one = extra["single_lane"]["kernels"][dom]["avg_ms"] / 1e3
         roof["one_lane"] = {"avg_ms": one * 1e3, "achieved": abytes[dom] / one / 1e9,
                             "frac": abytes[dom] / one / 1e9 / HBM_PEAK_GBPS}
@@ -895,6 +921,9 @@ def parse_args(argv=None):
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched workloads: skip the per-template comparison")
+    ap.add_argument("--lanes-only", action="store_true",
+                    help="time only the multi-lane run (no one-lane steps; for traces whose "
+                         "launches should all be the timed configuration's)")
     ap.add_argument("--star-strip", type=int, default=0,
                     help="star kernel strip width (threads per block); 0 = library default")
     ap.add_argument("--star-blocks", type=int, default=0,
@@ -923,6 +952,11 @@ def parse_args(argv=None):
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first "
                          "(a reference kernel of known size for HBM byte counters)")
+    ap.add_argument("--ref-cache", default="",
+                    help="directory for the rendered reference of the batched workloads (loaded "
+                         "when present, written otherwise): a profiled run can skip rendering")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="render (and cache) the workload's inputs, then exit")
     ap.add_argument("--copy-peak-mb", type=int, default=4096,
                     help="size of the timed device copy that gives the achievable HBM rate "
                          "(0: skip)")
@@ -947,6 +981,13 @@ def main(argv=None):
         del src, dst
     if args.workload == 4:
         print(json.dumps(run_serving(args)), flush=True)
+        return
+    if args.gen_only:
+        from synth import make_workload
+        for wl in ((args.workload,) if args.workload in (2, 3, 5) else (5,)):
+            cache = (os.path.join(args.ref_cache, f"reference_w{wl}_s{args.seed}.npy")
+                     if args.ref_cache and wl in (3, 5) else None)
+            make_workload(wl, args.seed, device=dev if wl in (3, 5) else None, ref_cache=cache)
         return
     if args.workload in (2, 3, 5):
         out = run_fixed(args, args.workload, steps=args.steps, warmup=args.warmup,

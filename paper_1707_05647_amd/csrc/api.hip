@@ -152,8 +152,8 @@ int oss_ctx_destroy(oss_ctx *ctx)
     }
     if (ctx->bits)
         (void)hipFree(ctx->bits);
-    if (ctx->cws)
-        (void)hipFree(ctx->cws);
+    if (ctx->ews)
+        (void)hipFree(ctx->ews);
     if (ctx->rws)
         (void)hipFree(ctx->rws);
     delete ctx;
@@ -704,13 +704,25 @@ static int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_templat
     return OSS_OK;
 }
 
-int oss::screen_workspace(oss_ctx *ctx, int64_t n)
+int oss::screen_workspace(oss_ctx *ctx, int64_t n_tmpl, int H, int W, bool carry)
 {
-    int rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap,
-                  (size_t)n * sizeof(uint32_t));
-    if (rc != OSS_OK)
-        return rc;
-    return grow(&ctx->cws, &ctx->cws_cap, compact_workspace_bytes(n));
+    if (carry) {
+        int rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap,
+                      (size_t)n_tmpl * H * W * sizeof(uint32_t));
+        if (rc != OSS_OK)
+            return rc;
+    }
+    return grow(&ctx->ews, &ctx->ews_cap, emit_workspace_bytes(n_tmpl, H, W));
+}
+
+EmitOut oss::emit_out(oss_ctx *ctx, int64_t n_tmpl, int H, int W, void **scan_ws)
+{
+    EmitOut eo{};
+    emit_carve(ctx->ews, n_tmpl, H, W, &eo.seg_count, &eo.stage, scan_ws);
+    eo.H = H;
+    eo.W = W;
+    eo.n_chunks = (W + SEG_W - 1) / SEG_W;
+    return eo;
 }
 
 extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
@@ -732,8 +744,8 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     hipStream_t st = static_cast<hipStream_t>(stream);
     const BuildGeom &g = ref->geom;
     const int64_t hw = (int64_t)g.H * g.W;
-    const int64_t n = hw * n_tmpl;
-    rc = screen_workspace(ctx, n);
+    const int strip = ctx->star_strip;
+    rc = screen_workspace(ctx, n_tmpl, g.H, g.W, false);
     if (rc != OSS_OK)
         return rc;
     PlanSlot *slot = nullptr;
@@ -741,22 +753,30 @@ extern "C" int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_f
     if (rc != OSS_OK)
         return rc;
     const DevTemplatePlan *dplan = static_cast<const DevTemplatePlan *>(slot->dev);
+    void *scan_ws = nullptr;
+    const EmitOut all = emit_out(ctx, n_tmpl, g.H, g.W, &scan_ws);
+    const int64_t segs_t = (int64_t)g.H * all.n_chunks;
     for (int t = 0; t < n_tmpl; ++t) {
-        const StarSweep sw = make_sweep(g.H, g.W, ctx->star_strip, ctx->star_blocks_per_xcd);
+        const StarSweep sw = make_sweep(g.H, g.W, strip, ctx->star_blocks_per_xcd);
         int smax = 0, rmax = 0;
         for (int j = 0; j < plans[t].n_radii; ++j) {
             smax = std::max(smax, (int)plans[t].radii[j].s);
             rmax = std::max(rmax, (int)plans[t].radii[j].r);
         }
-        hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
-                                         ctx->bits + hw * t, sw, smax, rmax,
+        // template t's segments, staging slots and mask
+        EmitOut eo = all;
+        eo.mask = dev_mask ? dev_mask + hw * t : nullptr;
+        eo.seg_count = all.seg_count + segs_t * t;
+        eo.stage = all.stage + segs_t * SEG_W * t;
+        hipError_t e = launch_star_plain(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t, eo, sw,
+                                         smax, rmax,
                                          ctx->star_lds ? 1 : ctx->star_pipe ? 2 : ctx->star_staged ? 3 : 0, st,
                                          &ctx->prof);
         if (e != hipSuccess)
             return OSS_E_DEVICE;
     }
-    hipError_t e = launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap,
-                                  dev_count, ctx->cws, st, &ctx->prof);
+    hipError_t e = launch_list(all.seg_count, all.stage, n_tmpl, g.H, g.W, dev_list, list_cap,
+                               dev_count, scan_ws, st, &ctx->prof);
     if (e != hipSuccess)
         return OSS_E_DEVICE;
     if (hipEventRecord(slot->ev, st) != hipSuccess)
@@ -843,7 +863,7 @@ static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
         int j0 = rad_begin;
         do {
             const int j1 = std::min(rad_end, j0 + step);
-            bp.passes.push_back({gi, j0, j1, j0 == rad_begin ? 1 : 0});
+            bp.passes.push_back({gi, j0, j1, j0 == rad_begin ? 1 : 0, j1 == rad_end ? 1 : 0, 0});
             j0 = j1;
         } while (j0 < rad_end);
     }
@@ -864,6 +884,7 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
     if (n_rings < 1 || n_rings > MAX_RINGS)
         return OSS_E_ARG;
     bp.rings = n_rings;
+    bp.n_tmpl = n_tmpl;
     if (n_rings > 1)
         bucket = 0;  // the ring tests of a probe combine in registers: one pass
     std::vector<int> count(n_tmpl, 0);
@@ -916,6 +937,7 @@ static int make_interval_plan(const oss_ref *ref, int32_t n_tmpl, const oss_inte
 {
     int slot_of[3];
     slots_of(ref->feat_mask, slot_of);
+    bp.n_tmpl = n_tmpl;
     std::vector<std::vector<PlanEntry>> per(n_tmpl);
     for (int i = 0; i < n_probes; ++i) {
         const oss_interval_probe &p = probes[i];
@@ -947,16 +969,19 @@ static int make_interval_plan(const oss_ref *ref, int32_t n_tmpl, const oss_inte
 }
 
 // Pack the plan into one upload; returns device pointers into the slot.
-static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t st,
-                             BatchDevPlan *dev, PlanSlot **slot)
+static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, uint8_t *const *masks,
+                             hipStream_t st, BatchDevPlan *dev, PlanSlot **slot)
 {
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t o_pass = 0;
+    const size_t o_mask = 0;
+    const size_t o_pass = al(o_mask + (size_t)std::max(1, bp.n_tmpl) * sizeof(uint8_t *));
     const size_t o_grp = al(o_pass + bp.passes.size() * sizeof(DevBatchPass));
     const size_t o_rad = al(o_grp + bp.groups.size() * sizeof(DevBatchGroup));
     const size_t o_prb = al(o_rad + bp.radii.size() * sizeof(DevBatchRadius));
     const size_t total = al(o_prb + std::max<size_t>(1, bp.probes.size()) * sizeof(DevBatchProbe));
     std::vector<char> buf(total, 0);
+    if (masks)
+        std::memcpy(buf.data() + o_mask, masks, (size_t)bp.n_tmpl * sizeof(uint8_t *));
     std::memcpy(buf.data() + o_pass, bp.passes.data(), bp.passes.size() * sizeof(DevBatchPass));
     std::memcpy(buf.data() + o_grp, bp.groups.data(), bp.groups.size() * sizeof(DevBatchGroup));
     std::memcpy(buf.data() + o_rad, bp.radii.data(), bp.radii.size() * sizeof(DevBatchRadius));
@@ -965,6 +990,7 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t 
     if (rc != OSS_OK)
         return rc;
     const char *d = static_cast<const char *>((*slot)->dev);
+    dev->mask_of = masks ? reinterpret_cast<uint8_t *const *>(d + o_mask) : nullptr;
     dev->passes = reinterpret_cast<const DevBatchPass *>(d + o_pass);
     dev->n_passes = (int)bp.passes.size();
     dev->groups = reinterpret_cast<const DevBatchGroup *>(d + o_grp);
@@ -975,19 +1001,68 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, hipStream_t 
     return OSS_OK;
 }
 
-// The batched star pass alone (scale bits into the context workspace).
+bool oss::plan_carries(const BatchHostPlan &bp)
+{
+    for (const DevBatchPass &p : bp.passes)
+        if (!p.last)
+            return true;
+    return false;
+}
+
+// The batched star pass alone (mask, segment counts and staged candidates
+// into the context's emission workspace).
 int oss::batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip,
-                    int blocks, hipStream_t st, PlanSlot **slot)
+                    int blocks, uint8_t *const *masks, hipStream_t st, PlanSlot **slot)
 {
     BatchDevPlan dev{};
-    int rc = upload_batch_plan(ctx, bp, st, &dev, slot);
+    int rc = upload_batch_plan(ctx, bp, masks, st, &dev, slot);
     if (rc != OSS_OK)
         return rc;
     const BuildGeom &g = ref->geom;
     const StarSweep sw = make_sweep(g.H, g.W, strip, blocks);
-    if (launch_star_batch(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dev, ctx->bits, sw,
+    void *scan_ws = nullptr;
+    EmitOut eo = emit_out(ctx, bp.n_tmpl, g.H, g.W, &scan_ws);
+    eo.dense = plan_carries(bp) ? ctx->bits : nullptr;
+    if (launch_star_batch(g, ref->bb.L, ref->bb.R, ref->bb.Rp, dev, eo, sw,
                           ctx->star_staged != 0, st, &ctx->prof) != hipSuccess)
         return OSS_E_DEVICE;
+    return OSS_OK;
+}
+
+// Per-template mask pointers of a screen's [n_tmpl][H][W] mask (empty: none).
+static std::vector<uint8_t *> mask_ptrs(uint8_t *dev_mask, int32_t n_tmpl, int64_t hw)
+{
+    std::vector<uint8_t *> m;
+    if (dev_mask)
+        for (int t = 0; t < n_tmpl; ++t)
+            m.push_back(dev_mask + hw * t);
+    return m;
+}
+
+// Batched star pass + list for one screen over ctx's workspaces.
+static int batched_screen(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp,
+                          uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
+                          int64_t *dev_count, hipStream_t st)
+{
+    const BuildGeom &g = ref->geom;
+    const int strip = ctx->star_strip;
+    int rc = screen_workspace(ctx, bp.n_tmpl, g.H, g.W, plan_carries(bp));
+    if (rc != OSS_OK)
+        return rc;
+    const std::vector<uint8_t *> masks = mask_ptrs(dev_mask, bp.n_tmpl, (int64_t)g.H * g.W);
+    PlanSlot *slot = nullptr;
+    rc = batch_star(ctx, ref, bp, strip, ctx->star_blocks_per_xcd,
+                    masks.empty() ? nullptr : masks.data(), st, &slot);
+    if (rc != OSS_OK)
+        return rc;
+    void *scan_ws = nullptr;
+    const EmitOut eo = emit_out(ctx, bp.n_tmpl, g.H, g.W, &scan_ws);
+    if (launch_list(eo.seg_count, eo.stage, bp.n_tmpl, g.H, g.W, dev_list, list_cap, dev_count,
+                    scan_ws, st, &ctx->prof) != hipSuccess)
+        return OSS_E_DEVICE;
+    if (hipEventRecord(slot->ev, st) != hipSuccess)
+        return OSS_E_DEVICE;
+    slot->used = true;
     return OSS_OK;
 }
 
@@ -1011,23 +1086,8 @@ extern "C" int oss_screen_batched(oss_ctx *ctx, const oss_ref *ref,
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
         return OSS_E_DEVICE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const BuildGeom &g = ref->geom;
-    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
-    rc = screen_workspace(ctx, n);
-    if (rc != OSS_OK)
-        return rc;
-    PlanSlot *slot = nullptr;
-    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
-    if (rc != OSS_OK)
-        return rc;
-    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
-                       ctx->cws, st, &ctx->prof) != hipSuccess)
-        return OSS_E_DEVICE;
-    if (hipEventRecord(slot->ev, st) != hipSuccess)
-        return OSS_E_DEVICE;
-    slot->used = true;
-    return OSS_OK;
+    return batched_screen(ctx, ref, bp, dev_mask, dev_list, list_cap, dev_count,
+                          static_cast<hipStream_t>(stream));
 }
 
 extern "C" int oss_screen_rings(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
@@ -1062,23 +1122,8 @@ extern "C" int oss_screen_rings(oss_ctx *ctx, const oss_ref *ref, const oss_temp
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
         return OSS_E_DEVICE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const BuildGeom &g = ref->geom;
-    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
-    rc = screen_workspace(ctx, n);
-    if (rc != OSS_OK)
-        return rc;
-    PlanSlot *slot = nullptr;
-    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
-    if (rc != OSS_OK)
-        return rc;
-    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
-                       ctx->cws, st, &ctx->prof) != hipSuccess)
-        return OSS_E_DEVICE;
-    if (hipEventRecord(slot->ev, st) != hipSuccess)
-        return OSS_E_DEVICE;
-    slot->used = true;
-    return OSS_OK;
+    return batched_screen(ctx, ref, bp, dev_mask, dev_list, list_cap, dev_count,
+                          static_cast<hipStream_t>(stream));
 }
 
 // Empirical search over the batched launch's shape: each candidate (strip
@@ -1102,9 +1147,6 @@ extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
         return OSS_E_DEVICE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const BuildGeom &g = ref->geom;
-    rc = screen_workspace(ctx, (int64_t)g.H * g.W * n_tmpl);
-    if (rc != OSS_OK)
-        return rc;
     // distinct radii per group bound the useful bucket sizes
     const std::vector<oss_tolerance> tols(n_tmpl, *tol);
     const std::vector<uint32_t> fms(n_tmpl, feat_mask);
@@ -1135,16 +1177,19 @@ extern "C" int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref,
         if (rc != OSS_OK)
             break;
         for (int sp : strips) {
+            rc = screen_workspace(ctx, n_tmpl, g.H, g.W, plan_carries(bp));
+            if (rc != OSS_OK)
+                break;
             for (int bl : blocks) {
                 PlanSlot *slot = nullptr;
-                rc = batch_star(ctx, ref, bp, sp, bl, st, &slot);  // warm-up
+                rc = batch_star(ctx, ref, bp, sp, bl, nullptr, st, &slot);  // warm-up
                 if (rc != OSS_OK)
                     break;
                 if (hipEventRecord(e0, st) != hipSuccess) {
                     rc = OSS_E_DEVICE;
                     break;
                 }
-                rc = batch_star(ctx, ref, bp, sp, bl, st, &slot);
+                rc = batch_star(ctx, ref, bp, sp, bl, nullptr, st, &slot);
                 if (rc != OSS_OK)
                     break;
                 float ms = 0.f;
@@ -1230,7 +1275,7 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
     const size_t tb = ref_layout(g, off);
     const size_t o_ind = (tb + 255) / 256 * 256;
     const size_t o_hit = o_ind + ((size_t)Hp * Wp + 255) / 256 * 256;
-    const size_t total = o_hit + (size_t)Hp * Wp * sizeof(uint32_t);
+    const size_t total = o_hit + (size_t)Hp * Wp;
     int rc = grow(&ctx->rws, &ctx->rws_cap, total);
     if (rc != OSS_OK)
         return rc;
@@ -1247,7 +1292,7 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
     bb.c_AD = m + off[A_CAD];
     bb.c_D = m + off[A_CD];
     uint8_t *ind = reinterpret_cast<uint8_t *>(m + o_ind);
-    uint32_t *hit = reinterpret_cast<uint32_t *>(m + o_hit);
+    uint8_t *hit = reinterpret_cast<uint8_t *>(m + o_hit);
     const StarSweep sw = make_sweep(Hp, Wp, ctx->star_strip, ctx->star_blocks_per_xcd);
     for (const auto &grp : groups) {
         const int t = grp.first.first, r = grp.first.second;
@@ -1274,8 +1319,14 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
         rc = upload_plan(ctx, &pl, sizeof(pl), st, &slot);
         if (rc != OSS_OK)
             return rc;
+        // the star pass's mask alone: hit[y][x] = 1 where the star holds a candidate
+        EmitOut eo{};
+        eo.mask = hit;
+        eo.H = Hp;
+        eo.W = Wp;
+        eo.n_chunks = (Wp + SEG_W - 1) / SEG_W;
         if (launch_star_plain(g, bb.L, bb.R, bb.Rp, static_cast<const DevTemplatePlan *>(slot->dev),
-                              hit, sw, 0, 0, ctx->star_pipe ? 2 : 0, st, &ctx->prof) !=
+                              eo, sw, 0, 0, ctx->star_pipe ? 2 : 0, st, &ctx->prof) !=
                 hipSuccess ||
             hipEventRecord(slot->ev, st) != hipSuccess)
             return OSS_E_DEVICE;
@@ -1308,23 +1359,8 @@ extern "C" int oss_screen_intervals(oss_ctx *ctx, const oss_ref *ref, int32_t n_
         return rc;
     if (hipSetDevice(ctx->device) != hipSuccess)
         return OSS_E_DEVICE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const BuildGeom &g = ref->geom;
-    const int64_t n = (int64_t)g.H * g.W * n_tmpl;
-    rc = screen_workspace(ctx, n);
-    if (rc != OSS_OK)
-        return rc;
-    PlanSlot *slot = nullptr;
-    rc = batch_star(ctx, ref, bp, ctx->star_strip, ctx->star_blocks_per_xcd, st, &slot);
-    if (rc != OSS_OK)
-        return rc;
-    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
-                       ctx->cws, st, &ctx->prof) != hipSuccess)
-        return OSS_E_DEVICE;
-    if (hipEventRecord(slot->ev, st) != hipSuccess)
-        return OSS_E_DEVICE;
-    slot->used = true;
-    return OSS_OK;
+    return batched_screen(ctx, ref, bp, dev_mask, dev_list, list_cap, dev_count,
+                          static_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -1699,7 +1735,8 @@ extern "C" int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_te
     hipStream_t st = static_cast<hipStream_t>(stream);
     const BuildGeom &g = ref->geom;
     const int64_t hw = (int64_t)g.H * g.W;
-    int rc = screen_workspace(ctx, hw * n_tmpl);
+    const int strip = ctx->star_strip;
+    int rc = screen_workspace(ctx, n_tmpl, g.H, g.W, false);
     if (rc != OSS_OK)
         return rc;
     PlanSlot *slot = nullptr;
@@ -1707,13 +1744,21 @@ extern "C" int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_te
     if (rc != OSS_OK)
         return rc;
     const DevMomPlan *dplan = static_cast<const DevMomPlan *>(slot->dev);
-    const StarSweep sw = make_sweep(g.H, g.W, ctx->star_strip, ctx->star_blocks_per_xcd);
-    for (int t = 0; t < n_tmpl; ++t)
+    const StarSweep sw = make_sweep(g.H, g.W, strip, ctx->star_blocks_per_xcd);
+    void *scan_ws = nullptr;
+    const EmitOut all = emit_out(ctx, n_tmpl, g.H, g.W, &scan_ws);
+    const int64_t segs_t = (int64_t)g.H * all.n_chunks;
+    for (int t = 0; t < n_tmpl; ++t) {
+        EmitOut eo = all;
+        eo.mask = dev_mask ? dev_mask + hw * t : nullptr;
+        eo.seg_count = all.seg_count + segs_t * t;
+        eo.stage = all.stage + segs_t * SEG_W * t;
         if (launch_star_moments(g, ref->feat_mask, ref->bb.L, ref->bb.R, ref->bb.Rp, dplan + t,
-                                ctx->bits + hw * t, sw, st, &ctx->prof) != hipSuccess)
+                                eo, sw, st, &ctx->prof) != hipSuccess)
             return OSS_E_DEVICE;
-    if (launch_compact(ctx->bits, n_tmpl, g.H, g.W, dev_mask, dev_list, list_cap, dev_count,
-                       ctx->cws, st, &ctx->prof) != hipSuccess)
+    }
+    if (launch_list(all.seg_count, all.stage, n_tmpl, g.H, g.W, dev_list, list_cap, dev_count,
+                    scan_ws, st, &ctx->prof) != hipSuccess)
         return OSS_E_DEVICE;
     if (hipEventRecord(slot->ev, st) != hipSuccess)
         return OSS_E_DEVICE;

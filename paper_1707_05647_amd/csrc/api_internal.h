@@ -24,10 +24,10 @@ constexpr int NSLOTS = 4;
 
 struct oss_ctx {
     int device = 0;
-    uint32_t *bits = nullptr;  // scale-bit words, n_tmpl * H * W
-    size_t bits_cap = 0;       // bytes
-    void *cws = nullptr;       // compaction workspace
-    size_t cws_cap = 0;        // bytes
+    void *ews = nullptr;       // emission workspace: segment counts, staged candidates, scan
+    size_t ews_cap = 0;        // bytes
+    uint32_t *bits = nullptr;  // scale-bit words n_tmpl * H * W, only for batched groups
+    size_t bits_cap = 0;       // that span several passes (bytes)
     oss::PlanSlot slots[oss::NSLOTS];
     int next_slot = 0;
     oss::Profiler prof;
@@ -60,6 +60,7 @@ namespace oss {
 // most BATCH_GROUP, each group's probes sorted by reference radius, passes
 // over runs of at most `bucket` distinct radii.
 struct BatchHostPlan {
+    int n_tmpl = 0;
     std::vector<DevBatchPass> passes;
     std::vector<DevBatchGroup> groups;
     std::vector<DevBatchRadius> radii;
@@ -77,10 +78,16 @@ int make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n
                     const oss_probe *probes, int32_t n_probes, const oss_tolerance *tols,
                     const uint32_t *fms, int bucket, BatchHostPlan &bp, int n_rings = 1);
 
-// Upload the plan and launch the batched star pass into ctx->bits on `st`;
-// *slot is the plan slot to mark used once an event follows the launch.
+// Upload the plan and launch the batched star pass on `st`: the mask of
+// template t goes to masks[t] (masks null, or an entry null: no mask), the
+// segment counts and staged candidates to ctx's emission workspace, which
+// must have been grown for bp.n_tmpl templates (screen_workspace); *slot is the plan slot to mark used once an event
+// follows the launch.
 int batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int strip, int blocks,
-               hipStream_t st, PlanSlot **slot);
+               uint8_t *const *masks, hipStream_t st, PlanSlot **slot);
+
+// Passes of the plan that carry scale bits to a later pass (need ctx->bits).
+bool plan_carries(const BatchHostPlan &bp);
 
 // Image descriptor valid (sizes, dtype, depth, pitch).
 bool desc_ok(const oss_image_desc *d);
@@ -88,7 +95,12 @@ bool desc_ok(const oss_image_desc *d);
 // int64 table accumulation cannot overflow for this image and feature set.
 bool overflow_ok(const oss_image_desc *d, uint32_t fm);
 
-// Grow ctx's scale-bit and compaction workspaces to n = n_tmpl * H * W words.
-int screen_workspace(oss_ctx *ctx, int64_t n);
+// Grow ctx's emission workspace for n_tmpl templates of H x W, and with
+// `carry` its scale-bit words to n_tmpl * H * W.
+int screen_workspace(oss_ctx *ctx, int64_t n_tmpl, int H, int W, bool carry);
+
+// Carve ctx's emission workspace (grown by screen_workspace) for n_tmpl
+// templates: EmitOut fields seg_count / stage / geometry, and the scan area.
+EmitOut emit_out(oss_ctx *ctx, int64_t n_tmpl, int H, int W, void **scan_ws);
 
 }  // namespace oss

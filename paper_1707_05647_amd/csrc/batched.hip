@@ -21,276 +21,58 @@
 // full sweep of the image with the plain kernel's persistent XCD-aware strip
 // schedule.  A bucket of nearby radii only touches table rows near y +- r
 // for its radii, which keeps an XCD's L2 footprint small when the radius
-// range is wide.  The first pass of a group writes the group's scale-bit
-// words; later passes OR into them.  Every pass assigns the same positions to
-// the same block and thread, so each word is only ever read and written by
-// one thread, in pass order.
-#include "star_common.h"
+// range is wide.  A group with several passes carries its scale bits from
+// pass to pass in scale-bit words (the first pass writes them, later passes
+// OR into them); every pass assigns the same positions to the same block and
+// thread, so each word is only ever read and written by one thread, in pass
+// order.  The group's last pass (the only one, without buckets) emits the
+// final bits: the mask, the segment counts and the staged candidates, from
+// which the list pass builds the candidate list.
+#include "batched_kernel.h"
 
 namespace oss {
 
-// STAGED (planar layouts): per radius the wave first looks up the first
-// quantity alone and tests it against the hull; the other quantities are
-// looked up only where it lies inside (the plain screen's staged form).
-
-template <typename Tab, int MT, bool RINGS, bool STAGED>
-__global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
-    const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
-    int64_t pitch_e, int64_t plane, int H, int W, const DevBatchPass *__restrict__ passes,
-    int n_passes,
-    const DevBatchGroup *__restrict__ groups, const DevBatchRadius *__restrict__ radii,
-    const DevBatchProbe *__restrict__ probes, uint32_t *__restrict__ bits, StarSweep sw)
-{
-    constexpr int NQ = Tab::NQ;
-    constexpr int64_t ES = Tab::ES;
-    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int units = (sw.n_units - xcd + 7) / 8;
-    const int items = units * sw.rows_per_part;
-    const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
-    const int64_t row_bytes = pitch_e * ES;
-    const int64_t hw = (int64_t)H * W;
-    for (int ip = 0; ip < n_passes; ++ip) {
-        const DevBatchPass ps = passes[ip];
-        const DevBatchGroup *grp = groups + ps.group;
-        const int nt = grp->n_t;
-        for (int it = j; it < items; it += sw.blocks_per_xcd) {
-            int y, x0;
-            sweep_item(sw, xcd, it, (int)blockDim.x, &y, &x0);
-            if (y >= H)
-                continue;
-            const int x = x0 + threadIdx.x;
-            const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
-            const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
-            const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
-            // Scale bits per template slot: whose own star passes (acc) and
-            // which a central star fails (fail).  An array indexed by the
-            // wave-uniform slot stays in registers up to 32 entries, so a
-            // group of 64 (no rings) keeps a second half, picked by a
-            // uniform branch.
-            static_assert(!RINGS || MT <= 32, "groups with rings hold at most 32 templates");
-            uint32_t acc[MT > 32 ? 32 : MT];
-            uint32_t acc_hi[MT > 32 ? MT - 32 : 1];
-            uint32_t fail[RINGS ? MT : 1];
-#pragma unroll
-            for (int t = 0; t < (MT > 32 ? 32 : MT); ++t) {
-                acc[t] = 0;
-                if constexpr (RINGS)
-                    fail[t] = 0;
-            }
-#pragma unroll
-            for (int t = 0; t < (MT > 32 ? MT - 32 : 1); ++t)
-                acc_hi[t] = 0;
-            for (int jr = ps.j0; jr < ps.j1; ++jr) {
-                const DevBatchRadius &rd = radii[jr];
-                const int r = rd.r, s = rd.s;
-                if (y < r || y > H - 1 - r)
-                    continue;
-                const bool xv = x >= r && x <= W - 1 - r;
-                if constexpr (RINGS) {
-                    // skip the radius where every probe it serves has failed a
-                    // central star already (its bit is then 0 whatever this
-                    // radius gives); radii ascend, so a probe's central stars,
-                    // smaller than its own, come first
-                    bool need = false;
-                    if (xv)
-                        for (int p = rd.first; p < rd.first + rd.count; ++p) {
-                            const DevBatchProbe &pr = probes[p];
-                            need = need | !((fail[pr.t] >> pr.k) & 1u);
-                        }
-                    if (__builtin_amdgcn_ballot_w64(need) == 0)
-                        continue;
-                }
-                // a valid position outside the radius' hull fails every entry
-                // of the radius: central-star entries record that failure
-                auto fail_all = [&]() {
-                    if constexpr (RINGS) {
-                        if (xv)
-                            for (int p = rd.first; p < rd.first + rd.count; ++p) {
-                                const DevBatchProbe &pr = probes[p];
-                                if (pr.ring)
-                                    fail[pr.t] |= 1u << pr.k;
-                            }
-                    }
-                };
-                int64_t F[NQ];
-                if constexpr (STAGED && Tab::STAGE && NQ > 1) {
-                    constexpr int C = Tab::C;
-                    const StarAddr ad = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
-                    bool in_c = false;
-                    if (xv) {
-                        F[C] = star_sum_c<Tab>(ad, plane);
-                        in_c = (F[C] >= rd.lo[C]) & (F[C] <= rd.hi[C]);
-                    }
-                    if (__builtin_amdgcn_ballot_w64(in_c) == 0) {
-                        fail_all();
-                        continue;
-                    }
-                    if (in_c)
-                        star_sums_rest<Tab>(ad, plane, F);
-                    bool in = in_c;
-                    if (in_c) {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
-                    }
-                    if (__builtin_amdgcn_ballot_w64(in) == 0 || !in) {
-                        fail_all();
-                        continue;
-                    }
-                } else {
-                    bool in = xv;
-                    if (xv) {
-                        star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);
-                    }
-                    // skip the probe loop when no lane of the wave lies in the hull
-                    if (__builtin_amdgcn_ballot_w64(in) == 0 || !in) {
-                        fail_all();
-                        continue;
-                    }
-                }
-                {
-                    for (int p = rd.first; p < rd.first + rd.count; ++p) {
-                        const DevBatchProbe pr = probes[p];
-                        bool pass = true;
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
-                        const uint32_t bit = pass ? (1u << pr.k) : 0u;
-                        if constexpr (RINGS) {
-                            if (pr.ring)
-                                fail[pr.t] |= pass ? 0u : (1u << pr.k);
-                            else
-                                acc[pr.t] |= bit;
-                        } else if constexpr (MT > 32) {
-                            if (pr.t < 32)
-                                acc[pr.t] |= bit;
-                            else
-                                acc_hi[pr.t - 32] |= bit;
-                        } else {
-                            acc[pr.t] |= bit;
-                        }
-                    }
-                }
-            }
-            if (x < W) {
-#pragma unroll
-                for (int t = 0; t < MT; ++t) {
-                    if (t < nt) {
-                        uint32_t *w = bits + (int64_t)grp->tmap[t] * hw + (int64_t)y * W + x;
-                        uint32_t v = t < 32 ? acc[t < 32 ? t : 0] : acc_hi[t >= 32 ? t - 32 : 0];
-                        if constexpr (RINGS)
-                            v &= ~fail[t];  // one pass per group: final here
-                        *w = ps.first ? v : (*w | v);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <typename Tab, bool STAGED>
-static void batch_launch_s(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                           const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                           hipStream_t st)
-{
-    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
-#define OSS_BATCH_LAUNCH(MT, RINGS)                                                               \
-    hipLaunchKernelGGL((star_batch_kernel<Tab, MT, RINGS, STAGED>), grid, block, 0, st, L, R, Rp, \
-                       g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, \
-                       bp.probes, bits, sw)
-    if (bp.rings > 1) {
-        if (bp.max_group <= 8)
-            OSS_BATCH_LAUNCH(8, true);
-        else
-            OSS_BATCH_LAUNCH(32, true);
-    } else if (bp.max_group <= 8) {
-        OSS_BATCH_LAUNCH(8, false);
-    } else if (bp.max_group <= 16) {
-        OSS_BATCH_LAUNCH(16, false);
-    } else if (bp.max_group <= 32) {
-        OSS_BATCH_LAUNCH(32, false);
-    } else {
-        OSS_BATCH_LAUNCH(64, false);
-    }
-#undef OSS_BATCH_LAUNCH
-}
-
-template <typename Tab>
-static void batch_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                         const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw, bool staged,
-                         hipStream_t st)
-{
-    if (staged && Tab::STAGE)
-        batch_launch_s<Tab, true>(g, L, R, Rp, bp, bits, sw, st);
-    else
-        batch_launch_s<Tab, false>(g, L, R, Rp, bp, bits, sw, st);
-}
-
-template <typename T>
-static hipError_t batch_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                          const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
-                          bool staged, hipStream_t st)
-{
-    if (g.planar) {
-        switch (g.nq) {
-        case 1: batch_launch<TabP<T, 1>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-        case 2: batch_launch<TabP<T, 2>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-        case 3: batch_launch<TabP<T, 3>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-        default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (g.nq) {
-    case 1: batch_launch<TabU<T, 1>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-    case 2: batch_launch<TabU<T, 2>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-    case 3: batch_launch<TabU<T, 3>>(g, L, R, Rp, bp, bits, sw, staged, st); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-static hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                            const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
+                            const BatchDevPlan &bp, const EmitOut &eo, const StarSweep &sw,
                             bool staged, hipStream_t st)
 {
     if (g.planar) {
         if (g.nq == 3 && g.sqi == 1)
-            batch_launch<TabPS<3, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+            batch_launch<TabPS<3, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);
         else if (g.nq == 2 && g.sqi == 1)
-            batch_launch<TabPS<2, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+            batch_launch<TabPS<2, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);
         else if (g.nq == 2 && g.sqi == 0)
-            batch_launch<TabPS<2, 0>>(g, L, R, Rp, bp, bits, sw, staged, st);
+            batch_launch<TabPS<2, 0>>(g, L, R, Rp, bp, eo, sw, staged, st);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
     }
     if (g.nq == 3 && g.sqi == 1)
-        batch_launch<TabMix<3, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        batch_launch<TabMix<3, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);
     else if (g.nq == 2 && g.sqi == 1)
-        batch_launch<TabMix<2, 1>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        batch_launch<TabMix<2, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);
     else if (g.nq == 2 && g.sqi == 0)
-        batch_launch<TabMix<2, 0>>(g, L, R, Rp, bp, bits, sw, staged, st);
+        batch_launch<TabMix<2, 0>>(g, L, R, Rp, bp, eo, sw, staged, st);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                             const BatchDevPlan &bp, const EmitOut &eo, const StarSweep &sw,
                              bool staged, hipStream_t stream, Profiler *prof)
 {
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
         bp.max_group > (bp.rings > 1 ? BATCH_GROUP_RINGS : BATCH_GROUP))
         return hipErrorInvalidValue;
+    if (!emit_ok(eo, g))
+        return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_BATCH, stream);
     if (g.sqi >= 0)
-        return batch_mix(g, L, R, Rp, bp, bits, sw, staged, stream);
+        return batch_mix(g, L, R, Rp, bp, eo, sw, staged, stream);
     if (g.ebytes == 4)
-        return batch_t<uint32_t>(g, L, R, Rp, bp, bits, sw, staged, stream);
-    return batch_t<uint64_t>(g, L, R, Rp, bp, bits, sw, staged, stream);
+        return batch_p32(g, L, R, Rp, bp, eo, sw, staged, stream);
+    return batch_p64(g, L, R, Rp, bp, eo, sw, staged, stream);
 }
 
 }  // namespace oss

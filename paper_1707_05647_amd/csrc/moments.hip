@@ -26,8 +26,8 @@ __device__ __forceinline__ int64_t sext(uint64_t v) { return (int64_t)v; }
 template <typename T, unsigned FM, bool PLANAR>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_moments_kernel(
     const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
-    int64_t plane, int H, int W, const DevMomPlan *__restrict__ plan,
-    uint32_t *__restrict__ bits, StarSweep sw)
+    int64_t plane, int H, int W, const DevMomPlan *__restrict__ plan, EmitOut eo,
+    StarSweep sw)
 {
     constexpr bool HAS_SQ = (FM & OSS_F_SQ) != 0;
     constexpr int NQ = HAS_SQ ? 4 : 3;
@@ -126,14 +126,14 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_moments_kernel(
                 acc |= pass ? (1u << pr.k) : 0u;
             }
         }
-        if (x < W)
-            bits[(int64_t)y * W + x] = acc;
+        emit_row<1>(eo, 1, y, x, [&](int) { return acc; }, [](int) { return 0; },
+                    [&](int) { return eo.mask; });
     }
 }
 
 template <typename T>
 static hipError_t moments_t(const BuildGeom &g, uint32_t fm, const void *L, const void *R,
-                            const void *Rp, const DevMomPlan *plan, uint32_t *bits,
+                            const void *Rp, const DevMomPlan *plan, const EmitOut &eo,
                             const StarSweep &sw, hipStream_t st)
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
@@ -142,7 +142,7 @@ static hipError_t moments_t(const BuildGeom &g, uint32_t fm, const void *L, cons
     constexpr unsigned F3 = OSS_F_SUM | OSS_F_MOMENTS, F4 = OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS;
 #define OSS_MOM_LAUNCH(FMV, PL)                                                                   \
     hipLaunchKernelGGL((star_moments_kernel<T, FMV, PL>), grid, block, 0, st, l, r, rp, g.pitch_e, \
-                       g.plane, g.H, g.W, plan, bits, sw)
+                       g.plane, g.H, g.W, plan, eo, sw)
     if (fm == F3 && g.planar)
         OSS_MOM_LAUNCH(F3, true);
     else if (fm == F3)
@@ -158,16 +158,18 @@ static hipError_t moments_t(const BuildGeom &g, uint32_t fm, const void *L, cons
 }
 
 hipError_t launch_star_moments(const BuildGeom &g, uint32_t fm, const void *L, const void *R,
-                               const void *Rp, const DevMomPlan *plan, uint32_t *bits,
+                               const void *Rp, const DevMomPlan *plan, const EmitOut &eo,
                                const StarSweep &sw, hipStream_t stream, Profiler *prof)
 {
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1 ||
         g.sqi >= 0)
         return hipErrorInvalidValue;
+    if (!emit_ok(eo, g))
+        return hipErrorInvalidValue;
     ProfScope ps(prof, K_STAR_MOM, stream);
     if (g.ebytes == 4)
-        return moments_t<uint32_t>(g, fm, L, R, Rp, plan, bits, sw, stream);
-    return moments_t<uint64_t>(g, fm, L, R, Rp, plan, bits, sw, stream);
+        return moments_t<uint32_t>(g, fm, L, R, Rp, plan, eo, sw, stream);
+    return moments_t<uint64_t>(g, fm, L, R, Rp, plan, eo, sw, stream);
 }
 
 }  // namespace oss

@@ -113,7 +113,10 @@ struct DevBatchGroup {
 struct DevBatchPass {
     int32_t group;
     int32_t j0, j1;  // radii [j0, j1) of the global radius array
-    int32_t first;   // 1: write the group's scale bits, 0: OR into them
+    int32_t first;   // 1: the group's first pass (nothing carried in)
+    int32_t last;    // 1: the group's last pass (emits the mask, counts and candidates);
+                     // 0: stores the scale-bit words for the next pass
+    int32_t pad;
 };
 
 // One radius of a batched group: its probes, and the hull of their
@@ -127,6 +130,7 @@ struct DevBatchRadius {
 constexpr int MAX_RINGS = 4;
 
 struct BatchDevPlan {
+    uint8_t *const *mask_of;  // per template of the screen (null: no mask)
     const DevBatchPass *passes;
     int n_passes;
     const DevBatchGroup *groups;
@@ -152,9 +156,8 @@ enum KernelId {
     K_BAND_FINAL,
     K_STAR,
     K_STAR_BATCH,
-    K_COMPACT_COUNT,
     K_COMPACT_SCAN,
-    K_COMPACT_WRITE,
+    K_COMPACT_LIST,
     K_STAR_MOM,
     K_COUNT
 };
@@ -202,6 +205,31 @@ hipError_t launch_build(const BuildGeom &g, const void *pixels, int64_t pitch_by
                         uint32_t feat_mask, const BuildBuffers &bb, hipStream_t stream,
                         Profiler *prof);
 
+// ---------------------------------------------------------------------------
+// Fused compaction (Algorithm 1: R <- R u {P}).  A segment is (template t,
+// image row y, chunk c): the 64 columns [64 c, 64 c + 64) of row y, which
+// one wave of a star pass covers.  For every row it screens, a wave writes,
+// per template, the mask bytes of its segment, the number of candidates in
+// it (one ballot) and the candidates themselves ({x, scale bits}, in column
+// order) to the segment's 64 staging slots: no barrier, no shared memory.
+// Segments in (t, y, c) order are in canonical (t, y, x) order; a sum per
+// 64 segments, a scan of those sums and a list pass then place the staged
+// candidates in the list.  The scale bits never reach memory as one word
+// per position.
+// ---------------------------------------------------------------------------
+constexpr int SEG_W = 64;  // columns per segment (one wave)
+
+struct EmitOut {
+    uint8_t *mask;              // plain launches: this template's mask [H][W] (or null);
+                                // batched launches take a mask per template beside it
+    uint8_t *seg_count;         // [T][H][n_chunks] candidates per segment (<= 64), or null:
+                                // the mask alone
+    uint2 *stage;               // [T][H][n_chunks][SEG_W]: {x, scale bits}
+    uint32_t *dense;            // batched launches over several passes of a group: scale-bit
+                                // words [T][H][W] carried between passes, else null
+    int H, W, n_chunks;         // n_chunks = ceil(W / SEG_W)
+};
+
 // Persistent strip sweep of the star kernel: strips `strip` columns wide (one
 // block), each split into `parts` row ranges when there are fewer than 8
 // strips; units are dealt to the 8 XCDs round-robin.
@@ -221,22 +249,36 @@ size_t star_lds_bytes(int strip, int nq, int ebytes, int smax, int rmax);
 // on planar tables (the first quantity alone, the others only where it
 // passes)
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                             const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                              int smax, int rmax, int variant, hipStream_t stream,
                              Profiler *prof);
 
 // staged: look up the first quantity alone and the others only where it
 // lies in the radius' hull (as variant 3 of the plain screen)
 hipError_t launch_star_batch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const BatchDevPlan &bp, uint32_t *bits, const StarSweep &sw,
+                             const BatchDevPlan &bp, const EmitOut &eo, const StarSweep &sw,
                              bool staged, hipStream_t stream, Profiler *prof);
 
-// compaction over n = n_tmpl * H * W scale-bit words in (t, y, x) order
-size_t compact_workspace_bytes(int64_t n);
+
+// segments of a screen of n_tmpl templates of H x W
+int64_t emit_segments(int64_t n_tmpl, int H, int W);
+// bytes of the emission workspace (counts, staging, scan) for n_tmpl templates
+size_t emit_workspace_bytes(int64_t n_tmpl, int H, int W);
+// carve the workspace: counts, staging, then the scan area
+void emit_carve(void *ws, int64_t n_tmpl, int H, int W, uint8_t **seg_count, uint2 **stage,
+                void **scan_ws);
+
+// The mask is written by the star pass; this places the staged candidates of
+// n_tmpl templates' segments (seg_count / stage as carved, possibly offset by
+// whole templates) into the list in (t, y, x) order and the total into
+// *count.  scan_ws: the carved scan area (one at a time per workspace).
+hipError_t launch_list(const uint8_t *seg_count, const uint2 *stage, int64_t n_tmpl, int H,
+                       int W, oss_candidate *list, int64_t list_cap, int64_t *count,
+                       void *scan_ws, hipStream_t stream, Profiler *prof);
 hipError_t launch_region_scatter(const oss_candidate *list, int64_t list_cap,
                                  const int64_t *count, int t, uint32_t bits, int H, int W,
                                  int pad, int64_t wp, uint8_t *ind, hipStream_t st);
-hipError_t launch_region_or(const uint32_t *hit, int H, int W, int pad, int64_t wp,
+hipError_t launch_region_or(const uint8_t *hit, int H, int W, int pad, int64_t wp,
                             uint8_t *region, hipStream_t st);
 
 // The paper's own features (mean, variance, first-moment magnitude) per
@@ -257,11 +299,7 @@ struct DevMomPlan {
 };
 
 hipError_t launch_star_moments(const BuildGeom &g, uint32_t fm, const void *L, const void *R,
-                               const void *Rp, const DevMomPlan *plan, uint32_t *bits,
+                               const void *Rp, const DevMomPlan *plan, const EmitOut &eo,
                                const StarSweep &sw, hipStream_t stream, Profiler *prof);
-
-hipError_t launch_compact(const uint32_t *bits, int64_t n_tmpl, int H, int W, uint8_t *mask,
-                          oss_candidate *list, int64_t list_cap, int64_t *count, void *workspace,
-                          hipStream_t stream, Profiler *prof);
 
 }  // namespace oss

@@ -5,7 +5,7 @@ namespace oss {
 
 const char *const kKernelNames[K_COUNT] = {
     "row_base", "band_agg", "carry", "band_final",
-    "star_plain", "star_batch", "compact_count", "compact_scan", "compact_write", "star_moments",
+    "star_plain", "star_batch", "compact_scan", "compact_list", "star_moments",
 };
 
 static hipEvent_t take(Profiler *p)

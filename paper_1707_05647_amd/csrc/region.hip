@@ -37,7 +37,7 @@ __global__ void region_scatter_kernel(const oss_candidate *__restrict__ list, in
 }
 
 // region[y][x] |= hit[(y + pad) * wp + x + pad] != 0
-__global__ void region_or_kernel(const uint32_t *__restrict__ hit, int H, int W, int pad,
+__global__ void region_or_kernel(const uint8_t *__restrict__ hit, int H, int W, int pad,
                                  int64_t wp, uint8_t *__restrict__ region)
 {
     const int64_t n = (int64_t)H * W;
@@ -59,7 +59,7 @@ hipError_t launch_region_scatter(const oss_candidate *list, int64_t list_cap,
     return hipGetLastError();
 }
 
-hipError_t launch_region_or(const uint32_t *hit, int H, int W, int pad, int64_t wp,
+hipError_t launch_region_or(const uint8_t *hit, int H, int W, int pad, int64_t wp,
                             uint8_t *region, hipStream_t st)
 {
     const int64_t n = (int64_t)H * W;

@@ -71,7 +71,13 @@ size_t output_bytes(const oss_request &r)
            align256((size_t)r.list_cap * sizeof(oss_candidate)) + 256;
 }
 
-size_t workspace_bytes(int64_t n) { return (size_t)n * sizeof(uint32_t) + compact_workspace_bytes(n); }
+// a lane's screen workspace for n_tmpl templates of H x W: the emission
+// workspace, and scale-bit words when a group's radii span several passes
+size_t workspace_bytes(int64_t n_tmpl, int H, int W, bool carry)
+{
+    return emit_workspace_bytes(n_tmpl, H, W) +
+           (carry ? (size_t)n_tmpl * H * W * sizeof(uint32_t) : 0);
+}
 
 struct Resident {
     uint64_t key = 0;
@@ -120,7 +126,7 @@ struct oss_server {
     size_t in_use = 0, peak = 0;
     oss_server_stats st{};
 
-    size_t lane_ws(const Lane &l) const { return l.ctx->bits_cap + l.ctx->cws_cap; }
+    size_t lane_ws(const Lane &l) const { return l.ctx->bits_cap + l.ctx->ews_cap; }
     void account(ptrdiff_t d)
     {
         in_use = (size_t)((ptrdiff_t)in_use + d);
@@ -205,11 +211,11 @@ bool make_room(oss_server *s, size_t need, uint64_t keep, bool keep_valid, int l
         const size_t b = s->lane_ws(l);
         if (l.ctx->bits)
             (void)hipFree(l.ctx->bits);
-        if (l.ctx->cws)
-            (void)hipFree(l.ctx->cws);
+        if (l.ctx->ews)
+            (void)hipFree(l.ctx->ews);
         l.ctx->bits = nullptr;
-        l.ctx->cws = nullptr;
-        l.ctx->bits_cap = l.ctx->cws_cap = 0;
+        l.ctx->ews = nullptr;
+        l.ctx->bits_cap = l.ctx->ews_cap = 0;
         s->account(-(ptrdiff_t)b);
     }
     return s->in_use + need <= budget;
@@ -287,8 +293,10 @@ int launch(oss_server *s, int li, std::vector<Req *> &batch, Resident *r, bool h
                              fms.data(), l.ctx->batch_bucket, bp);
     if (rc != OSS_OK)
         return rc;
+    const BuildGeom &g = r->ref->geom;
+    const int strip = l.ctx->star_strip;
     const size_t ws0 = s->lane_ws(l);
-    rc = screen_workspace(l.ctx, (int64_t)T * hw);
+    rc = screen_workspace(l.ctx, T, g.H, g.W, plan_carries(bp));
     s->account((ptrdiff_t)s->lane_ws(l) - (ptrdiff_t)ws0);
     if (rc != OSS_OK)
         return rc;
@@ -301,16 +309,25 @@ int launch(oss_server *s, int li, std::vector<Req *> &batch, Resident *r, bool h
     } else if (hipStreamWaitEvent(l.st, r->ready, 0) != hipSuccess) {
         return OSS_E_DEVICE;
     }
+    // each merged template's mask goes straight to its request's output
+    std::vector<uint8_t *> masks;
+    for (Req *q : batch)
+        for (int t = 0; t < q->r.n_tmpl; ++t)
+            masks.push_back(q->mask() + (int64_t)t * hw);
     PlanSlot *slot = nullptr;
-    rc = batch_star(l.ctx, r->ref, bp, l.ctx->star_strip, l.ctx->star_blocks_per_xcd, l.st, &slot);
+    rc = batch_star(l.ctx, r->ref, bp, strip, l.ctx->star_blocks_per_xcd, masks.data(), l.st,
+                    &slot);
     if (rc != OSS_OK)
         return rc;
-    const BuildGeom &g = r->ref->geom;
+    void *scan_ws = nullptr;
+    const EmitOut eo = emit_out(l.ctx, T, g.H, g.W, &scan_ws);
+    const int64_t segs_t = (int64_t)g.H * eo.n_chunks;
     t0 = 0;
     for (Req *q : batch) {
-        if (launch_compact(l.ctx->bits + (int64_t)t0 * hw, q->r.n_tmpl, g.H, g.W, q->mask(),
-                           q->list(), q->r.list_cap, q->dcount(), l.ctx->cws, l.st,
-                           &l.ctx->prof) != hipSuccess)
+        // the request's own templates' segments, into its own list and count
+        if (launch_list(eo.seg_count + segs_t * t0, eo.stage + segs_t * SEG_W * t0, q->r.n_tmpl,
+                        g.H, g.W, q->list(), q->r.list_cap, q->dcount(), scan_ws, l.st,
+                        &l.ctx->prof) != hipSuccess)
             return OSS_E_DEVICE;
         if (hipMemcpyAsync(s->counts + q->slot, q->dcount(), sizeof(int64_t),
                            hipMemcpyDeviceToHost, l.st) != hipSuccess)
@@ -404,7 +421,8 @@ void schedule(oss_server *s)
                 tt += batch[i]->r.n_tmpl;
                 outs += batch[i]->out_bytes;
             }
-            const size_t ws = workspace_bytes(tt * h->hw());
+            const size_t ws =
+                workspace_bytes(tt, h->r.desc.H, h->r.desc.W, l.ctx->batch_bucket > 0);
             return outs + (ws > ws_now ? ws - ws_now : 0) + (hit ? 0 : tables);
         };
         // replacing non-covering tables frees them first
@@ -610,8 +628,11 @@ int oss_server_submit(oss_server *s, const oss_request *rq, int64_t *id)
     int rc = oss_ref_bytes(&rq->desc, rq->feat_mask, need_r, &tables);
     if (rc != OSS_OK)
         return rc;
-    const int64_t hw = (int64_t)rq->desc.H * rq->desc.W;
-    const size_t foot = tables + output_bytes(*rq) + workspace_bytes((int64_t)rq->n_tmpl * hw);
+    // the lanes' bucket setting is the server's (fixed at create)
+    const Lane &l0 = s->lanes[0];
+    const size_t foot = tables + output_bytes(*rq) +
+                        workspace_bytes(rq->n_tmpl, rq->desc.H, rq->desc.W,
+                                        l0.ctx->batch_bucket > 0);
     if (foot > (size_t)s->cfg.memory_budget)
         return OSS_E_NOMEM;
     Req *q = new (std::nothrow) Req();

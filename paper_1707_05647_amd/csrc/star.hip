@@ -49,7 +49,7 @@ template <typename Tab, bool STAGED>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
     int64_t pitch_e, int64_t plane, int H, int W, const DevTemplatePlan *__restrict__ plan,
-    uint32_t *__restrict__ bits, StarSweep sw)
+    EmitOut eo, StarSweep sw)
 {
     constexpr int NQ = Tab::NQ;
     constexpr int64_t ES = Tab::ES;  // bytes per table entry
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
                 }
             }
         }
-        if (x < W)
-            bits[(int64_t)y * W + x] = acc;
+        emit_row<1>(eo, 1, y, x, [&](int) { return acc; }, [](int) { return 0; },
+                    [&](int) { return eo.mask; });
     }
 }
 
@@ -173,7 +173,7 @@ template <typename Tab>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_pipe_kernel(
     const void *__restrict__ L, const void *__restrict__ R, const void *__restrict__ Rp,
     int64_t pitch_e, int64_t plane, int H, int W, const DevTemplatePlan *__restrict__ plan,
-    uint32_t *__restrict__ bits, StarSweep sw)
+    EmitOut eo, StarSweep sw)
 {
     constexpr int NQ = Tab::NQ;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -229,8 +229,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_pipe_kernel(
                 }
             }
         }
-        if (x < W)
-            bits[(int64_t)y * W + x] = acc;
+        emit_row<1>(eo, 1, y, x, [&](int) { return acc; }, [](int) { return 0; },
+                    [&](int) { return eo.mask; });
     }
 }
 
@@ -262,8 +262,8 @@ __device__ __forceinline__ void stage_row(T *__restrict__ dst, int cap, const ch
 template <typename T, int NQ>
 __global__ __launch_bounds__(STAR_MAX_THREADS) void star_lds_kernel(
     const T *__restrict__ L, const T *__restrict__ R, const T *__restrict__ Rp, int64_t pitch_e,
-    int H, int W, const DevTemplatePlan *__restrict__ plan, uint32_t *__restrict__ bits,
-    StarSweep sw, int smax, int rmax)
+    int H, int W, const DevTemplatePlan *__restrict__ plan, EmitOut eo, StarSweep sw, int smax,
+    int rmax)
 {
     extern __shared__ char smem_raw[];
     constexpr int64_t ES = (int64_t)sizeof(T) * NQ;
@@ -333,8 +333,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_lds_kernel(
                 }
             }
         }
-        if (x < W)
-            bits[(int64_t)y * W + x] = acc;
+        emit_row<1>(eo, 1, y, x, [&](int) { return acc; }, [](int) { return 0; },
+                    [&](int) { return eo.mask; });
     }
 }
 
@@ -357,65 +357,65 @@ StarSweep make_sweep(int H, int W, int strip, int blocks_per_xcd)
 
 template <typename T, int NQ>
 static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T *rp,
-                            const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                            const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                             int smax, int rmax, hipStream_t stream)
 {
     const size_t lds = star_lds_bytes(sw.strip, NQ, sizeof(T), smax, rmax);
     hipLaunchKernelGGL((star_lds_kernel<T, NQ>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), lds,
-                       stream, l, r, rp, g.pitch_e, g.H, g.W, plan, bits, sw, smax, rmax);
+                       stream, l, r, rp, g.pitch_e, g.H, g.W, plan, eo, sw, smax, rmax);
 }
 
 template <typename Tab>
 static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                              const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                              const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                               hipStream_t stream, int variant)
 {
     const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
     if (variant == 2) {
         hipLaunchKernelGGL((star_pipe_kernel<Tab>), grid, block, 0, stream, L, R, Rp, g.pitch_e,
-                           g.plane, g.H, g.W, plan, bits, sw);
+                           g.plane, g.H, g.W, plan, eo, sw);
         return;
     }
     if constexpr (Tab::STAGE && Tab::NQ > 1) {
         if (variant == 3) {
             hipLaunchKernelGGL((star_plain_kernel<Tab, true>), grid, block, 0, stream, L, R, Rp,
-                               g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+                               g.pitch_e, g.plane, g.H, g.W, plan, eo, sw);
             return;
         }
     }
     hipLaunchKernelGGL((star_plain_kernel<Tab, false>), grid, block, 0, stream, L, R, Rp,
-                       g.pitch_e, g.plane, g.H, g.W, plan, bits, sw);
+                       g.pitch_e, g.plane, g.H, g.W, plan, eo, sw);
 }
 
 template <typename T>
 static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                         const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                         const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                          int smax, int rmax, bool lds, int variant, hipStream_t stream)
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
     if (g.planar) {
         switch (g.nq) {
-        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
-        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
-        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+        case 1: star_plain_launch<TabP<T, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
+        case 2: star_plain_launch<TabP<T, 2>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
+        case 3: star_plain_launch<TabP<T, 3>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     if (lds) {
         switch (g.nq) {
-        case 1: star_lds_launch<T, 1>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
-        case 2: star_lds_launch<T, 2>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
-        case 3: star_lds_launch<T, 3>(g, l, r, rp, plan, bits, sw, smax, rmax, stream); break;
+        case 1: star_lds_launch<T, 1>(g, l, r, rp, plan, eo, sw, smax, rmax, stream); break;
+        case 2: star_lds_launch<T, 2>(g, l, r, rp, plan, eo, sw, smax, rmax, stream); break;
+        case 3: star_lds_launch<T, 3>(g, l, r, rp, plan, eo, sw, smax, rmax, stream); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     switch (g.nq) {
-    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
-    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
-    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, bits, sw, stream, variant); break;
+    case 1: star_plain_launch<TabU<T, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
+    case 2: star_plain_launch<TabU<T, 2>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
+    case 3: star_plain_launch<TabU<T, 3>>(g, L, R, Rp, plan, eo, sw, stream, variant); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -423,47 +423,49 @@ static hipError_t star_t(const BuildGeom &g, const void *L, const void *R, const
 
 // 64-bit squares (mixed 16-byte entries or split planes): no LDS variant.
 static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                           const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                           const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                            hipStream_t stream, int variant)
 {
     if (g.planar) {
         if (g.nq == 3 && g.sqi == 1)
-            star_plain_launch<TabPS<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+            star_plain_launch<TabPS<3, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);
         else if (g.nq == 2 && g.sqi == 1)
-            star_plain_launch<TabPS<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+            star_plain_launch<TabPS<2, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);
         else if (g.nq == 2 && g.sqi == 0)
-            star_plain_launch<TabPS<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+            star_plain_launch<TabPS<2, 0>>(g, L, R, Rp, plan, eo, sw, stream, variant);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
     }
     if (g.nq == 3 && g.sqi == 1)
-        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        star_plain_launch<TabMix<3, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);
     else if (g.nq == 2 && g.sqi == 1)
-        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        star_plain_launch<TabMix<2, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);
     else if (g.nq == 2 && g.sqi == 0)
-        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, bits, sw, stream, variant);
+        star_plain_launch<TabMix<2, 0>>(g, L, R, Rp, plan, eo, sw, stream, variant);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_star_plain(const BuildGeom &g, const void *L, const void *R, const void *Rp,
-                             const DevTemplatePlan *plan, uint32_t *bits, const StarSweep &sw,
+                             const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                              int smax, int rmax, int variant, hipStream_t stream,
                              Profiler *prof)
 {
     bool lds = variant == 1;
     if (sw.strip < 64 || sw.strip > STAR_MAX_THREADS || sw.strip % 64 || sw.blocks_per_xcd < 1)
         return hipErrorInvalidValue;
+    if (!emit_ok(eo, g))
+        return hipErrorInvalidValue;
     if (lds && star_lds_bytes(sw.strip, g.nq, g.ebytes, smax, rmax) > STAR_LDS_MAX)
         lds = false;
     ProfScope ps(prof, K_STAR, stream);
     if (g.sqi >= 0)
-        return star_mix(g, L, R, Rp, plan, bits, sw, stream, variant);
+        return star_mix(g, L, R, Rp, plan, eo, sw, stream, variant);
     if (g.ebytes == 4)
-        return star_t<uint32_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, variant, stream);
-    return star_t<uint64_t>(g, L, R, Rp, plan, bits, sw, smax, rmax, lds, variant, stream);
+        return star_t<uint32_t>(g, L, R, Rp, plan, eo, sw, smax, rmax, lds, variant, stream);
+    return star_t<uint64_t>(g, L, R, Rp, plan, eo, sw, smax, rmax, lds, variant, stream);
 }
 
 }  // namespace oss

@@ -285,6 +285,71 @@ __device__ __forceinline__ void star_sums_rest(const StarAddr &p, int64_t plane,
                      Tab::load_rest(p.h, plane), Tab::load_rest(p.k, plane), F);
 }
 
+// ---------------------------------------------------------------------------
+// Emission of one screened row segment: the wave's 64 columns of row y with
+// the final scale bits of MT template slots; per slot the mask bytes, the
+// segment's candidate count and its candidates in column order (see
+// EmitOut; with eo.seg_count null only the mask).  Wave-local: a ballot
+// gives the count, the lane's rank among the set ballot bits its slot.
+// ---------------------------------------------------------------------------
+
+// The emission geometry matches the tables (host check).
+inline bool emit_ok(const EmitOut &eo, const BuildGeom &g)
+{
+    return eo.H == g.H && eo.W == g.W && eo.n_chunks == (g.W + SEG_W - 1) / SEG_W &&
+           (eo.seg_count == nullptr) == (eo.stage == nullptr);
+}
+
+// A byte store through a global-memory pointer: a store through a generic
+// pointer becomes a flat store, which also counts on the scalar-load counter
+// and would make the next scalar-load wait for it.
+__device__ __forceinline__ void store_u8_global(uint8_t *p, uint8_t v)
+{
+    *(__attribute__((address_space(1))) uint8_t *)p = v;
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t ballot)
+{
+    // set ballot bits below this lane
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+}
+
+// x: this lane's column (the wave covers a 64-aligned run of columns);
+// val(t) -> scale bits of slot t (compile-time t); tg(t) -> template index of
+// slot t in the screen; mk(t) -> its mask (or null); nt slots in use.  tg and
+// mk should read read-only kernel arguments (scalar loads): a vector load
+// here would wait for every store in flight, since one counter counts both.
+template <int MT, typename Val, typename Tg, typename Mk>
+__device__ __forceinline__ void emit_row(const EmitOut &eo, int nt, int y, int x, Val val, Tg tg,
+                                         Mk mk)
+{
+    const int lane = threadIdx.x & 63;
+    if (x - lane >= eo.W)
+        return;  // a wave wholly right of the image (uniform)
+    const bool inw = x < eo.W;
+    const int64_t srow = (int64_t)y * eo.n_chunks + (x >> 6);  // segment within a template
+    const int64_t tseg = (int64_t)eo.H * eo.n_chunks;          // segments per template
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        if (t < nt) {
+            const uint32_t v = val(t);
+            const bool on = inw && v != 0u;
+            uint8_t *m = mk(t);
+            if (m && inw)
+                store_u8_global(m + (int64_t)y * eo.W + x, on ? 1 : 0);
+            if (eo.seg_count) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(on);
+                const int64_t seg = (int64_t)tg(t) * tseg + srow;
+                if (lane == 0)
+                    eo.seg_count[seg] = (uint8_t)__popcll(bal);
+                if (on)
+                    eo.stage[seg * SEG_W + lane_rank(bal)] = make_uint2((uint32_t)x, v);
+            }
+        }
+    }
+}
+
 // Position of sweep item `it` of XCD `xcd`: image row y and the strip's first
 // column x0 (y >= H marks an empty item of a short last part).
 __device__ __forceinline__ void sweep_item(const StarSweep &sw, int xcd, int it, int strip_w, int *y,

@@ -28,11 +28,10 @@ KERNELS = {
     "carry": ("carry_kernel", "paper_1707_05647_amd/csrc/builder.hip"),
     "band_final": ("band_final_kernel", "paper_1707_05647_amd/csrc/builder.hip"),
     "star_plain": ("star_plain_kernel", "paper_1707_05647_amd/csrc/star.hip"),
-    "star_batch": ("star_batch_kernel", "paper_1707_05647_amd/csrc/batched.hip"),
+    "star_batch": ("star_batch_kernel", "paper_1707_05647_amd/csrc/batched_kernel.h"),
     "star_moments": ("star_moments_kernel", "paper_1707_05647_amd/csrc/moments.hip"),
-    "compact_count": ("compact_count_kernel", "paper_1707_05647_amd/csrc/compact.hip"),
     "compact_scan": ("compact_scan_kernel", "paper_1707_05647_amd/csrc/compact.hip"),
-    "compact_write": ("compact_write_kernel", "paper_1707_05647_amd/csrc/compact.hip"),
+    "compact_list": ("compact_list_kernel", "paper_1707_05647_amd/csrc/compact.hip"),
     "copy": ("copy", None),
 }
 

@@ -34,7 +34,8 @@ def _round_clip(v: np.ndarray, hi: int, dtype) -> np.ndarray:
 def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
                blobs_per_512sq: float = 200.0, n_blobs: int | None = None,
                base: float = 128.0, amp: float = 80.0, sig_lo: float = 4.0,
-               sig_hi: float = 64.0, noise: float = 8.0, device=None) -> np.ndarray:
+               sig_hi: float = 64.0, noise: float = 8.0, device=None,
+               render: bool = True) -> np.ndarray | None:
     """Base + Gaussian blobs + iid uniform noise, rounded and clipped.
 
     * ``n_blobs`` defaults to ``blobs_per_512sq`` per 512x512 of area.
@@ -49,11 +50,16 @@ def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
     float64 (fast for very large images); the noise then comes from a torch
     generator seeded from ``rng``, so the image is a deterministic function
     of the seed but not bit-identical to the host rendering.  The result is
-    returned as a host array either way.
+    returned as a host array either way.  With ``render=False`` (device
+    rendering only) the same numbers are drawn from ``rng`` and nothing is
+    rendered (None is returned): the generator is left exactly where a
+    rendering would leave it, for callers that hold the image already.
     """
     if device is not None:
         return _blob_image_torch(H, W, rng, depth, blobs_per_512sq, n_blobs, base, amp, sig_lo,
-                                 sig_hi, noise, device)
+                                 sig_hi, noise, device, render)
+    if not render:
+        raise ValueError("render=False needs device rendering (its noise is one seed)")
     if n_blobs is None:
         n_blobs = max(1, int(round(blobs_per_512sq * H * W / (512.0 * 512.0))))
     img = np.full((H, W), base, dtype=np.float64)
@@ -82,8 +88,7 @@ def blob_image(H: int, W: int, rng: np.random.Generator, *, depth: int = 8,
 
 
 def _blob_image_torch(H, W, rng, depth, blobs_per_512sq, n_blobs, base, amp, sig_lo, sig_hi,
-                      noise, device):
-    import torch
+                      noise, device, render=True):
     if n_blobs is None:
         n_blobs = max(1, int(round(blobs_per_512sq * H * W / (512.0 * 512.0))))
     amps = rng.uniform(-amp, amp, n_blobs)
@@ -91,6 +96,9 @@ def _blob_image_torch(H, W, rng, depth, blobs_per_512sq, n_blobs, base, amp, sig
     cxs = rng.uniform(0.0, W, n_blobs)
     cys = rng.uniform(0.0, H, n_blobs)
     nseed = int(rng.integers(0, 2 ** 62))
+    if not render:
+        return None
+    import torch
     img = torch.full((H, W), base, dtype=torch.float64, device=device)
     xs_all = torch.arange(W, dtype=torch.float64, device=device)
     ys_all = torch.arange(H, dtype=torch.float64, device=device)

@@ -34,6 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .images import blob_image, cut_patch, make_rng, pick_centre, rotate_scale_patch
+from .images import blob_image as _blob_image
 
 # feature bits, as in the library's feature mask
 F_SUM, F_SQ, F_GRAD = 1, 2, 4
@@ -97,13 +98,30 @@ def _resampled_template(rng, ref, hi, obj_radius_fn, *, std_min, apron, margin_m
 
 def make_workload(cfg_id: int, seed: int = 0, *, H: int | None = None, W: int | None = None,
                   n_templates: int | None = None, blobs_per_512sq: float = 200.0,
-                  sig_hi: float = 64.0, device=None) -> Workload:
+                  sig_hi: float = 64.0, device=None, ref_cache: str | None = None) -> Workload:
     """Build workload ``cfg_id`` from ``seed``.  ``H``/``W``/``n_templates``
     shrink it for tests; ``blobs_per_512sq``/``sig_hi`` keep small images
     textured (the default blob recipe is sized for large images);
-    ``device`` renders the reference image with torch on that device."""
+    ``device`` renders the reference image with torch on that device.
+    ``ref_cache`` (with ``device``): an .npy file holding the rendered
+    reference; loaded when it exists (the generator still draws the same
+    numbers, so the templates are the same), written otherwise."""
+    import os
     rng = make_rng(cfg_id, seed)
     bkw = {"blobs_per_512sq": blobs_per_512sq, "sig_hi": sig_hi, "device": device}
+
+    def blob_image(H, W, rng, **kw):  # noqa: F811  (the cached form of the generator)
+        if ref_cache is None or device is None:
+            return _blob_image(H, W, rng, **kw)
+        if os.path.exists(ref_cache):
+            _blob_image(H, W, rng, render=False, **kw)
+            img = np.load(ref_cache, allow_pickle=False)
+            if img.shape != (H, W):
+                raise ValueError(f"{ref_cache} holds a {img.shape} image, not {(H, W)}")
+            return img
+        img = _blob_image(H, W, rng, **kw)
+        np.save(ref_cache, img, allow_pickle=False)
+        return img
     if cfg_id == 1:
         H = H or 512
         W = W or H
