@@ -62,6 +62,8 @@ extern "C" {
 #define OSS_E_OVERFLOW (-3) /* an integer table could overflow int64 */
 #define OSS_E_DEVICE (-4)   /* a HIP runtime call failed */
 #define OSS_E_STATE (-5)    /* handle used with the wrong context or shape */
+#define OSS_E_LIMIT (-6)    /* the call needs more than a fixed capacity (the scratch of
+                             * oss_screen_noalloc) */
 
 /* pixel types */
 #define OSS_U8 0
@@ -305,6 +307,31 @@ int oss_screen(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl, 
                const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
                uint32_t feat_mask, uint8_t *dev_mask, oss_candidate *dev_list, int64_t list_cap,
                int64_t *dev_count, void *stream);
+
+/*
+ * oss_screen without allocation, for callers that cannot allocate device
+ * memory during a screen: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs, kernels and
+ * results as oss_screen (the same options apply); the context and the
+ * reference are made beforehand.  Its scratch (the launch plans, the
+ * per-segment candidate counts, the staged candidates and the scan) lives in
+ * one fixed device array of OSS_NOALLOC_SCRATCH_BYTES per GPU, held by the
+ * library until the process ends; the call makes no hipMalloc, hipFree or
+ * other allocation, host or device, and is not profiled (oss_ctx_profile
+ * does not see its kernels).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams, threads or contexts) race
+ * and must be serialised by the caller.  Nothing in the array needs clearing
+ * between calls (each call writes every count it reads).  OSS_E_LIMIT when
+ * the screen needs more scratch than the array holds: about
+ * n_tmpl * H * ceil(W / 64) * 513 bytes of counts and staging plus 2.5 KB
+ * per template; a 4096 x 4096 screen of one template fits.
+ */
+#define OSS_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+int oss_screen_noalloc(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                       int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                       const oss_tolerance *tol, uint32_t feat_mask, uint8_t *dev_mask,
+                       oss_candidate *dev_list, int64_t list_cap, int64_t *dev_count,
+                       void *stream);
 
 /*
  * Same contract and outputs as oss_screen, with all templates and probes in

@@ -16,12 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboss.so")
 
 OSS_OK, OSS_E_ARG, OSS_E_NOMEM, OSS_E_OVERFLOW, OSS_E_DEVICE, OSS_E_STATE = 0, -1, -2, -3, -4, -5
+OSS_E_LIMIT = -6
 OSS_U8, OSS_U16 = 0, 1
 OSS_F_SUM, OSS_F_SQ, OSS_F_GRAD, OSS_F_ALL = 1, 2, 4, 7
 OSS_F_XMOM, OSS_F_YMOM, OSS_F_MOMENTS = 8, 16, 24
 OSS_MAX_QUANTITIES = 5
 OSS_T_MEAN, OSS_T_VAR, OSS_T_MAG = 1, 2, 4
 OSS_MAX_SCALES = 32
+OSS_NOALLOC_SCRATCH_BYTES = 160 << 20
 
 EXPORTED = [
     "oss_ctx_create", "oss_ctx_destroy", "oss_status_string", "oss_ref_bytes", "oss_ref_create",
@@ -30,6 +32,7 @@ EXPORTED = [
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
     "oss_ref_layout", "oss_region", "oss_template_moments", "oss_screen_moments", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
+    "oss_screen_noalloc",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_OPT_TABLE_PLANAR = 5
@@ -161,6 +164,7 @@ def load(path: str | None = None):
     lib.oss_screen.argtypes = [vp, vp, C.POINTER(oss_template_feat), i32, C.POINTER(oss_probe), i32,
                                C.POINTER(oss_tolerance), u32, vp, vp, i64, vp, vp]
     lib.oss_screen_batched.argtypes = lib.oss_screen.argtypes
+    lib.oss_screen_noalloc.argtypes = lib.oss_screen.argtypes
     lib.oss_screen_intervals.argtypes = [vp, vp, i32, C.POINTER(oss_interval_probe), i32, u32,
                                          vp, vp, i64, vp, vp]
     lib.oss_alg1_probes.argtypes = [vp, C.POINTER(oss_image_desc), i32,
@@ -379,6 +383,18 @@ def oss_screen(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None,
     _check(fn(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask), _ptr(mask),
               _ptr(cand_list), int(list_cap), _ptr(count), _stream(stream)),
            "oss_screen_batched" if batched else "oss_screen")
+
+
+def oss_screen_noalloc(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None,
+                       cand_list=None, list_cap: int = 0, count=None, stream=None):
+    """oss_screen with its scratch in the library's fixed device array (no
+    allocation; OSS_E_LIMIT past OSS_NOALLOC_SCRATCH_BYTES)."""
+    ta, nt, pa, npb, tol = _screen_args(tmpl, probes, tol)
+    if count is None:
+        raise ValueError("count tensor required")
+    _check(load().oss_screen_noalloc(ctx, ref, ta, nt, pa, npb, C.byref(tol), int(feat_mask),
+                                     _ptr(mask), _ptr(cand_list), int(list_cap), _ptr(count),
+                                     _stream(stream)), "oss_screen_noalloc")
 
 
 def oss_screen_batched(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int, mask=None,

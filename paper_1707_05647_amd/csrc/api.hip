@@ -102,6 +102,7 @@ const char *oss_status_string(int status)
     case OSS_E_OVERFLOW: return "OSS_E_OVERFLOW";
     case OSS_E_DEVICE: return "OSS_E_DEVICE";
     case OSS_E_STATE: return "OSS_E_STATE";
+    case OSS_E_LIMIT: return "OSS_E_LIMIT";
     default: return "OSS_E_UNKNOWN";
     }
 }
@@ -122,6 +123,11 @@ int oss_ctx_create(int device, oss_ctx **out)
     if (!c)
         return OSS_E_NOMEM;
     c->device = device;
+    // the no-allocation screen's scratch address on this device
+    if (noalloc_init(device) != OSS_OK) {
+        delete c;
+        return OSS_E_DEVICE;
+    }
     for (auto &s : c->slots) {
         if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
             oss_ctx_destroy(c);
@@ -626,62 +632,94 @@ static int upload_plan(oss_ctx *ctx, const void *src, size_t bytes, hipStream_t 
     return OSS_OK;
 }
 
-// Build the per-template plans: distinct radii in increasing order, and for
-// each the probes with their exact feature-sum bounds in table slot order.
-static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
-                      const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
-                      uint32_t fm, std::vector<DevTemplatePlan> &plans)
+// Probe list valid for a reference: template and scale ids in range, radii
+// within the tables' reach, at most OSS_MAX_SCALES probes per template.
+int oss::check_probes(const oss_ref *ref, int32_t n_tmpl, const oss_probe *probes,
+                      int32_t n_probes)
 {
-    plans.assign(n_tmpl, DevTemplatePlan{});
-    std::vector<std::vector<oss_probe>> per(n_tmpl);
     for (int i = 0; i < n_probes; ++i) {
         const oss_probe &p = probes[i];
         if (p.template_id < 0 || p.template_id >= n_tmpl || p.scale_id < 0 ||
             p.scale_id >= OSS_MAX_SCALES || p.r < 0 || p.r > ref->max_radius)
             return OSS_E_ARG;
-        per[p.template_id].push_back(p);
-        if ((int)per[p.template_id].size() > OSS_MAX_SCALES)
+    }
+    for (int t = 0; t < n_tmpl; ++t) {
+        int k = 0;
+        for (int i = 0; i < n_probes; ++i)
+            k += probes[i].template_id == t;
+        if (k > OSS_MAX_SCALES)
             return OSS_E_ARG;
+    }
+    return OSS_OK;
+}
+
+// Template t's plan (probes already checked): its distinct radii in
+// increasing order, and for each the probes with their exact feature-sum
+// bounds in table slot order.  No heap allocation.
+void oss::template_plan(const oss_ref *ref, const oss_template_feat &tf, int32_t t,
+                        const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+                        uint32_t fm, DevTemplatePlan *pl)
+{
+    *pl = DevTemplatePlan{};
+    // the template's probes, stably sorted by radius (insertion sort)
+    oss_probe v[OSS_MAX_SCALES];
+    int n = 0;
+    for (int i = 0; i < n_probes; ++i) {
+        if (probes[i].template_id != t)
+            continue;
+        int j = n++;
+        while (j > 0 && v[j - 1].r > probes[i].r) {
+            v[j] = v[j - 1];
+            --j;
+        }
+        v[j] = probes[i];
     }
     // feature f -> table slot (the reference's quantities in bit order)
     int slot_of[3], slot = 0;
     for (int f = 0; f < 3; ++f)
         slot_of[f] = (ref->feat_mask & (1u << f)) ? slot++ : -1;
-    for (int t = 0; t < n_tmpl; ++t) {
-        auto &v = per[t];
-        std::stable_sort(v.begin(), v.end(),
-                         [](const oss_probe &a, const oss_probe &b) { return a.r < b.r; });
-        DevTemplatePlan &pl = plans[t];
-        int nr = 0;
-        for (size_t i = 0; i < v.size(); ++i) {
-            if (nr == 0 || pl.radii[nr - 1].r != v[i].r) {
-                pl.radii[nr].r = v[i].r;
-                pl.radii[nr].s = square_half(v[i].r);
-                pl.radii[nr].first = (int32_t)i;
-                pl.radii[nr].count = 0;
-                ++nr;
-            }
-            pl.radii[nr - 1].count++;
-            DevProbe &dp = pl.probes[i];
-            dp.k = v[i].scale_id;
-            for (int q = 0; q < 3; ++q) {
-                dp.lo[q] = INT64_MIN;
-                dp.hi[q] = INT64_MAX;
-            }
-            for (int f = 0; f < 3; ++f) {
-                if (!(fm & (1u << f)))
-                    continue;
-                feature_bounds(f, tmpl[t].F[f], v[i].r, tmpl[t].rho, tol->P[f], tol->Q,
-                               &dp.lo[slot_of[f]], &dp.hi[slot_of[f]]);
-            }
+    int nr = 0;
+    for (int i = 0; i < n; ++i) {
+        if (nr == 0 || pl->radii[nr - 1].r != v[i].r) {
+            pl->radii[nr].r = v[i].r;
+            pl->radii[nr].s = square_half(v[i].r);
+            pl->radii[nr].first = (int32_t)i;
+            pl->radii[nr].count = 0;
+            ++nr;
         }
-        pl.n_radii = nr;
+        pl->radii[nr - 1].count++;
+        DevProbe &dp = pl->probes[i];
+        dp.k = v[i].scale_id;
+        for (int q = 0; q < 3; ++q) {
+            dp.lo[q] = INT64_MIN;
+            dp.hi[q] = INT64_MAX;
+        }
+        for (int f = 0; f < 3; ++f) {
+            if (!(fm & (1u << f)))
+                continue;
+            feature_bounds(f, tf.F[f], v[i].r, tf.rho, tol->P[f], tol->Q, &dp.lo[slot_of[f]],
+                           &dp.hi[slot_of[f]]);
+        }
     }
+    pl->n_radii = nr;
+}
+
+// Build the per-template plans.
+static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
+                      const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+                      uint32_t fm, std::vector<DevTemplatePlan> &plans)
+{
+    int rc = check_probes(ref, n_tmpl, probes, n_probes);
+    if (rc != OSS_OK)
+        return rc;
+    plans.assign(n_tmpl, DevTemplatePlan{});
+    for (int t = 0; t < n_tmpl; ++t)
+        template_plan(ref, tmpl[t], t, probes, n_probes, tol, fm, &plans[t]);
     return OSS_OK;
 }
 
 // Argument checks shared by the screens (before anything is launched).
-static int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+int oss::check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
                              int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
                              const oss_tolerance *tol, uint32_t feat_mask, int64_t list_cap,
                              const oss_candidate *dev_list, const int64_t *dev_count)

@@ -89,6 +89,24 @@ int batch_star(oss_ctx *ctx, const oss_ref *ref, const BatchHostPlan &bp, int st
 // Passes of the plan that carry scale bits to a later pass (need ctx->bits).
 bool plan_carries(const BatchHostPlan &bp);
 
+// Probe list valid for the reference (ids, radii, scales per template).
+int check_probes(const oss_ref *ref, int32_t n_tmpl, const oss_probe *probes, int32_t n_probes);
+
+// Argument checks shared by the screens (before anything is launched).
+int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat *tmpl,
+                      int32_t n_tmpl, const oss_probe *probes, int32_t n_probes,
+                      const oss_tolerance *tol, uint32_t feat_mask, int64_t list_cap,
+                      const oss_candidate *dev_list, const int64_t *dev_count);
+
+// Template t's launch plan from checked probes (no heap allocation).
+void template_plan(const oss_ref *ref, const oss_template_feat &tf, int32_t t,
+                   const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
+                   uint32_t fm, DevTemplatePlan *pl);
+
+// Look up the no-allocation screen's scratch on `device` (current), once per
+// device; called when a context is created.
+int noalloc_init(int device);
+
 // Image descriptor valid (sizes, dtype, depth, pitch).
 bool desc_ok(const oss_image_desc *d);
 
