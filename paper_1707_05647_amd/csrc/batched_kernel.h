@@ -190,11 +190,14 @@ inline void batch_launch_s(const BuildGeom &g, const void *L, const void *R, con
                            const BatchDevPlan &bp, const EmitOut &eo, const StarSweep &sw,
                            hipStream_t st)
 {
-    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
 #define OSS_BATCH_LAUNCH(MT, RINGS)                                                               \
-    hipLaunchKernelGGL((star_batch_kernel<Tab, MT, RINGS, STAGED>), grid, block, 0, st, L, R, Rp, \
-                       g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups, bp.radii, \
-                       bp.probes, bp.mask_of, eo, sw)
+    do {                                                                                          \
+        auto *k = &star_batch_kernel<Tab, MT, RINGS, STAGED>;                                     \
+        const StarSweep rs = resident_sweep(reinterpret_cast<const void *>(k), sw, 0);            \
+        hipLaunchKernelGGL(k, dim3(8 * rs.blocks_per_xcd), dim3(rs.strip), 0, st, L, R, Rp,       \
+                           g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,        \
+                           bp.radii, bp.probes, bp.mask_of, eo, rs);                              \
+    } while (0)
     if (bp.rings > 1) {
         if (bp.max_group <= 8)
             OSS_BATCH_LAUNCH(8, true);

@@ -138,11 +138,14 @@ static hipError_t moments_t(const BuildGeom &g, uint32_t fm, const void *L, cons
 {
     const T *l = static_cast<const T *>(L), *r = static_cast<const T *>(R),
             *rp = static_cast<const T *>(Rp);
-    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
     constexpr unsigned F3 = OSS_F_SUM | OSS_F_MOMENTS, F4 = OSS_F_SUM | OSS_F_SQ | OSS_F_MOMENTS;
 #define OSS_MOM_LAUNCH(FMV, PL)                                                                   \
-    hipLaunchKernelGGL((star_moments_kernel<T, FMV, PL>), grid, block, 0, st, l, r, rp, g.pitch_e, \
-                       g.plane, g.H, g.W, plan, eo, sw)
+    do {                                                                                          \
+        auto *k = &star_moments_kernel<T, FMV, PL>;                                               \
+        const StarSweep rs = resident_sweep(reinterpret_cast<const void *>(k), sw, 0);            \
+        hipLaunchKernelGGL(k, dim3(8 * rs.blocks_per_xcd), dim3(rs.strip), 0, st, l, r, rp,       \
+                           g.pitch_e, g.plane, g.H, g.W, plan, eo, rs);                           \
+    } while (0)
     if (fm == F3 && g.planar)
         OSS_MOM_LAUNCH(F3, true);
     else if (fm == F3)

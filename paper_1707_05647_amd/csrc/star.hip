@@ -361,8 +361,10 @@ static void star_lds_launch(const BuildGeom &g, const T *l, const T *r, const T 
                             int smax, int rmax, hipStream_t stream)
 {
     const size_t lds = star_lds_bytes(sw.strip, NQ, sizeof(T), smax, rmax);
-    hipLaunchKernelGGL((star_lds_kernel<T, NQ>), dim3(8 * sw.blocks_per_xcd), dim3(sw.strip), lds,
-                       stream, l, r, rp, g.pitch_e, g.H, g.W, plan, eo, sw, smax, rmax);
+    auto *k = &star_lds_kernel<T, NQ>;
+    const StarSweep rs = resident_sweep(reinterpret_cast<const void *>(k), sw, lds);
+    hipLaunchKernelGGL(k, dim3(8 * rs.blocks_per_xcd), dim3(rs.strip), lds, stream, l, r, rp,
+                       g.pitch_e, g.H, g.W, plan, eo, rs, smax, rmax);
 }
 
 template <typename Tab>
@@ -370,21 +372,22 @@ static void star_plain_launch(const BuildGeom &g, const void *L, const void *R, 
                               const DevTemplatePlan *plan, const EmitOut &eo, const StarSweep &sw,
                               hipStream_t stream, int variant)
 {
-    const dim3 grid(8 * sw.blocks_per_xcd), block(sw.strip);
+    auto go = [&](auto *k) {
+        const StarSweep rs = resident_sweep(reinterpret_cast<const void *>(k), sw, 0);
+        hipLaunchKernelGGL(k, dim3(8 * rs.blocks_per_xcd), dim3(rs.strip), 0, stream, L, R, Rp,
+                           g.pitch_e, g.plane, g.H, g.W, plan, eo, rs);
+    };
     if (variant == 2) {
-        hipLaunchKernelGGL((star_pipe_kernel<Tab>), grid, block, 0, stream, L, R, Rp, g.pitch_e,
-                           g.plane, g.H, g.W, plan, eo, sw);
+        go(&star_pipe_kernel<Tab>);
         return;
     }
     if constexpr (Tab::STAGE && Tab::NQ > 1) {
         if (variant == 3) {
-            hipLaunchKernelGGL((star_plain_kernel<Tab, true>), grid, block, 0, stream, L, R, Rp,
-                               g.pitch_e, g.plane, g.H, g.W, plan, eo, sw);
+            go(&star_plain_kernel<Tab, true>);
             return;
         }
     }
-    hipLaunchKernelGGL((star_plain_kernel<Tab, false>), grid, block, 0, stream, L, R, Rp,
-                       g.pitch_e, g.plane, g.H, g.W, plan, eo, sw);
+    go(&star_plain_kernel<Tab, false>);
 }
 
 template <typename T>

@@ -350,6 +350,24 @@ __device__ __forceinline__ void emit_row(const EmitOut &eo, int nt, int y, int x
     }
 }
 
+// The sweep with at most as many blocks per XCD as the GPU holds at once for
+// this kernel (host side).  Items are dealt to blocks statically, so a block
+// that cannot be resident until others finish would run its share as a tail
+// after them.
+inline StarSweep resident_sweep(const void *kernel, StarSweep sw, size_t lds_bytes)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, sw.strip, lds_bytes) !=
+            hipSuccess)
+        return sw;
+    const int cap = per_cu * (cus / 8);
+    if (cap > 0 && sw.blocks_per_xcd > cap)
+        sw.blocks_per_xcd = cap;
+    return sw;
+}
+
 // Position of sweep item `it` of XCD `xcd`: image row y and the strip's first
 // column x0 (y >= H marks an empty item of a short last part).
 __device__ __forceinline__ void sweep_item(const StarSweep &sw, int xcd, int it, int strip_w, int *y,
