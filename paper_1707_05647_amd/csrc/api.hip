@@ -897,6 +897,31 @@ static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
             bp.probes.push_back(dp);
         }
         const int rad_end = (int)bp.radii.size();
+        // each radius' core: the intersection of its probes' intervals, and
+        // the scale bits its probes set per template slot
+        for (int j = rad_begin; j < rad_end; ++j) {
+            DevBatchRadius &rd = bp.radii[j];
+            rd.cb_first = -1;
+            bool core = bp.rings == 1;
+            for (int q = 0; q < 3; ++q) {
+                rd.clo[q] = INT64_MIN;
+                rd.chi[q] = INT64_MAX;
+            }
+            for (int p = rd.first; p < rd.first + rd.count && core; ++p) {
+                const DevBatchProbe &pr = bp.probes[p];
+                for (int q = 0; q < 3; ++q) {
+                    rd.clo[q] = std::max(rd.clo[q], pr.lo[q]);
+                    rd.chi[q] = std::min(rd.chi[q], pr.hi[q]);
+                    core = core && rd.clo[q] <= rd.chi[q];
+                }
+            }
+            if (!core)
+                continue;
+            rd.cb_first = (int32_t)bp.core_bits.size();
+            bp.core_bits.resize(bp.core_bits.size() + nt, 0u);
+            for (int p = rd.first; p < rd.first + rd.count; ++p)
+                bp.core_bits[rd.cb_first + bp.probes[p].t] |= 1u << bp.probes[p].k;
+        }
         const int step = bucket > 0 ? bucket : std::max(1, rad_end - rad_begin);
         int j0 = rad_begin;
         do {
@@ -1016,7 +1041,8 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, uint8_t *con
     const size_t o_grp = al(o_pass + bp.passes.size() * sizeof(DevBatchPass));
     const size_t o_rad = al(o_grp + bp.groups.size() * sizeof(DevBatchGroup));
     const size_t o_prb = al(o_rad + bp.radii.size() * sizeof(DevBatchRadius));
-    const size_t total = al(o_prb + std::max<size_t>(1, bp.probes.size()) * sizeof(DevBatchProbe));
+    const size_t o_cb = al(o_prb + std::max<size_t>(1, bp.probes.size()) * sizeof(DevBatchProbe));
+    const size_t total = al(o_cb + std::max<size_t>(1, bp.core_bits.size()) * sizeof(uint32_t));
     std::vector<char> buf(total, 0);
     if (masks)
         std::memcpy(buf.data() + o_mask, masks, (size_t)bp.n_tmpl * sizeof(uint8_t *));
@@ -1024,6 +1050,7 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, uint8_t *con
     std::memcpy(buf.data() + o_grp, bp.groups.data(), bp.groups.size() * sizeof(DevBatchGroup));
     std::memcpy(buf.data() + o_rad, bp.radii.data(), bp.radii.size() * sizeof(DevBatchRadius));
     std::memcpy(buf.data() + o_prb, bp.probes.data(), bp.probes.size() * sizeof(DevBatchProbe));
+    std::memcpy(buf.data() + o_cb, bp.core_bits.data(), bp.core_bits.size() * sizeof(uint32_t));
     int rc = upload_plan(ctx, buf.data(), total, st, slot);
     if (rc != OSS_OK)
         return rc;
@@ -1034,6 +1061,7 @@ static int upload_batch_plan(oss_ctx *ctx, const BatchHostPlan &bp, uint8_t *con
     dev->groups = reinterpret_cast<const DevBatchGroup *>(d + o_grp);
     dev->radii = reinterpret_cast<const DevBatchRadius *>(d + o_rad);
     dev->probes = reinterpret_cast<const DevBatchProbe *>(d + o_prb);
+    dev->core_bits = reinterpret_cast<const uint32_t *>(d + o_cb);
     dev->max_group = bp.max_group;
     dev->rings = bp.rings;
     return OSS_OK;

@@ -65,6 +65,7 @@ struct BatchHostPlan {
     std::vector<DevBatchGroup> groups;
     std::vector<DevBatchRadius> radii;
     std::vector<DevBatchProbe> probes;
+    std::vector<uint32_t> core_bits;  // per radius with a core: one word per template slot
     int max_group = 0;
     int rings = 1;
 };

@@ -17,8 +17,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     int64_t pitch_e, int64_t plane, int H, int W, const DevBatchPass *__restrict__ passes,
     int n_passes,
     const DevBatchGroup *__restrict__ groups, const DevBatchRadius *__restrict__ radii,
-    const DevBatchProbe *__restrict__ probes, uint8_t *const *__restrict__ mask_of, EmitOut eo,
-    StarSweep sw)
+    const DevBatchProbe *__restrict__ probes, const uint32_t *__restrict__ core_bits,
+    uint8_t *const *__restrict__ mask_of, EmitOut eo, StarSweep sw)
 {
     constexpr int NQ = Tab::NQ;
     constexpr int64_t ES = Tab::ES;
@@ -92,6 +92,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                     }
                 };
                 int64_t F[NQ];
+                bool in = false;  // inside the radius' hull
                 if constexpr (STAGED && Tab::STAGE && NQ > 1) {
                     constexpr int C = Tab::C;
                     const StarAddr ad = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                     }
                     if (in_c)
                         star_sums_rest<Tab>(ad, plane, F);
-                    bool in = in_c;
+                    in = in_c;
                     if (in_c) {
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                         continue;
                     }
                 } else {
-                    bool in = xv;
+                    in = xv;
                     if (xv) {
                         star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
 #pragma unroll
@@ -128,6 +129,30 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                     if (__builtin_amdgcn_ballot_w64(in) == 0 || !in) {
                         fail_all();
                         continue;
+                    }
+                }
+                if constexpr (!RINGS) {
+                    // every hull lane of the wave inside the core passes every
+                    // probe of the radius: the radius' bits per slot at once
+                    if (rd.cb_first >= 0) {
+                        bool inc = in;
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            inc = inc & (F[q] >= rd.clo[q]) & (F[q] <= rd.chi[q]);
+                        if (__builtin_amdgcn_ballot_w64(in && !inc) == 0) {
+                            const uint32_t *cb = core_bits + rd.cb_first;
+#pragma unroll
+                            for (int t = 0; t < MT; ++t) {
+                                if (t < nt) {
+                                    const uint32_t b = inc ? cb[t] : 0u;
+                                    if (t < 32)
+                                        acc[t < 32 ? t : 0] |= b;
+                                    else
+                                        acc_hi[t >= 32 ? t - 32 : 0] |= b;
+                                }
+                            }
+                            continue;
+                        }
                     }
                 }
                 {
@@ -196,7 +221,7 @@ inline void batch_launch_s(const BuildGeom &g, const void *L, const void *R, con
         const StarSweep rs = resident_sweep(reinterpret_cast<const void *>(k), sw, 0);            \
         hipLaunchKernelGGL(k, dim3(8 * rs.blocks_per_xcd), dim3(rs.strip), 0, st, L, R, Rp,       \
                            g.pitch_e, g.plane, g.H, g.W, bp.passes, bp.n_passes, bp.groups,        \
-                           bp.radii, bp.probes, bp.mask_of, eo, rs);                              \
+                           bp.radii, bp.probes, bp.core_bits, bp.mask_of, eo, rs);                \
     } while (0)
     if (bp.rings > 1) {
         if (bp.max_group <= 8)

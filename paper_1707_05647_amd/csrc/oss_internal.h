@@ -119,12 +119,19 @@ struct DevBatchPass {
     int32_t pad;
 };
 
-// One radius of a batched group: its probes, and the hull of their
-// intervals per feature slot (a position outside it fails every probe).
+// One radius of a batched group: its probes, the hull of their intervals
+// per feature slot (a position outside it fails every probe) and their
+// intersection, the core (a position inside it passes every probe).  With a
+// core, core_bits[cb_first + slot] holds the scale bits the radius' probes
+// set for each template slot of the group; cb_first < 0: no core (empty, or
+// central-star entries).
 struct DevBatchRadius {
     int32_t r, s;
     int32_t first, count;
     int64_t lo[3], hi[3];
+    int64_t clo[3], chi[3];
+    int32_t cb_first;
+    int32_t pad;
 };
 
 constexpr int MAX_RINGS = 4;
@@ -136,6 +143,7 @@ struct BatchDevPlan {
     const DevBatchGroup *groups;
     const DevBatchRadius *radii;
     const DevBatchProbe *probes;
+    const uint32_t *core_bits;
     int max_group;
     int rings;  // 1: plain probes; > 1: central-star rings (one pass per group)
 };
