@@ -932,6 +932,18 @@ static void build_groups(const std::vector<std::vector<PlanEntry>> &per,
     }
 }
 
+// Each radius' table-row offsets from row y-1: rows y-s-1, y+s, y-r-1, y+r.
+static void set_row_offsets(const oss_ref *ref, BatchHostPlan &bp)
+{
+    const int64_t rb = ref->geom.pitch_e * ref->geom.tab_es;
+    for (DevBatchRadius &rd : bp.radii) {
+        rd.roff[0] = -(int64_t)rd.s * rb;
+        rd.roff[1] = (int64_t)(rd.s + 1) * rb;
+        rd.roff[2] = -(int64_t)rd.r * rb;
+        rd.roff[3] = (int64_t)(rd.r + 1) * rb;
+    }
+}
+
 // feature f -> table slot (the reference's quantities in bit order), -1 if absent
 static void slots_of(uint32_t ref_fm, int slot_of[3])
 {
@@ -991,6 +1003,7 @@ int oss::make_batch_plan(const oss_ref *ref, const oss_template_feat *tmpl, int3
         return tmpl[(int64_t)a * n_rings].rho < tmpl[(int64_t)b * n_rings].rho;
     });
     build_groups(per, order, bucket, bp);
+    set_row_offsets(ref, bp);
     return OSS_OK;
 }
 
@@ -1028,6 +1041,7 @@ static int make_interval_plan(const oss_ref *ref, int32_t n_tmpl, const oss_inte
         order[t] = t;
     bp.rings = 1;
     build_groups(per, order, bucket, bp);
+    set_row_offsets(ref, bp);
     return OSS_OK;
 }
 

@@ -41,6 +41,9 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
             const char *Lb = reinterpret_cast<const char *>(L) + (int64_t)x0 * ES;
             const char *Rb = reinterpret_cast<const char *>(R) + (int64_t)x0 * ES;
             const char *Rpb = reinterpret_cast<const char *>(Rp) + (int64_t)x0 * ES;
+            // table row y (image row y - 1) of each table at the strip
+            const int64_t yrow = (int64_t)y * row_bytes;
+            const char *Ly = Lb + yrow, *Ry = Rb + yrow, *Rpy = Rpb + yrow;
             // Scale bits per template slot: whose own star passes (acc) and
             // which a central star fails (fail).  An array indexed by the
             // wave-uniform slot stays in registers up to 32 entries, so a
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 bool in = false;  // inside the radius' hull
                 if constexpr (STAGED && Tab::STAGE && NQ > 1) {
                     constexpr int C = Tab::C;
-                    const StarAddr ad = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
+                    const StarAddr ad = star_addr_rows<Tab>(Ly, Ry, Rpy, rd.roff, lane_off, r, s);
                     bool in_c = false;
                     if (xv) {
                         F[C] = star_sum_c<Tab>(ad, plane);
@@ -120,7 +123,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 } else {
                     in = xv;
                     if (xv) {
-                        star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
+                        star_sums_at<Tab>(star_addr_rows<Tab>(Ly, Ry, Rpy, rd.roff, lane_off, r, s),
+                                          F, plane);
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
                             in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);

@@ -130,6 +130,7 @@ struct DevBatchRadius {
     int32_t first, count;
     int64_t lo[3], hi[3];
     int64_t clo[3], chi[3];
+    int64_t roff[4];  // byte offsets of table rows y-s-1, y+s, y-r-1, y+r from row y-1
     int32_t cb_first;
     int32_t pad;
 };

@@ -250,7 +250,42 @@ __device__ __forceinline__ StarAddr star_addr(const char *Lb, const char *Rb, co
     return o;
 }
 
+// The same addresses from the item's row bases (table row y of L, R and R':
+// image row y - 1) and the radius' row offsets roff = {-s, s+1, -r, r+1}
+// table rows in bytes (computed once per plan), so no per-radius multiply.
+template <typename Tab>
+__device__ __forceinline__ StarAddr star_addr_rows(const char *Ly, const char *Ry,
+                                                   const char *Rpy, const int64_t *roff,
+                                                   uint32_t lane_off, int r, int s)
+{
+    constexpr int64_t ES = Tab::ES;
+    const char *l_top = Ly + roff[0];  // row y-s-1
+    const char *l_bot = Ly + roff[1];  // row y+s
+    const char *r_top = Ry + roff[2];  // row y-r-1
+    const char *r_bot = Ry + roff[3];  // row y+r
+    const int64_t ds = (int64_t)s * ES, ds1 = (int64_t)(s + 1) * ES;
+    const int64_t dr = (int64_t)r * ES, dr1 = (int64_t)(r + 1) * ES;
+    StarAddr o;
+    o.a = l_bot + ds + lane_off;    // L(x+s,   y+s)
+    o.b = l_bot - ds1 + lane_off;   // L(x-s-1, y+s)
+    o.c = l_top + ds + lane_off;    // L(x+s,   y-s-1)
+    o.d = l_top - ds1 + lane_off;   // L(x-s-1, y-s-1)
+    o.e = r_bot + lane_off;         // R(x, y+r)
+    o.f = Rpy - dr1 + lane_off;     // R'(x-r-1, y-1)
+    o.h = Rpy + dr + lane_off;      // R'(x+r, y-1)
+    o.k = r_top + lane_off;         // R(x, y-r-1)
+    return o;
+}
+
 // Star feature sums of every quantity.
+template <typename Tab>
+__device__ __forceinline__ void star_sums_at(const StarAddr &p, int64_t *F, int64_t plane)
+{
+    Tab::reduce(Tab::load(p.a, plane), Tab::load(p.b, plane), Tab::load(p.c, plane),
+                Tab::load(p.d, plane), Tab::load(p.e, plane), Tab::load(p.f, plane),
+                Tab::load(p.h, plane), Tab::load(p.k, plane), F);
+}
+
 template <typename Tab>
 __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
                                           int64_t row_bytes, uint32_t lane_off, int y, int r,
