@@ -64,6 +64,8 @@ extern "C" {
 #define OSS_E_STATE (-5)    /* handle used with the wrong context or shape */
 #define OSS_E_LIMIT (-6)    /* the call needs more than a fixed capacity (the scratch of
                              * oss_screen_noalloc) */
+#define OSS_E_CANCELLED (-7) /* a queued serving request cancelled by the caller */
+#define OSS_E_TIMEOUT (-8)   /* a serving request queued longer than the server's limit */
 
 /* pixel types */
 #define OSS_U8 0
@@ -534,7 +536,7 @@ int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_fe
  * oss_server_submit and run by oss_server_pump: the oldest queued request is
  * admitted when its footprint fits the budget (its reference tables unless
  * resident, its mask of n_tmpl*H*W bytes, 16 bytes per list entry of
- * capacity, and the lane's scale-bit workspace of 4*n_tmpl*H*W bytes),
+ * capacity, and the lane's emission workspace of about 8*n_tmpl*H*W bytes),
  * evicting least recently used resident references that no queued or
  * running request needs (a request that does not fit waits for running
  * work to finish or for results to be released).  Every queued request on the same reference that
@@ -543,8 +545,14 @@ int oss_autotune_batched(oss_ctx *ctx, const oss_ref *ref, const oss_template_fe
  * tolerance and feature set); each request then gets its own compaction into
  * its own mask and list, so its result is identical to a screen of that
  * request alone.  Work of different references runs concurrently on the
- * lanes.  This is an addition to the paper's method (its Algorithm 1 screens
- * one reference against one template).
+ * lanes: requests submitted while launches run are admitted as lanes and
+ * memory free up, and the server's own device memory (lane workspaces,
+ * output blocks, reference tables) is allocated and freed in stream order on
+ * the lanes' streams, so scheduling never waits for the whole device.  A
+ * queued request can be cancelled, and one that waits longer than the
+ * configured queue timeout fails with OSS_E_TIMEOUT instead of running.
+ * This is an addition to the paper's method (its Algorithm 1 screens one
+ * reference against one template).
  * ------------------------------------------------------------------------ */
 typedef struct oss_server oss_server;
 
@@ -553,6 +561,8 @@ typedef struct oss_server_config {
     int32_t lanes;                /* concurrent lanes, 1..8 */
     int32_t max_batch_templates;  /* templates per merged launch (>= 1); a
                                      request with more still runs alone */
+    int64_t queue_timeout_ns;     /* a request still queued this long after its
+                                     arrival fails with OSS_E_TIMEOUT (0: none) */
 } oss_server_config;
 
 typedef struct oss_request {
@@ -614,6 +624,12 @@ int oss_server_pump(oss_server *srv, int64_t wait_us, int32_t *n_completed);
 /* Pump until no request is queued or running.  OSS_E_NOMEM if queued
  * requests cannot be admitted until completed results are released. */
 int oss_server_drain(oss_server *srv);
+
+/* Cancel a queued request: it leaves the queue and completes with status
+ * OSS_E_CANCELLED (release it as any other).  OSS_E_STATE if it has been
+ * launched or has finished (a running launch is not interrupted; its result
+ * arrives as usual), OSS_E_ARG for an unknown id or a null server. */
+int oss_server_cancel(oss_server *srv, int64_t id);
 
 /* Status and output of a request (status OSS_E_STATE while pending). */
 int oss_server_result(oss_server *srv, int64_t id, oss_result *out);

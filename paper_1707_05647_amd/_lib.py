@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboss.so")
 
 OSS_OK, OSS_E_ARG, OSS_E_NOMEM, OSS_E_OVERFLOW, OSS_E_DEVICE, OSS_E_STATE = 0, -1, -2, -3, -4, -5
-OSS_E_LIMIT = -6
+OSS_E_LIMIT, OSS_E_CANCELLED, OSS_E_TIMEOUT = -6, -7, -8
 OSS_U8, OSS_U16 = 0, 1
 OSS_F_SUM, OSS_F_SQ, OSS_F_GRAD, OSS_F_ALL = 1, 2, 4, 7
 OSS_F_XMOM, OSS_F_YMOM, OSS_F_MOMENTS = 8, 16, 24
@@ -32,7 +32,7 @@ EXPORTED = [
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
     "oss_ref_layout", "oss_region", "oss_template_moments", "oss_screen_moments", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
-    "oss_screen_noalloc",
+    "oss_screen_noalloc", "oss_server_cancel",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_OPT_TABLE_PLANAR = 5
@@ -92,7 +92,7 @@ class oss_template_mom(C.Structure):
 
 class oss_server_config(C.Structure):
     _fields_ = [("memory_budget", C.c_int64), ("lanes", C.c_int32),
-                ("max_batch_templates", C.c_int32)]
+                ("max_batch_templates", C.c_int32), ("queue_timeout_ns", C.c_int64)]
 
 
 class oss_request(C.Structure):
@@ -191,6 +191,7 @@ def load(path: str | None = None):
     lib.oss_server_drain.argtypes = [vp]
     lib.oss_server_result.argtypes = [vp, i64, C.POINTER(oss_result)]
     lib.oss_server_release.argtypes = [vp, i64]
+    lib.oss_server_cancel.argtypes = [vp, i64]
     lib.oss_server_stats_read.argtypes = [vp, C.POINTER(oss_server_stats)]
     for name in EXPORTED:
         if name != "oss_status_string":
@@ -415,9 +416,10 @@ def oss_autotune_batched(ctx: int, ref: int, tmpl, probes, tol, feat_mask: int,
 # --- serving loop -----------------------------------------------------------
 
 def oss_server_create(device: int, memory_budget: int, lanes: int = 2,
-                      max_batch_templates: int = 64) -> int:
+                      max_batch_templates: int = 64, queue_timeout_ns: int = 0) -> int:
     h = C.c_void_p()
-    cfg = oss_server_config(int(memory_budget), int(lanes), int(max_batch_templates))
+    cfg = oss_server_config(int(memory_budget), int(lanes), int(max_batch_templates),
+                            int(queue_timeout_ns))
     _check(load().oss_server_create(int(device), C.byref(cfg), C.byref(h)), "oss_server_create")
     return h.value
 
@@ -452,6 +454,10 @@ def oss_server_result(srv: int, rid: int) -> oss_result:
     out = oss_result()
     _check(load().oss_server_result(srv, int(rid), C.byref(out)), "oss_server_result")
     return out
+
+
+def oss_server_cancel(srv: int, rid: int):
+    _check(load().oss_server_cancel(srv, int(rid)), "oss_server_cancel")
 
 
 def oss_server_release(srv: int, rid: int):

@@ -89,6 +89,24 @@ bool oss::desc_ok(const oss_image_desc *d)
     return true;
 }
 
+// Device allocation and release: in stream order on `async` when given (a
+// context used on that stream only), else plain (a free synchronises the
+// device).
+static hipError_t dev_alloc(void **p, size_t bytes, hipStream_t async)
+{
+    return async ? hipMallocAsync(p, bytes, async) : hipMalloc(p, bytes);
+}
+
+static void dev_free(void *p, hipStream_t async)
+{
+    if (!p)
+        return;
+    if (async)
+        (void)hipFreeAsync(p, async);
+    else
+        (void)hipFree(p);
+}
+
 static int hip_status(hipError_t e) { return e == hipSuccess ? OSS_OK : OSS_E_DEVICE; }
 
 extern "C" {
@@ -103,6 +121,8 @@ const char *oss_status_string(int status)
     case OSS_E_DEVICE: return "OSS_E_DEVICE";
     case OSS_E_STATE: return "OSS_E_STATE";
     case OSS_E_LIMIT: return "OSS_E_LIMIT";
+    case OSS_E_CANCELLED: return "OSS_E_CANCELLED";
+    case OSS_E_TIMEOUT: return "OSS_E_TIMEOUT";
     default: return "OSS_E_UNKNOWN";
     }
 }
@@ -143,8 +163,7 @@ int oss_ctx_destroy(oss_ctx *ctx)
     if (!ctx)
         return OSS_E_ARG;
     (void)hipSetDevice(ctx->device);
-    ctx->prof.on = false;
-    (void)ctx->prof.resolve();
+    hipStream_t as = ctx->alloc_stream;
     for (auto &s : ctx->slots) {
         if (s.ev) {
             if (s.used)
@@ -153,15 +172,13 @@ int oss_ctx_destroy(oss_ctx *ctx)
         }
         if (s.host)
             (void)hipHostFree(s.host);
-        if (s.dev)
-            (void)hipFree(s.dev);
+        dev_free(s.dev, as);
     }
-    if (ctx->bits)
-        (void)hipFree(ctx->bits);
-    if (ctx->ews)
-        (void)hipFree(ctx->ews);
-    if (ctx->rws)
-        (void)hipFree(ctx->rws);
+    dev_free(ctx->bits, as);
+    dev_free(ctx->ews, as);
+    dev_free(ctx->rws, as);
+    if (as)
+        (void)hipStreamSynchronize(as);
     delete ctx;
     return OSS_OK;
 }
@@ -284,7 +301,8 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
     r->geom = ref_geom(desc, feat_mask, r->max_radius, ctx->table_planar);
     size_t off[A_COUNT];
     r->bytes = ref_layout(r->geom, off);
-    if (hipMalloc(&r->mem, r->bytes) != hipSuccess) {
+    r->free_stream = ctx->alloc_stream;
+    if (dev_alloc(&r->mem, r->bytes, r->free_stream) != hipSuccess) {
         delete r;
         return OSS_E_NOMEM;
     }
@@ -323,8 +341,9 @@ int oss_ref_release(oss_ref *ref)
     if (!ref)
         return OSS_E_ARG;
     (void)hipSetDevice(ref->ctx->device);
-    if (ref->mem)
-        (void)hipFree(ref->mem);
+    // with stream-ordered tables the caller guarantees that no work reading
+    // them is still pending (or is ordered before the free on that stream)
+    dev_free(ref->mem, ref->free_stream);
     delete ref;
     return OSS_OK;
 }
@@ -585,19 +604,21 @@ int oss_feature_bounds(int32_t feature, int64_t FT, int32_t r, int32_t rho,
 
 }  // extern "C"
 
-// grow a device buffer (synchronising the device before freeing the old one)
-static int grow(void **p, size_t *cap, size_t need)
+// grow a device buffer; the old one may still be read by work enqueued on
+// the context's streams: without a stream of its own the context waits for
+// the device before freeing it, with one the free is ordered after that work
+static int grow(void **p, size_t *cap, size_t need, hipStream_t async)
 {
     if (*cap >= need)
         return OSS_OK;
     if (*p) {
-        if (hipDeviceSynchronize() != hipSuccess)
+        if (!async && hipDeviceSynchronize() != hipSuccess)
             return OSS_E_DEVICE;
-        (void)hipFree(*p);
+        dev_free(*p, async);
         *p = nullptr;
         *cap = 0;
     }
-    if (hipMalloc(p, need) != hipSuccess) {
+    if (dev_alloc(p, need, async) != hipSuccess) {
         *p = nullptr;
         return OSS_E_NOMEM;
     }
@@ -613,16 +634,18 @@ static int upload_plan(oss_ctx *ctx, const void *src, size_t bytes, hipStream_t 
     if (s.used && hipEventSynchronize(s.ev) != hipSuccess)
         return OSS_E_DEVICE;
     if (s.cap < bytes) {
+        // the slot's last use has completed (its event, above)
         if (s.host)
             (void)hipHostFree(s.host);
-        if (s.dev)
-            (void)hipFree(s.dev);
+        dev_free(s.dev, ctx->alloc_stream);
         s.host = s.dev = nullptr;
         s.cap = 0;
         if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess)
             return OSS_E_NOMEM;
-        if (hipMalloc(&s.dev, bytes) != hipSuccess)
+        if (dev_alloc(&s.dev, bytes, ctx->alloc_stream) != hipSuccess) {
+            s.dev = nullptr;
             return OSS_E_NOMEM;
+        }
         s.cap = bytes;
     }
     std::memcpy(s.host, src, bytes);
@@ -704,6 +727,29 @@ void oss::template_plan(const oss_ref *ref, const oss_template_feat &tf, int32_t
     pl->n_radii = nr;
 }
 
+int oss::reserve_plan_slots(oss_ctx *ctx, size_t bytes)
+{
+    for (PlanSlot &s : ctx->slots) {
+        if (s.cap >= bytes)
+            continue;
+        if (s.used && hipEventSynchronize(s.ev) != hipSuccess)
+            return OSS_E_DEVICE;
+        if (s.host)
+            (void)hipHostFree(s.host);
+        dev_free(s.dev, ctx->alloc_stream);
+        s.host = s.dev = nullptr;
+        s.cap = 0;
+        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess)
+            return OSS_E_NOMEM;
+        if (dev_alloc(&s.dev, bytes, ctx->alloc_stream) != hipSuccess) {
+            s.dev = nullptr;
+            return OSS_E_NOMEM;
+        }
+        s.cap = bytes;
+    }
+    return OSS_OK;
+}
+
 // Build the per-template plans.
 static int make_plans(const oss_ref *ref, const oss_template_feat *tmpl, int32_t n_tmpl,
                       const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
@@ -746,11 +792,12 @@ int oss::screen_workspace(oss_ctx *ctx, int64_t n_tmpl, int H, int W, bool carry
 {
     if (carry) {
         int rc = grow(reinterpret_cast<void **>(&ctx->bits), &ctx->bits_cap,
-                      (size_t)n_tmpl * H * W * sizeof(uint32_t));
+                      (size_t)n_tmpl * H * W * sizeof(uint32_t), ctx->alloc_stream);
         if (rc != OSS_OK)
             return rc;
     }
-    return grow(&ctx->ews, &ctx->ews_cap, emit_workspace_bytes(n_tmpl, H, W));
+    return grow(&ctx->ews, &ctx->ews_cap, emit_workspace_bytes(n_tmpl, H, W),
+                ctx->alloc_stream);
 }
 
 EmitOut oss::emit_out(oss_ctx *ctx, int64_t n_tmpl, int H, int W, void **scan_ws)
@@ -1356,7 +1403,7 @@ extern "C" int oss_region(oss_ctx *ctx, int32_t H, int32_t W, int32_t n_tmpl,
     const size_t o_ind = (tb + 255) / 256 * 256;
     const size_t o_hit = o_ind + ((size_t)Hp * Wp + 255) / 256 * 256;
     const size_t total = o_hit + (size_t)Hp * Wp;
-    int rc = grow(&ctx->rws, &ctx->rws_cap, total);
+    int rc = grow(&ctx->rws, &ctx->rws_cap, total, ctx->alloc_stream);
     if (rc != OSS_OK)
         return rc;
     char *m = static_cast<char *>(ctx->rws);
@@ -1757,6 +1804,7 @@ extern "C" int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_te
             return OSS_E_ARG;
     }
     const __int128 Q = tol->Q;
+    const int64_t maxv = ((int64_t)1 << ref->desc.bit_depth) - 1;  // largest pixel value
     for (int t = 0; t < n_tmpl; ++t) {
         auto &v = per[t];
         std::stable_sort(v.begin(), v.end(),
@@ -1783,10 +1831,26 @@ extern "C" int oss_screen_moments(oss_ctx *ctx, const oss_ref *ref, const oss_te
             dp.tests = (int32_t)tests;
             const __int128 A_r = star_area(r);
             feature_bounds(0, T.F1, r, T.rho, tol->P[0], tol->Q, &dp.lo1, &dp.hi1);
-            // variance: (Q-P) VT A(r)^2 <= Q V A(rho)^2 <= (Q+P) VT A(r)^2
+            if (tests & OSS_T_VAR) {
+                // the kernel forms V = A(r) F2 - F1^2 in int64: both terms are
+                // at most A(r)^2 maxv^2, which must stay below 2^63
+                const long double a2m2 = (long double)A_r * (long double)A_r *
+                                         (long double)maxv * (long double)maxv;
+                if (a2m2 >= 9.2e18L)
+                    return OSS_E_OVERFLOW;
+            }
+            // variance: (Q-P) VT A(r)^2 <= Q V A(rho)^2 <= (Q+P) VT A(r)^2,
+            // the products checked against 128 bits (VT >= 0)
             const __int128 den_v = Q * A_rho * A_rho;
-            dp.loV = ceil_div_i128((Q - tol->P[1]) * VT * A_r * A_r, den_v);
-            dp.hiV = floor_div_i128((Q + tol->P[1]) * VT * A_r * A_r, den_v);
+            const u128 vt = VT > 0 ? (u128)VT : 0;
+            const u128 ar2 = (u128)A_r * (u128)A_r;
+            const __int128 qmv = Q - tol->P[1];
+            u128 lo_v = 0, hi_v = 0;
+            if (!mul3((u128)(Q + tol->P[1]), vt, ar2, &hi_v) ||
+                !mul3(qmv > 0 ? (u128)qmv : 0, vt, ar2, &lo_v))
+                return OSS_E_OVERFLOW;
+            dp.loV = qmv > 0 ? ceil_div_i128((__int128)lo_v, den_v) : INT64_MIN;
+            dp.hiV = floor_div_i128((__int128)hi_v, den_v);
             // magnitude: (Q-P)^2 MT N(r)^2 <= Q^2 M N(rho)^2 <= (Q+P)^2 MT N(r)^2
             const u128 N_r = (u128)r * (u128)A_r;
             const u128 qp = (u128)(Q + tol->P[2]), qm = Q >= tol->P[2] ? (u128)(Q - tol->P[2]) : 0;

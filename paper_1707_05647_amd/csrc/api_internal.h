@@ -41,6 +41,10 @@ struct oss_ctx {
     int build_stream = 1;          // OSS_OPT_BUILD_STREAM
     void *rws = nullptr;           // preserved-region workspace (tables of the padded
     size_t rws_cap = 0;            // indicator image, the image, the star pass output)
+    // a context used on one stream only (a serving lane): its workspaces,
+    // plan buffers and reference tables are allocated and freed in stream
+    // order on that stream, so growing them never synchronises the device
+    hipStream_t alloc_stream = nullptr;
 };
 
 struct oss_ref {
@@ -51,6 +55,7 @@ struct oss_ref {
     oss::BuildGeom geom{};
     void *mem = nullptr;  // one allocation for everything below
     size_t bytes = 0;
+    hipStream_t free_stream = nullptr;  // stream-ordered allocation: freed on this stream
     oss::BuildBuffers bb{};
 };
 
@@ -103,6 +108,10 @@ int check_screen_args(oss_ctx *ctx, const oss_ref *ref, const oss_template_feat 
 void template_plan(const oss_ref *ref, const oss_template_feat &tf, int32_t t,
                    const oss_probe *probes, int32_t n_probes, const oss_tolerance *tol,
                    uint32_t fm, DevTemplatePlan *pl);
+
+// Grow every plan slot of ctx to at least `bytes` now (a serving lane does
+// this once, so its launches do not grow slots later).
+int reserve_plan_slots(oss_ctx *ctx, size_t bytes);
 
 // Look up the no-allocation screen's scratch on `device` (current), once per
 // device; called when a context is created.

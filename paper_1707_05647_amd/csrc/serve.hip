@@ -108,6 +108,7 @@ bool same_desc(const oss_image_desc &a, const oss_image_desc &b)
 }
 
 constexpr int COUNT_SLOTS = 4096;
+constexpr size_t PLAN_RESERVE = (size_t)1 << 20;  // plan bytes per slot, reserved at create
 
 }  // namespace
 
@@ -155,7 +156,10 @@ void drop_res(oss_server *s, Resident *r)
     s->res.erase(s->res.begin() + (r - s->res.data()));
 }
 
-void *alloc_out(oss_server *s, size_t bytes, size_t *got)
+// Output blocks, evicted tables and idle lanes' workspaces are allocated
+// and freed in stream order (on the lane that schedules), so admission never
+// waits for the whole device.
+void *alloc_out(oss_server *s, size_t bytes, size_t *got, hipStream_t st)
 {
     // smallest cached block that is large enough and not more than twice the need
     int best = -1;
@@ -170,17 +174,17 @@ void *alloc_out(oss_server *s, size_t bytes, size_t *got)
         return p;
     }
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess)
+    if (hipMallocAsync(&p, bytes, st) != hipSuccess)
         return nullptr;
     s->account((ptrdiff_t)bytes);
     *got = bytes;
     return p;
 }
 
-void free_cache(oss_server *s)
+void free_cache(oss_server *s, hipStream_t st)
 {
     for (FreeBlock &b : s->cache) {
-        (void)hipFree(b.p);
+        (void)hipFreeAsync(b.p, st);
         s->account(-(ptrdiff_t)b.bytes);
     }
     s->cache.clear();
@@ -194,7 +198,7 @@ bool make_room(oss_server *s, size_t need, uint64_t keep, bool keep_valid, int l
     const size_t budget = (size_t)s->cfg.memory_budget;
     if (s->in_use + need <= budget)
         return true;
-    free_cache(s);
+    free_cache(s, s->lanes[lane].st);
     while (s->in_use + need > budget) {
         Resident *victim = nullptr;
         for (Resident &r : s->res)
@@ -210,9 +214,9 @@ bool make_room(oss_server *s, size_t need, uint64_t keep, bool keep_valid, int l
             continue;
         const size_t b = s->lane_ws(l);
         if (l.ctx->bits)
-            (void)hipFree(l.ctx->bits);
+            (void)hipFreeAsync(l.ctx->bits, l.st);
         if (l.ctx->ews)
-            (void)hipFree(l.ctx->ews);
+            (void)hipFreeAsync(l.ctx->ews, l.st);
         l.ctx->bits = nullptr;
         l.ctx->ews = nullptr;
         l.ctx->bits_cap = l.ctx->ews_cap = 0;
@@ -359,9 +363,27 @@ bool any_busy(const oss_server *s)
     return false;
 }
 
+// Queued requests that waited longer than the server's queue timeout fail.
+void expire(oss_server *s)
+{
+    if (s->cfg.queue_timeout_ns <= 0 || s->queue.empty())
+        return;
+    const int64_t now = now_ns();
+    for (size_t i = 0; i < s->queue.size();) {
+        Req *q = s->queue[i];
+        if (now - q->t_arr > s->cfg.queue_timeout_ns) {
+            fail(s, q, OSS_E_TIMEOUT);
+            s->queue.erase(s->queue.begin() + (ptrdiff_t)i);
+        } else {
+            ++i;
+        }
+    }
+}
+
 // Admit and launch queued work on free lanes, oldest request first.
 void schedule(oss_server *s)
 {
+    expire(s);
     for (int li = 0; li < (int)s->lanes.size() && !s->queue.empty(); ++li) {
         Lane &l = s->lanes[li];
         if (l.busy)
@@ -450,7 +472,7 @@ void schedule(oss_server *s)
         // outputs
         bool ok = true;
         for (Req *q : batch) {
-            q->out = alloc_out(s, q->out_bytes, &q->blk_bytes);
+            q->out = alloc_out(s, q->out_bytes, &q->blk_bytes, l.st);
             if (!q->out) {
                 ok = false;
                 break;
@@ -530,7 +552,7 @@ extern "C" {
 int oss_server_create(int device, const oss_server_config *cfg, oss_server **out)
 {
     if (!out || !cfg || cfg->memory_budget <= 0 || cfg->lanes < 1 || cfg->lanes > 8 ||
-        cfg->max_batch_templates < 1)
+        cfg->max_batch_templates < 1 || cfg->queue_timeout_ns < 0)
         return OSS_E_ARG;
     *out = nullptr;
     oss_server *s = new (std::nothrow) oss_server();
@@ -547,6 +569,12 @@ int oss_server_create(int device, const oss_server_config *cfg, oss_server **out
         if (hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess)
             rc = OSS_E_DEVICE;
+        if (rc == OSS_OK) {
+            // the lane's context allocates in stream order on its stream, and
+            // its plan slots are sized once for the largest merged launch
+            l.ctx->alloc_stream = l.st;
+            rc = reserve_plan_slots(l.ctx, PLAN_RESERVE);
+        }
         s->lanes.push_back(l);
     }
     if (rc == OSS_OK && hipHostMalloc(reinterpret_cast<void **>(&s->counts),
@@ -574,25 +602,34 @@ int oss_server_destroy(oss_server *s)
     for (Lane &l : s->lanes)
         if (l.st)
             (void)hipStreamSynchronize(l.st);
+    hipStream_t st0 = s->lanes.empty() ? nullptr : s->lanes[0].st;
+    auto free_block = [&](void *p) {
+        if (st0)
+            (void)hipFreeAsync(p, st0);
+    };
     for (auto &kv : s->reqs) {
         if (kv.second->out)
-            (void)hipFree(kv.second->out);
+            free_block(kv.second->out);
         delete kv.second;
     }
     for (FreeBlock &b : s->cache)
-        (void)hipFree(b.p);
+        free_block(b.p);
     for (Resident &r : s->res) {
         if (r.ready)
             (void)hipEventDestroy(r.ready);
         (void)oss_ref_release(r.ref);
     }
+    // each context frees its own stream-ordered buffers and waits for them,
+    // before its stream goes
     for (Lane &l : s->lanes) {
         if (l.done)
             (void)hipEventDestroy(l.done);
-        if (l.st)
-            (void)hipStreamDestroy(l.st);
         if (l.ctx)
             (void)oss_ctx_destroy(l.ctx);
+        if (l.st) {
+            (void)hipStreamSynchronize(l.st);
+            (void)hipStreamDestroy(l.st);
+        }
     }
     if (s->counts)
         (void)hipHostFree(s->counts);
@@ -687,6 +724,21 @@ int oss_server_drain(oss_server *s)
         if (!s->queue.empty() && !any_busy(s))
             return OSS_E_NOMEM;  // queued work waits for results to be released
     }
+    return OSS_OK;
+}
+
+int oss_server_cancel(oss_server *s, int64_t id)
+{
+    if (!s)
+        return OSS_E_ARG;
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end())
+        return OSS_E_ARG;
+    Req *q = it->second;
+    if (q->state != RQ_QUEUED)
+        return OSS_E_STATE;
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), q));
+    fail(s, q, OSS_E_CANCELLED);
     return OSS_OK;
 }
 

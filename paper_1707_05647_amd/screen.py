@@ -157,8 +157,9 @@ class Server:
     by device-memory footprint, resident-reference cache, merged launches."""
 
     def __init__(self, device: int = 0, memory_budget: int = 64 << 30, lanes: int = 2,
-                 max_batch_templates: int = 64):
-        self.handle = L.oss_server_create(device, memory_budget, lanes, max_batch_templates)
+                 max_batch_templates: int = 64, queue_timeout_ns: int = 0):
+        self.handle = L.oss_server_create(device, memory_budget, lanes, max_batch_templates,
+                                          queue_timeout_ns)
         self._pixels = {}  # request id -> device pixels kept alive until release
 
     def submit(self, ref_key: int, pixels, templates, probes, tol, feat_mask: int,
@@ -193,6 +194,10 @@ class Server:
         if n:
             c[:, 3] &= 0xFFFFFFFF
         return mask, c, r.count
+
+    def cancel(self, rid: int):
+        """Cancel a queued request (it completes with OSS_E_CANCELLED)."""
+        L.oss_server_cancel(self.handle, rid)
 
     def release(self, rid: int):
         L.oss_server_release(self.handle, rid)

@@ -41,6 +41,27 @@ def test_status_strings(lib):
     assert lib.status_string(0) == "OSS_OK"
     assert lib.status_string(-1) == "OSS_E_ARG"
     assert lib.status_string(-3) == "OSS_E_OVERFLOW"
+    assert lib.status_string(lib.OSS_E_LIMIT) == "OSS_E_LIMIT"
+    assert lib.status_string(lib.OSS_E_CANCELLED) == "OSS_E_CANCELLED"
+    assert lib.status_string(lib.OSS_E_TIMEOUT) == "OSS_E_TIMEOUT"
+
+
+def test_status_codes_match_header(lib):
+    hdr = open(os.path.join(ROOT, "include", "oss.h")).read()
+    for name, val in re.findall(r"#define (OSS_E_\w+) \((-\d+)\)", hdr):
+        assert getattr(lib, name) == int(val), name
+
+
+def test_server_calls_refuse_a_null_server(lib):
+    """Argument errors of the serving calls come back before any device work
+    (no GPU needed)."""
+    raw = lib.load()
+    assert raw.oss_server_cancel(None, 1) == lib.OSS_E_ARG
+    assert raw.oss_server_release(None, 1) == lib.OSS_E_ARG
+    assert raw.oss_server_pump(None, 0, None) == lib.OSS_E_ARG
+    cfg = lib.oss_server_config(1 << 30, 1, 8, -1)  # negative queue timeout
+    out = C.c_void_p()
+    assert raw.oss_server_create(0, C.byref(cfg), C.byref(out)) == lib.OSS_E_ARG
 
 
 def test_ref_bytes(lib):

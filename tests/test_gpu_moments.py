@@ -92,3 +92,41 @@ def test_moments_mean_and_magnitude_only(runner):
     want = om.screen_full(img, tms, probes, (0, 0, 0), 1, 5)
     assert np.array_equal(lst, oc.mask_and_list(want)[1])
     assert mask[0, 55, 60] == 1 and mask[1, 70, 90] == 1
+
+
+def _var_limit_radius(maxv):
+    """Largest radius whose variance terms A(r)^2 maxv^2 stay below the
+    library's int64 bound (9.2e18, just under 2^63)."""
+    r = 1
+    while oc.star_area(r + 1) ** 2 * maxv * maxv < 9.2e18:
+        r += 1
+    return r
+
+
+def test_moments_16bit_variance_at_its_limit(runner):
+    """16-bit data at the largest radius whose int64 variance terms cannot
+    overflow: element by element equal to the oracle (exact integers); one
+    radius more is refused with OSS_E_OVERFLOW before anything runs."""
+    L = runner.L
+    r_ok = _var_limit_radius(65535)
+    H, W = 2 * r_ok + 27, 2 * r_ok + 45
+    img = (blob_image(H, W, make_rng(97, 0), blobs_per_512sq=1500, sig_hi=12,
+                      depth=12).astype(np.uint32) * 16).astype(np.uint16)
+    cy, cx = H // 2, W // 2
+    tms = [(cut_patch(img, cx, cy, r_ok), r_ok)]
+    probes = [(0, 0, r_ok)]
+    say(f"  16-bit variance limit radius {r_ok} on {H}x{W}")
+    n = _check(runner, img, tms, probes, (6, 30, 40, 100), 7, 27, 16, r_ok)
+    assert n > 0
+    # one radius more: the template features at r_ok + 1 need a bigger cut
+    img2 = np.zeros((H + 4, W + 4), np.uint16)
+    img2[:H, :W] = img
+    ref = runner.ctx.reference(L.device_image(img2, runner.dev), 27, 16, max_radius=r_ok + 1)
+    tm = [L.oss_template_moments(cut_patch(img2, cx + 1, cy + 1, r_ok + 1), r_ok + 1,
+                                 bit_depth=16)]
+    count = runner.torch.zeros(1, dtype=runner.torch.int64, device=runner.dev)
+    with pytest.raises(L.OssError) as e:
+        L.oss_screen_moments(runner.ctx.handle, ref.handle, tm, [(0, 0, r_ok + 1)],
+                             (6, 30, 40, 100), 7, None, None, 0, count)
+    assert e.value.status == L.OSS_E_OVERFLOW
+    ref.release()
