@@ -281,8 +281,9 @@ int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the
  * largest radius whose star fits, less one when OSS_F_GRAD is requested (the
- * template's border pixels have a clamped gradient).  Algorithm 1,
- * "features(Z)" of the template loop. */
+ * template's border pixels have a clamped gradient); with OSS_F_GRAD a star
+ * touching the border is refused (OSS_E_ARG).  Algorithm 1, "features(Z)"
+ * of the template loop. */
 int oss_template_features(const void *host_pixels, const oss_image_desc *desc, int32_t rho,
                           uint32_t feat_mask, oss_template_feat *out);
 

@@ -462,9 +462,13 @@ int oss_template_features(const void *host_pixels, const oss_image_desc *desc, i
     const int H = desc->H, W = desc->W;
     const int cx = (W - 1) / 2, cy = (H - 1) / 2;
     const int rmax = std::min(std::min(cx, W - 1 - cx), std::min(cy, H - 1 - cy));
+    // with the gradient the star must keep off the template's border: a tip
+    // on the border sees a clamped gradient there that the same pixel inside
+    // the reference does not have, and an exact copy could then fail
+    const int rcap = rmax - ((feat_mask & OSS_F_GRAD) ? 1 : 0);
     if (rho < 0)
-        rho = rmax - ((feat_mask & OSS_F_GRAD) ? 1 : 0);
-    if (rho < 0 || rho > rmax)
+        rho = rcap;
+    if (rho < 0 || rho > rcap)
         return OSS_E_ARG;
     star_feats_at(host_pixels, desc, cx, cy, rho, feat_mask, out->F);
     out->rho = rho;
