@@ -62,10 +62,15 @@ def test_batched_equals_oracle_cfg3(runner, bucket):
 @pytest.mark.parametrize("n_t", [40, 70])
 def test_batched_equals_plain_many_templates(runner, n_t):
     """40 templates: one group, its slots 32.. in the second register half;
-    70: two groups (64 + 6)."""
+    70: two groups (64 + 6).  The per-template screen equals the oracle;
+    every batched launch shape equals it."""
     w = make_workload(3, 2, H=192, W=224, n_templates=n_t, blobs_per_512sq=1500, sig_hi=16)
     say(f"batched vs plain: {len(w.templates)} templates, {len(w.probes)} probes")
     a = _screen(runner, w, False)
+    want = oc.screen_full(w.ref, [(t.pixels, t.rho) for t in w.templates],
+                          sorted(w.probes, key=lambda p: p[2]), w.feat_mask, w.tol_P, w.tol_Q)
+    wmask, wlist = oc.mask_and_list(want)
+    assert a[2] == len(wlist) and np.array_equal(a[0], wmask) and np.array_equal(a[1], wlist)
     for opts in ({}, {runner.L.OSS_OPT_BATCH_BUCKET: 2},
                  {runner.L.OSS_OPT_STAR_STRIP: 128, runner.L.OSS_OPT_STAR_BLOCKS_PER_XCD: 5}):
         b = _with_options(runner, opts, lambda: _screen(runner, w, True))

@@ -8,7 +8,9 @@ launch shape.  The oracle cannot screen these images whole, so:
     bits of every template, read from the candidate list, and the mask are
     bit-exact against the oracle;
   * everywhere: the list is strictly increasing in (t, y, x), holds exactly
-    the mask's positions, and carries non-zero scale bits.
+    the mask's positions, and carries non-zero scale bits;
+  * every position of a 64-row band (all columns for the 8192^2 workload,
+    4096 columns for the 16384^2 one) bit-exact against the oracle.
 """
 import numpy as np
 import pytest
@@ -48,7 +50,38 @@ def _sample(w, n, rng):
     return xs, ys
 
 
-def _full_size(runner, cfg, planar, n_sample):
+def _band_check(w, T, HW, c, keys, mask, y0, dev, x0=0, x1=None):
+    """A 64-row band, every position of columns [x0, x1): the oracle's scale
+    bits of every template against the list's, and the mask."""
+    import torch
+    y1 = min(w.H, y0 + 64)
+    x1 = w.W if x1 is None else x1
+    ys, xs = np.mgrid[y0:y1, x0:x1]
+    xs = xs.ravel().astype(np.int32)
+    ys = ys.ravel().astype(np.int32)
+    # probes sorted by radius: the oracle sums each star once per radius
+    probes = sorted(w.probes, key=lambda p: p[2])
+    say(f"  oracle on rows {y0}..{y1 - 1}, columns {x0}..{x1 - 1} ({len(xs)} positions)")
+    want = oc.screen_positions(w.ref, [(t.pixels, t.rho) for t in w.templates], probes,
+                               w.feat_mask, w.tol_P, w.tol_Q, xs, ys)
+    got = np.zeros_like(want)
+    bw = x1 - x0
+    for t in range(T):
+        a = int(torch.searchsorted(keys, torch.tensor([t * HW + y0 * w.W], device=dev)))
+        b = int(torch.searchsorted(keys, torch.tensor([t * HW + y1 * w.W], device=dev)))
+        sel = c[a:b].cpu().numpy().astype(np.int64)
+        sel = sel[(sel[:, 2] >= x0) & (sel[:, 2] < x1)]
+        if len(sel):
+            idx = (sel[:, 1] - y0) * bw + (sel[:, 2] - x0)
+            got[t, idx] = sel[:, 3].astype(np.uint32)
+    bad = np.argwhere(got != want)
+    assert len(bad) == 0, f"band rows {y0}..{y1 - 1}: {len(bad)} (t, position) pairs differ"
+    gm = mask[:, y0:y1, x0:x1].reshape(T, -1).cpu().numpy()
+    assert np.array_equal(gm, (want != 0).astype(np.uint8))
+    return int((want != 0).sum())
+
+
+def _full_size(runner, cfg, planar, n_sample, band):
     torch, L = runner.torch, runner.L
     dev = runner.dev
     h = runner.ctx.handle
@@ -115,14 +148,20 @@ def _full_size(runner, cfg, planar, n_sample):
               torch.from_numpy(xs.astype(np.int64)).to(dev)].cpu().numpy()
     assert np.array_equal(gm, (want != 0).astype(np.uint8))
     assert want.any(axis=1).all()  # every template has sampled candidates
+    nb = _band_check(w, T, HW, c, keys, mask, band[0], dev, band[1], band[2])
+    say(f"  band: {nb} candidates, bit-exact")
     del mask, cands, count, c, keys, pos
     torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("planar", [0, 1], ids=["interleaved", "planar"])
 def test_cfg3_full_size_sampled(runner, planar):
-    _full_size(runner, 3, planar, 400)
+    # the band: the top 64 rows, every column, where radii turn valid one by one
+    _full_size(runner, 3, planar, 400, (0, 0, None))
 
 
 def test_cfg5_full_size_sampled(runner):
-    _full_size(runner, 5, 1, 1500)
+    # the band: 64 rows through the middle (every radius valid), 4096 columns
+    # (eight 512-column strips: strip and XCD boundaries inside); every
+    # column of it would take minutes of oracle time
+    _full_size(runner, 5, 1, 1500, (16384 // 2 - 32, 6144, 10240))
