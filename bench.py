@@ -93,7 +93,6 @@ def algorithmic_bytes(H, W, n_tmpl, px_bytes, entry_bytes, n_cand=0):
         "star_batch": table + n_tmpl * hw,
         "star_moments": table + n_tmpl * hw,
         # writes the candidate list
-        "compact_write": 16 * n_cand,
         "compact_list": 16 * n_cand,
         "row_base": hw * px_bytes,
         "band_agg": hw * px_bytes,
@@ -576,8 +575,9 @@ def evaluate_regions(w, ctx, L, torch, dev, cands, count, cap):
 
 
 def copy_peak(torch, dev, mib=4096, reps=5):
-    """Achievable HBM rate: a plain device-to-device copy of `mib` MiB timed
-    with events (bytes read + bytes written per second, best of `reps`)."""
+    """Achievable HBM rates: a plain device-to-device copy of `mib` MiB timed
+    with events (bytes read + bytes written per second, best of `reps`), and
+    a fill of the same buffer (bytes written per second)."""
     src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -591,18 +591,31 @@ def copy_peak(torch, dev, mib=4096, reps=5):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         best = ms if best is None else min(best, ms)
+    # write-only: a fill of the same buffer (the rate a store-bound kernel,
+    # such as the table builder's final pass, can reach)
+    fbest = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.fill_(7)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        fbest = ms if fbest is None else min(fbest, ms)
     del src, dst
     torch.cuda.empty_cache()
     return {"GBps": 2.0 * (mib << 20) / (best / 1e3) / 1e9, "bytes_per_copy": 2 * (mib << 20),
-            "ms": best, "kernel": "torch device copy (read + write)"}
+            "ms": best, "kernel": "torch device copy (read + write)",
+            "fill_GBps": (mib << 20) / (fbest / 1e3) / 1e9, "fill_ms": fbest}
 
 
 def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_baseline=True,
               compare_plain=True):
     """Workloads 2, 3 and 5: the timed steps on one lane, then on `lanes`
-    lanes (the headline figure), the batched-over-plain comparison for the
-    batched workloads, the roofline figures and the sampled CPU oracle.
-    Returns the result dict."""
+    lanes (the faster of the two runs is the headline figure, both are
+    reported), the batched-over-plain comparison for the batched workloads,
+    the roofline figures and the sampled CPU oracle.  Returns the result
+    dict."""
     import torch
 
     from paper_1707_05647_amd import _lib as L
@@ -770,21 +783,31 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
         # batched against per-template launches, one lane each
         extra["plain_value"] = ps / (extra["plain_ms_per_step"] / 1e3) / 1e9
         extra["batched_over_plain"] = extra["plain_ms_per_step"] / (sec * 1e3)
+    def run_summary(s, pr, build_stream):
+        return {"value": ps / s / 1e9, "ms_per_step": s * 1e3, "build_stream": build_stream,
+                "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
+                            for k, v in pr.items()}}
+
+    timed_lanes = lanes
     if lanes >= 2 and sec:
-        # the timed figures below are the lanes' run; the single lane's are kept
-        extra["single_lane"] = {
-            "value": ps / sec / 1e9, "ms_per_step": sec * 1e3,
-            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
-            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)}
-                        for k, v in prof.items()}}
+        extra["single_lane"] = run_summary(
+            sec, prof, L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM))
     if lanes >= 2:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_BUILD_STREAM, lane_stream)
         print(f"workload {workload}: timed steps, {lanes} lanes", file=sys.stderr, flush=True)
         sub = argparse.Namespace(**vars(args))
         sub.steps, sub.warmup = steps, warmup
-        sec, prof, same = pipelined(sub, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r, cap,
-                                    batched_path, screen_step, n, mask, cands)
+        sec_l, prof_l, same = pipelined(sub, lanes, w, L, torch, dev, ctx, img, ref_fm, max_r,
+                                        cap, batched_path, screen_step, n, mask, cands)
         extra["lanes_identical_to_single_lane"] = same
+        extra["lanes_run"] = dict(run_summary(sec_l, prof_l, lane_stream), lanes=lanes)
+        if sec is None or sec_l < sec:
+            # the lanes' run is the headline (the single lane's figures are kept)
+            sec, prof = sec_l, prof_l
+        else:
+            # a star pass that fills the GPU alone gains nothing from a second
+            # lane beside it: the faster one-lane run is the headline
+            timed_lanes = 1
         value = ps / sec / 1e9
     eb = sum(b // 8 for _, b in ref.slots)  # table bytes per position, all quantities
     staged = (ref.plane_bytes > 0 and len(ref.slots) > 1 and not args.moments
@@ -811,9 +834,9 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
         "algorithmic_unit": "tables read once (entry bytes x 3 tables x (H+1)(W+1)) + uint8 "
                             "mask (templates x H x W)",
         "avg_ms": avg_s * 1e3,
-        "timed_on": f"{lanes} lanes" if lanes >= 2 else "one lane",
+        "timed_on": f"{timed_lanes} lanes" if timed_lanes >= 2 else "one lane",
     }
-    if "single_lane" in extra and dom in extra["single_lane"]["kernels"]:
+    if timed_lanes >= 2 and "single_lane" in extra and dom in extra["single_lane"]["kernels"]:
         one = extra["single_lane"]["kernels"][dom]["avg_ms"] / 1e3
         roof["one_lane"] = {"avg_ms": one * 1e3, "achieved": abytes[dom] / one / 1e9,
                             "frac": abytes[dom] / one / 1e9 / HBM_PEAK_GBPS}
@@ -859,10 +882,12 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
             "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
             "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
             "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
-            "build_stream": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM),
+            "build_stream": (extra["single_lane"]["build_stream"] if timed_lanes < lanes
+                             else L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BUILD_STREAM)),
             "batch_bucket": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_BATCH_BUCKET),
             "launch": "batched" if batched_path else "plain",
-            "lanes": lanes,
+            "lanes": timed_lanes,
+            "lanes_tried": lanes,
             "serial_screens": bool(args.serial_screens),
             "rings": args.rings,
             "alg1": bool(args.alg1),
@@ -1003,7 +1028,7 @@ def main(argv=None):
         w2 = run_fixed(args, 2, steps=max(args.steps, 20), warmup=args.warmup,
                        cpu_seconds=min(args.cpu_seconds, 5.0), evaluate=args.evaluate != 0)
         out["workload_2"] = nested(w2, ("value", "unit", "ms_per_step", "config", "roofline",
-                                        "kernels", "single_lane", "candidates",
+                                        "kernels", "single_lane", "lanes_run", "candidates",
                                         "pruned_patch_pct", "evaluation", "cpu_baseline",
                                         "lanes_identical_to_single_lane"))
         print("serving loop", file=sys.stderr, flush=True)
