@@ -135,15 +135,21 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                         continue;
                     }
                 }
+                // every hull lane of the wave inside the core passes every
+                // probe of the radius.  Up to 16 slots: the radius' bits per
+                // slot at once, from the core words.  Larger groups skip the
+                // probes' compares inside the one probe loop instead: a second
+                // site updating their accumulators held a second copy of them
+                // in registers (64 more for 64 slots: half the occupancy).
+                bool core_all = false;
                 if constexpr (!RINGS) {
-                    // every hull lane of the wave inside the core passes every
-                    // probe of the radius: the radius' bits per slot at once
                     if (rd.cb_first >= 0) {
                         bool inc = in;
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
                             inc = inc & (F[q] >= rd.clo[q]) & (F[q] <= rd.chi[q]);
-                        if (__builtin_amdgcn_ballot_w64(in && !inc) == 0) {
+                        core_all = __builtin_amdgcn_ballot_w64(in && !inc) == 0;
+                        if (MT <= 16 && core_all) {
                             const uint32_t *cb = core_bits + rd.cb_first;
 #pragma unroll
                             for (int t = 0; t < MT; ++t) {
@@ -162,10 +168,12 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                 {
                     for (int p = rd.first; p < rd.first + rd.count; ++p) {
                         const DevBatchProbe pr = probes[p];
-                        bool pass = true;
+                        bool pass = in;
+                        if (!core_all) {
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                            for (int q = 0; q < NQ; ++q)
+                                pass = pass & (F[q] >= pr.lo[q]) & (F[q] <= pr.hi[q]);
+                        }
                         const uint32_t bit = pass ? (1u << pr.k) : 0u;
                         if constexpr (RINGS) {
                             if (pr.ring)
