@@ -194,30 +194,27 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
             // the pass's scale bits per slot, with the bits carried in from
             // the group's earlier passes; a group's last pass emits them
             // (mask, segment counts, staged candidates), an earlier pass
-            // carries them on in scale-bit words
-            auto get = [&](int t) -> uint32_t {
-                return t < 32 ? acc[t < 32 ? t : 0] : acc_hi[t >= 32 ? t - 32 : 0];
-            };
+            // carries them on in scale-bit words.  (No lambda reads the
+            // accumulators: one capturing them by reference put them in
+            // scratch memory in the ring kernels.)
+            EmitRow er;
+            const bool emit = ps.last && emit_begin(eo, y, x, &er);
 #pragma unroll
             for (int t = 0; t < MT; ++t) {
                 if (t < nt) {
-                    uint32_t v = get(t);
+                    uint32_t v = t < 32 ? acc[t < 32 ? t : 0] : acc_hi[t >= 32 ? t - 32 : 0];
                     if constexpr (RINGS)
                         v &= ~fail[t];  // one pass per group: final here
-                    const int64_t wi = (int64_t)grp->tmap[t] * hw + (int64_t)y * W + x;
+                    const int tg = grp->tmap[t];
+                    const int64_t wi = (int64_t)tg * hw + (int64_t)y * W + x;
                     if (!ps.first && x < W)
                         v |= eo.dense[wi];
                     if (!ps.last && x < W)
                         eo.dense[wi] = v;
-                    if (t < 32)
-                        acc[t < 32 ? t : 0] = v;
-                    else
-                        acc_hi[t >= 32 ? t - 32 : 0] = v;
+                    if (emit)
+                        emit_slot(eo, er, y, x, v, tg, mask_of ? mask_of[tg] : nullptr);
                 }
             }
-            if (ps.last)
-                emit_row<MT>(eo, nt, y, x, get, [&](int t) { return grp->tmap[t]; },
-                             [&](int t) { return mask_of ? mask_of[grp->tmap[t]] : nullptr; });
         }
     }
 }

@@ -350,39 +350,59 @@ __device__ __forceinline__ int lane_rank(uint64_t ballot)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-// x: this lane's column (the wave covers a 64-aligned run of columns);
-// val(t) -> scale bits of slot t (compile-time t); tg(t) -> template index of
-// slot t in the screen; mk(t) -> its mask (or null); nt slots in use.  tg and
-// mk should read read-only kernel arguments (scalar loads): a vector load
-// here would wait for every store in flight, since one counter counts both.
+// Emission of one image row of a wave: x is this lane's column (the wave
+// covers a 64-aligned run of columns).  emit_begin is false for a wave wholly
+// right of the image (uniform); emit_slot then writes one template's mask
+// bytes, segment count and staged candidates from this lane's scale bits v.
+// tg is the template index of the slot in the screen, m its mask (or null);
+// both should come from read-only kernel arguments (scalar loads): a vector
+// load here would wait for every store in flight, since one counter counts
+// both.
+struct EmitRow {
+    int64_t srow;  // segment within a template
+    int64_t tseg;  // segments per template
+    int lane;
+    bool inw;      // this lane's column lies in the image
+};
+
+__device__ __forceinline__ bool emit_begin(const EmitOut &eo, int y, int x, EmitRow *er)
+{
+    er->lane = threadIdx.x & 63;
+    er->inw = x < eo.W;
+    er->srow = (int64_t)y * eo.n_chunks + (x >> 6);
+    er->tseg = (int64_t)eo.H * eo.n_chunks;
+    return x - er->lane < eo.W;
+}
+
+__device__ __forceinline__ void emit_slot(const EmitOut &eo, const EmitRow &er, int y, int x,
+                                          uint32_t v, int tg, uint8_t *m)
+{
+    const bool on = er.inw && v != 0u;
+    if (m && er.inw)
+        store_u8_global(m + (int64_t)y * eo.W + x, on ? 1 : 0);
+    if (eo.seg_count) {
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(on);
+        const int64_t seg = (int64_t)tg * er.tseg + er.srow;
+        if (er.lane == 0)
+            eo.seg_count[seg] = (uint8_t)__popcll(bal);
+        if (on)
+            eo.stage[seg * SEG_W + lane_rank(bal)] = make_uint2((uint32_t)x, v);
+    }
+}
+
+// The whole row for slots 0..nt-1: val(t) -> scale bits of slot t
+// (compile-time t), tg(t) -> template index, mk(t) -> mask (or null).
 template <int MT, typename Val, typename Tg, typename Mk>
 __device__ __forceinline__ void emit_row(const EmitOut &eo, int nt, int y, int x, Val val, Tg tg,
                                          Mk mk)
 {
-    const int lane = threadIdx.x & 63;
-    if (x - lane >= eo.W)
-        return;  // a wave wholly right of the image (uniform)
-    const bool inw = x < eo.W;
-    const int64_t srow = (int64_t)y * eo.n_chunks + (x >> 6);  // segment within a template
-    const int64_t tseg = (int64_t)eo.H * eo.n_chunks;          // segments per template
+    EmitRow er;
+    if (!emit_begin(eo, y, x, &er))
+        return;
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-        if (t < nt) {
-            const uint32_t v = val(t);
-            const bool on = inw && v != 0u;
-            uint8_t *m = mk(t);
-            if (m && inw)
-                store_u8_global(m + (int64_t)y * eo.W + x, on ? 1 : 0);
-            if (eo.seg_count) {
-                const uint64_t bal = __builtin_amdgcn_ballot_w64(on);
-                const int64_t seg = (int64_t)tg(t) * tseg + srow;
-                if (lane == 0)
-                    eo.seg_count[seg] = (uint8_t)__popcll(bal);
-                if (on)
-                    eo.stage[seg * SEG_W + lane_rank(bal)] = make_uint2((uint32_t)x, v);
-            }
-        }
-    }
+    for (int t = 0; t < MT; ++t)
+        if (t < nt)
+            emit_slot(eo, er, y, x, val(t), tg(t), mk(t));
 }
 
 // The sweep with at most as many blocks per XCD as the GPU holds at once for
