@@ -155,11 +155,17 @@ def cpu_baseline(w, bits_gpu, seconds: float, seed: int = 1, gpu_bits=None, gpu_
         return oc.screen_positions(w.ref, tm, w.probes, w.feat_mask, w.tol_P, w.tol_Q, xs, ys,
                                    G=G)
 
+    # size the sample from a probe run long enough (>= 0.5 s) that the
+    # oracle's fixed cost per call does not inflate the per-position time
     n0 = 512 if len(w.probes) > 50 else 4096
-    xs, ys = sample(n0)
-    t0 = time.perf_counter()
-    screen(xs, ys)
-    dt = max(time.perf_counter() - t0, 1e-4)
+    while True:
+        xs, ys = sample(n0)
+        t0 = time.perf_counter()
+        screen(xs, ys)
+        dt = max(time.perf_counter() - t0, 1e-4)
+        if dt >= 0.5 or n0 >= 2_000_000 or 4 * dt > seconds:
+            break
+        n0 *= 4
     n = int(max(n0, min(8_000_000, n0 * seconds / dt)))
     xs, ys = sample(n)
     t0 = time.perf_counter()
