@@ -254,7 +254,7 @@ def run_pipelined(lanes, make_lane, steps, warmup, L, torch):
 
 OPTIONS = ("OSS_OPT_STAR_STRIP", "OSS_OPT_STAR_BLOCKS_PER_XCD", "OSS_OPT_STAR_LDS",
            "OSS_OPT_BATCH_BUCKET", "OSS_OPT_TABLE_PLANAR", "OSS_OPT_STAR_PIPE",
-           "OSS_OPT_STAR_STAGED", "OSS_OPT_BUILD_STREAM")
+           "OSS_OPT_STAR_STAGED", "OSS_OPT_BUILD_STREAM", "OSS_OPT_TABLE_REC")
 
 
 _LANE_STREAMS = []
@@ -652,6 +652,8 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
         planar = 0
     if planar >= 0:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR, planar)
+    if args.table_rec >= 0:
+        L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_TABLE_REC, args.table_rec)
     if args.pipe >= 0:
         L.oss_ctx_set_option(ctx.handle, L.OSS_OPT_STAR_PIPE, args.pipe)
     if args.staged >= 0:
@@ -819,9 +821,8 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
     staged = (ref.plane_bytes > 0 and len(ref.slots) > 1 and not args.moments
               and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED) == 1
               and L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE) == 0)
-    # table bytes per entry as stored (64-bit squares in two 32-bit planes)
-    ebs = ref.entry_bytes * (len(ref.slots) + sum(1 for _, b in ref.slots if b == 64)) \
-        if ref.plane_bytes else ref.entry_bytes
+    # table bytes per entry as stored, over all planes
+    ebs = ref.stored_entry_bytes
     abytes = algorithmic_bytes(w.H, w.W, T, 2 if w.depth > 8 else 1, ebs, n_cand=n)
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1), "max_ms": v[2]}
             for k, v in prof.items()}
@@ -886,6 +887,8 @@ def run_fixed(args, workload, *, steps, warmup, cpu_seconds, evaluate, cpu_basel
                                                         L.OSS_OPT_STAR_BLOCKS_PER_XCD),
             "star_lds": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_LDS),
             "table_planar": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_PLANAR),
+            "table_rec": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_TABLE_REC),
+            "table_slot_bits": [b for _, b in ref.slots],
             "star_pipe": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_PIPE),
             "star_staged": L.oss_ctx_get_option(ctx.handle, L.OSS_OPT_STAR_STAGED),
             "build_stream": (extra["single_lane"]["build_stream"] if timed_lanes < lanes
@@ -978,6 +981,10 @@ def parse_args(argv=None):
     ap.add_argument("--planar", type=int, default=-1,
                     help="1/0: planar / interleaved tables; -1 = library default "
                          "(interleaved for workload 3, whose tolerances are loose)")
+    ap.add_argument("--table-rec", type=int, default=-1,
+                    help="1/0: record tables (squares' low words and gradients in 8-byte "
+                         "records, the squares' bits 32..39 in a byte plane) where they apply, "
+                         "or four 32-bit planes; -1 = library default (record)")
     ap.add_argument("--star-lds", type=int, default=-1,
                     help="1/0: star kernel with / without LDS staging; -1 = library default")
     ap.add_argument("--copy-probe-mb", type=int, default=0,

@@ -173,6 +173,18 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                on another stream keeps more of its lines
  *                                in L2 (default); 0: ordinary stores, faster
  *                                for a build that runs alone
+ *   OSS_OPT_TABLE_REC            1: planar references of the sum, the squares
+ *                                and the gradient whose squares' square and
+ *                                diamond sums stay below 2^40 (12-bit pixels
+ *                                up to radius ~180, 8-bit beyond the 32-bit
+ *                                limit) store the sum plane, one 8-byte
+ *                                record {squares low word, gradient} per
+ *                                entry and a byte plane of the squares' bits
+ *                                32..39: 13 bytes per entry instead of 16,
+ *                                and a staged star pass's second lookups
+ *                                read one record line and one byte line per
+ *                                lane instead of three plane lines
+ *                                (default); 0: four 32-bit planes
  * They change speed only, never results. */
 #define OSS_OPT_STAR_STRIP 1
 #define OSS_OPT_STAR_BLOCKS_PER_XCD 2
@@ -182,6 +194,7 @@ int oss_ctx_destroy(oss_ctx *ctx);
 #define OSS_OPT_STAR_PIPE 6
 #define OSS_OPT_STAR_STAGED 7
 #define OSS_OPT_BUILD_STREAM 8
+#define OSS_OPT_TABLE_REC 9
 int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value);
 int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value);
 
@@ -277,6 +290,30 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
  */
 int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
                    int32_t bits[OSS_MAX_QUANTITIES], int64_t *plane_bytes);
+/* (oss_ref_layout returns OSS_E_STATE for record tables, OSS_OPT_TABLE_REC:
+ * their quantities have different strides; oss_ref_layout_q describes every
+ * layout.) */
+
+/* Where one quantity of table entry e = (y+1) * pitch_entries + (x+1) sits,
+ * relative to the table pointer of oss_ref_tables: its low `bits` bits at
+ * byte offset + e * stride, and, when hi_bits > 0, its next hi_bits bits at
+ * byte hi_offset + e * hi_stride.  The value is stored modulo
+ * 2^(bits + hi_bits), which keeps every square and diamond sum of it exact
+ * (it is below that bound). */
+typedef struct oss_quantity_layout {
+    int64_t offset;
+    int32_t stride, bits;
+    int64_t hi_offset;  /* -1: no high part */
+    int32_t hi_stride, hi_bits;
+} oss_quantity_layout;
+
+/* The layout of each quantity slot q < *nq (feature order, enabled ones
+ * only) of the tables of `ref` (L, R and R' share it); slots q >= *nq get
+ * offset -1.  *plane_bytes: the first plane's size for planar tables (the
+ * distance between planes of equal width), 0 for interleaved entries.
+ * Host, synchronous. */
+int oss_ref_layout_q(const oss_ref *ref, oss_quantity_layout out[OSS_MAX_QUANTITIES],
+                     int32_t *nq, int64_t *plane_bytes);
 
 /* Template features (host, synchronous): the radius-rho star at the centre
  * of a host image, G taken on the template itself.  rho < 0 picks the

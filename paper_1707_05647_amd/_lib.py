@@ -32,12 +32,13 @@ EXPORTED = [
     "oss_ctx_set_option", "oss_ctx_get_option", "oss_screen_batched", "oss_autotune_batched",
     "oss_ref_layout", "oss_region", "oss_template_moments", "oss_screen_moments", "oss_screen_intervals", "oss_alg1_probes", "oss_template_features_rings", "oss_screen_rings", "oss_server_create", "oss_server_destroy", "oss_server_submit", "oss_server_pump",
     "oss_server_drain", "oss_server_result", "oss_server_release", "oss_server_stats_read",
-    "oss_screen_noalloc", "oss_server_cancel",
+    "oss_screen_noalloc", "oss_server_cancel", "oss_ref_layout_q",
 ]
 OSS_OPT_STAR_STRIP, OSS_OPT_STAR_BLOCKS_PER_XCD, OSS_OPT_STAR_LDS, OSS_OPT_BATCH_BUCKET = 1, 2, 3, 4
 OSS_OPT_TABLE_PLANAR = 5
 OSS_OPT_STAR_PIPE = 6
 OSS_OPT_STAR_STAGED = 7
+OSS_OPT_TABLE_REC = 9
 OSS_OPT_BUILD_STREAM = 8
 OSS_MAX_RINGS = 4
 OSS_TUNE_MAX = 64
@@ -58,6 +59,11 @@ class oss_probe(C.Structure):
 
 class oss_tolerance(C.Structure):
     _fields_ = [("P", C.c_int32 * 3), ("Q", C.c_int32)]
+
+
+class oss_quantity_layout(C.Structure):
+    _fields_ = [("offset", C.c_int64), ("stride", C.c_int32), ("bits", C.c_int32),
+                ("hi_offset", C.c_int64), ("hi_stride", C.c_int32), ("hi_bits", C.c_int32)]
 
 
 class oss_candidate(C.Structure):
@@ -153,6 +159,8 @@ def load(path: str | None = None):
                                    C.POINTER(i32)]
     lib.oss_ref_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
                                    C.POINTER(i64)]
+    lib.oss_ref_layout_q.argtypes = [vp, C.POINTER(oss_quantity_layout), C.POINTER(i32),
+                                     C.POINTER(i64)]
     lib.oss_template_features.argtypes = [vp, C.POINTER(oss_image_desc), i32, u32,
                                           C.POINTER(oss_template_feat)]
     lib.oss_feature_bounds.argtypes = [i32, i64, i32, i32, C.POINTER(oss_tolerance),
@@ -324,6 +332,18 @@ def oss_ref_layout(ref: int):
     _check(load().oss_ref_layout(ref, C.byref(eb), off, bits, C.byref(plane)), "oss_ref_layout")
     return (eb.value, [(off[q], bits[q]) for q in range(OSS_MAX_QUANTITIES) if bits[q]],
             plane.value)
+
+
+def oss_ref_layout_q(ref: int):
+    """([(offset, stride, bits, hi_offset, hi_stride, hi_bits) per quantity
+    slot], plane_bytes): hi_offset -1 means no high part; a value is stored
+    modulo 2^(bits + hi_bits)."""
+    out = (oss_quantity_layout * OSS_MAX_QUANTITIES)()
+    nq = C.c_int32()
+    plane = C.c_int64()
+    _check(load().oss_ref_layout_q(ref, out, C.byref(nq), C.byref(plane)), "oss_ref_layout_q")
+    return ([(o.offset, o.stride, o.bits, o.hi_offset, o.hi_stride, o.hi_bits)
+             for o in out[:nq.value]], plane.value)
 
 
 def oss_ref_tables(ref: int):

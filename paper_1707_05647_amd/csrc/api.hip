@@ -234,8 +234,13 @@ static int32_t resolve_max_radius(const oss_image_desc *d, int32_t max_radius)
 // sum of it up to the maximum radius stays below 2^32.  All quantities fit:
 // 32-bit values.  Only the squares do not: the squares in 64 bits, the others
 // in 32.  Otherwise 64-bit values.  Planar (the default) or interleaved
-// entries as the context asks.
-static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int planar)
+// entries as the context asks.  Planar tables of the sum, the squares and
+// the gradient whose squares' square and diamond sums stay below 2^40 use
+// the record layout when the context asks (rec): the squares' low words and
+// the gradient in one 8-byte record per entry, the squares' bits 32..39 in a
+// byte plane.
+static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int planar,
+                          int rec = 0)
 {
     const __int128 s = square_half(R);
     const __int128 area = std::max((2 * s + 1) * (2 * s + 1),
@@ -251,8 +256,11 @@ static BuildGeom ref_geom(const oss_image_desc *d, uint32_t fm, int32_t R, int p
     }
     if (fits(fm))
         return make_geom(d->H, d->W, nq, 4, -1, planar);
-    if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ))
-        return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0, planar);
+    if ((fm & OSS_F_SQ) && nq >= 2 && fits(fm & ~(uint32_t)OSS_F_SQ)) {
+        const bool sq40 = max_quantity(d, OSS_F_SQ) * area < ((__int128)1 << 40);
+        return make_geom(d->H, d->W, nq, 8, (fm & OSS_F_SUM) ? 1 : 0, planar,
+                         (rec && planar && fm == OSS_F_ALL && sq40) ? 1 : 0);
+    }
     return make_geom(d->H, d->W, nq, 8, -1, planar);
 }
 
@@ -298,7 +306,7 @@ int oss_ref_create(oss_ctx *ctx, const oss_image_desc *desc, uint32_t feat_mask,
     r->desc = *desc;
     r->feat_mask = feat_mask;
     r->max_radius = resolve_max_radius(desc, max_radius);
-    r->geom = ref_geom(desc, feat_mask, r->max_radius, ctx->table_planar);
+    r->geom = ref_geom(desc, feat_mask, r->max_radius, ctx->table_planar, ctx->table_rec);
     size_t off[A_COUNT];
     r->bytes = ref_layout(r->geom, off);
     r->free_stream = ctx->alloc_stream;
@@ -371,12 +379,65 @@ int oss_ref_tables(const oss_ref *ref, const void **L, const void **R, const voi
     return OSS_OK;
 }
 
+int oss_ref_layout_q(const oss_ref *ref, oss_quantity_layout out[OSS_MAX_QUANTITIES],
+                     int32_t *nq, int64_t *plane_bytes)
+{
+    if (!ref || !out || !nq || !plane_bytes)
+        return OSS_E_ARG;
+    const BuildGeom &g = ref->geom;
+    *nq = g.nq;
+    *plane_bytes = g.plane;
+    int j = 0;
+    for (int q = 0; q < OSS_MAX_QUANTITIES; ++q) {
+        oss_quantity_layout &o = out[q];
+        o = oss_quantity_layout{-1, 0, 0, -1, 0, 0};
+        if (q >= g.nq)
+            continue;
+        if (g.rec) {
+            // sum plane; {squares low word, gradient} records; squares' byte plane
+            o.stride = q == 0 ? 4 : 8;
+            o.bits = 32;
+            o.offset = q == 0 ? 0 : q == 1 ? g.plane - 4 : g.plane;
+            if (q == 1) {
+                o.hi_offset = 3 * g.plane + 3;
+                o.hi_stride = 1;
+                o.hi_bits = 8;
+            }
+        } else if (g.planar && g.sqi >= 0) {
+            const int pl = q <= g.sqi ? q : q + 1;
+            o.offset = pl * g.plane;
+            o.stride = 4;
+            o.bits = 32;
+            if (q == g.sqi) {
+                o.hi_offset = (pl + 1) * g.plane;
+                o.hi_stride = 4;
+                o.hi_bits = 32;
+            }
+        } else if (g.planar) {
+            o.offset = q * g.plane;
+            o.stride = g.ebytes;
+            o.bits = 8 * g.ebytes;
+        } else if (g.sqi < 0) {
+            o.offset = q * g.ebytes;
+            o.stride = g.tab_es;
+            o.bits = 8 * g.ebytes;
+        } else {
+            o.stride = 16;
+            o.offset = q == g.sqi ? 0 : 8 + 4 * j++;
+            o.bits = q == g.sqi ? 64 : 32;
+        }
+    }
+    return OSS_OK;
+}
+
 int oss_ref_layout(const oss_ref *ref, int32_t *entry_stride, int64_t offset[OSS_MAX_QUANTITIES],
                    int32_t bits[OSS_MAX_QUANTITIES], int64_t *plane_bytes)
 {
     if (!ref || !entry_stride || !offset || !bits || !plane_bytes)
         return OSS_E_ARG;
     const BuildGeom &g = ref->geom;
+    if (g.rec)
+        return OSS_E_STATE;  // per-quantity strides: oss_ref_layout_q
     *entry_stride = g.tab_es;
     *plane_bytes = g.plane;
     int j = 0;
@@ -534,6 +595,11 @@ int oss_ctx_set_option(oss_ctx *ctx, int32_t option, int32_t value)
             return OSS_E_ARG;
         ctx->build_stream = value;
         return OSS_OK;
+    case OSS_OPT_TABLE_REC:
+        if (value != 0 && value != 1)
+            return OSS_E_ARG;
+        ctx->table_rec = value;
+        return OSS_OK;
     default:
         return OSS_E_ARG;
     }
@@ -552,6 +618,7 @@ int oss_ctx_get_option(oss_ctx *ctx, int32_t option, int32_t *value)
     case OSS_OPT_STAR_PIPE: *value = ctx->star_pipe; return OSS_OK;
     case OSS_OPT_STAR_STAGED: *value = ctx->star_staged; return OSS_OK;
     case OSS_OPT_BUILD_STREAM: *value = ctx->build_stream; return OSS_OK;
+    case OSS_OPT_TABLE_REC: *value = ctx->table_rec; return OSS_OK;
     default: return OSS_E_ARG;
     }
 }

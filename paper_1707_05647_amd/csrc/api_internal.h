@@ -36,6 +36,7 @@ struct oss_ctx {
     int star_lds = 0;              // OSS_OPT_STAR_LDS
     int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
     int table_planar = 1;          // OSS_OPT_TABLE_PLANAR
+    int table_rec = 1;             // OSS_OPT_TABLE_REC
     int star_pipe = 0;             // OSS_OPT_STAR_PIPE
     int star_staged = 1;           // OSS_OPT_STAR_STAGED
     int build_stream = 1;          // OSS_OPT_BUILD_STREAM

@@ -37,7 +37,9 @@ hipError_t batch_mix(const BuildGeom &g, const void *L, const void *R, const voi
                             bool staged, hipStream_t st)
 {
     if (g.planar) {
-        if (g.nq == 3 && g.sqi == 1)
+        if (g.rec)
+            batch_launch<TabPR>(g, L, R, Rp, bp, eo, sw, staged, st);
+        else if (g.nq == 3 && g.sqi == 1)
             batch_launch<TabPS<3, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);
         else if (g.nq == 2 && g.sqi == 1)
             batch_launch<TabPS<2, 1>>(g, L, R, Rp, bp, eo, sw, staged, st);

@@ -28,6 +28,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
     const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
     const int64_t row_bytes = pitch_e * ES;
     const int64_t hw = (int64_t)H * W;
+    const TabBases tb{static_cast<const char *>(L), static_cast<const char *>(R),
+                      static_cast<const char *>(Rp)};
     for (int ip = 0; ip < n_passes; ++ip) {
         const DevBatchPass ps = passes[ip];
         const DevBatchGroup *grp = groups + ps.group;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                         continue;
                     }
                     if (in_c)
-                        star_sums_rest<Tab>(ad, plane, F);
+                        star_sums_rest<Tab>(ad, tb, plane, F);
                     in = in_c;
                     if (in_c) {
 #pragma unroll
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_batch_kernel(
                     in = xv;
                     if (xv) {
                         star_sums_at<Tab>(star_addr_rows<Tab>(Ly, Ry, Rpy, rd.roff, lane_off, r, s),
-                                          F, plane);
+                                          tb, F, plane);
 #pragma unroll
                         for (int q = 0; q < NQ; ++q)
                             in = in & (F[q] >= rd.lo[q]) & (F[q] <= rd.hi[q]);

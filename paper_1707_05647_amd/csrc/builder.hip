@@ -31,7 +31,7 @@ namespace oss {
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar, int rec)
 {
     BuildGeom g;
     g.H = H;
@@ -40,6 +40,7 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
     g.ebytes = ebytes;
     g.sqi = sqi;
     g.planar = planar ? 1 : 0;
+    g.rec = (rec && g.planar && sqi == 1 && nq == 3) ? 1 : 0;
     // Rows of a whole number of 128-byte lines, and entry index 0 (x = -1)
     // TAB_LINE - tab_es bytes into each table (plane) allocation: image
     // column 0 of every row then starts a line, so the final pass's 64-column
@@ -50,6 +51,9 @@ BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi, int planar)
         g.tab_es = sqi >= 0 ? 4 : ebytes;
         g.plane = ((int64_t)(H + 1) * g.pitch_e * g.tab_es + TAB_LINE + 255) / 256 * 256;
         g.tab_bytes = g.plane * (sqi >= 0 ? nq + 1 : nq);
+        if (g.rec)  // sum plane, record plane (twice its size), byte plane
+            g.tab_bytes = 3 * g.plane +
+                          ((int64_t)(H + 1) * g.pitch_e + TAB_LINE + 255) / 256 * 256;
     } else {
         g.tab_es = sqi >= 0 ? 16 : nq * ebytes;
         g.plane = 0;
@@ -598,9 +602,11 @@ __global__ __launch_bounds__(256) void carry_kernel(BuildGeom g, const T *__rest
 // (LAY_INTER), one value in each of NQ planes (LAY_PLANAR), the 16-byte mixed
 // entry (64-bit squares from slot SQI, the other quantities modulo 2^32,
 // written as one 16-byte store; LAY_MIX), or 32-bit planes with the squares
-// split into a low-word and a high-word plane (LAY_PLANAR_MIX).  plane_b is
-// the byte distance between planes.
-enum { LAY_INTER = 0, LAY_PLANAR = 1, LAY_MIX = 2, LAY_PLANAR_MIX = 3 };
+// split into a low-word and a high-word plane (LAY_PLANAR_MIX), or the sum
+// plane, {squares low word, gradient} records and a byte plane of the
+// squares' bits 32..39 (LAY_PLANAR_REC: sum, squares, gradient).  plane_b is
+// the byte distance between planes (the sum plane's size).
+enum { LAY_INTER = 0, LAY_PLANAR = 1, LAY_MIX = 2, LAY_PLANAR_MIX = 3, LAY_PLANAR_REC = 4 };
 
 // One table value; NT: a non-temporal (streaming) store.  A compile-time
 // choice: a run-time branch between the two stores is merged by the
@@ -635,6 +641,14 @@ __device__ __forceinline__ void store_entry(T *__restrict__ tab, int64_t e, cons
             if (q == SQI)
                 put<NT>(t32 + (pl + 1) * pe + e, (uint32_t)((uint64_t)v[q] >> 32));
         }
+    } else if constexpr (LAY == LAY_PLANAR_REC) {
+        char *b = reinterpret_cast<char *>(tab);
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 rec = {(uint32_t)v[1], (uint32_t)v[2]};
+        put<NT>(reinterpret_cast<uint32_t *>(b) + e, (uint32_t)v[0]);
+        put<NT>(reinterpret_cast<u32x2 *>(b + plane_b - 4 + 8 * e), rec);
+        put<NT>(reinterpret_cast<uint8_t *>(b + 3 * plane_b + 3 + e),
+                (uint8_t)((uint64_t)v[1] >> 32));
     } else if constexpr (LAY == LAY_INTER) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
@@ -848,7 +862,9 @@ static hipError_t build_pix(const BuildGeom &g, const void *px, int64_t pb, uint
             switch (fm) {
             case 3: return build_t<Pix, 3, uint64_t, LAY_PLANAR_MIX, 1>(g, px, pb, bb, st, pr);
             case 6: return build_t<Pix, 6, uint64_t, LAY_PLANAR_MIX, 0>(g, px, pb, bb, st, pr);
-            case 7: return build_t<Pix, 7, uint64_t, LAY_PLANAR_MIX, 1>(g, px, pb, bb, st, pr);
+            case 7:
+                return g.rec ? build_t<Pix, 7, uint64_t, LAY_PLANAR_REC, 1>(g, px, pb, bb, st, pr)
+                             : build_t<Pix, 7, uint64_t, LAY_PLANAR_MIX, 1>(g, px, pb, bb, st, pr);
             default: return hipErrorInvalidValue;
             }
         }

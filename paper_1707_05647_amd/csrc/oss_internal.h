@@ -56,6 +56,9 @@ struct BuildGeom {
     int cx0, cw;       // carry range [cx0, cx0 + cw): the union of the final tiles' columns
     int nbp;           // row-prefix bases per row: P_y(64 j - 1), j in [0, nbp)
     int nt;            // 1: table entries stored non-temporally (streaming)
+    int rec;           // planar record layout (sum, squares, gradient; squares'
+                       // region sums below 2^40): sum plane, 8-byte {squares low
+                       // word, gradient} records, byte plane of squares bits 32..39
 };
 
 // Table entries hold the nq quantities in feature order, each in ebytes
@@ -64,10 +67,13 @@ struct BuildGeom {
 // as 32 bits each (modulo 2^32), zero padded.  planar: each quantity in a
 // plane of its own, plane allocations 256-byte aligned; with sqi >= 0 every
 // plane holds 32-bit values and the squares take two planes, low word then
-// high word.  Rows are a multiple of TAB_LINE bytes, and entry 0 of a table
-// (plane) sits tab_off = TAB_LINE - tab_es bytes into its allocation.
+// high word, unless rec: then (sum, squares, gradient only) the sum plane is
+// followed by an 8-byte {squares low word, gradient} record per entry and a
+// byte plane of the squares' bits 32..39 (see TabPR).  Rows are a multiple of
+// TAB_LINE bytes, and entry 0 of a table (plane) sits tab_off = TAB_LINE -
+// tab_es bytes into its allocation.
 constexpr int TAB_LINE = 128;
-BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1, int planar = 0);
+BuildGeom make_geom(int H, int W, int nq, int ebytes, int sqi = -1, int planar = 0, int rec = 0);
 
 // ---------------------------------------------------------------------------
 // Screening plan uploaded per call.

@@ -59,6 +59,8 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
     // byte offset of column x0 + tid + 1 relative to column x0
     const uint32_t lane_off = (uint32_t)((threadIdx.x + 1) * ES);
     const int64_t row_bytes = pitch_e * ES;
+    const TabBases tb{static_cast<const char *>(L), static_cast<const char *>(R),
+                      static_cast<const char *>(Rp)};
     // the plan (radii, probe bounds) in LDS once per block: per radius it is
     // read there instead of through the scalar cache
     __shared__ DevTemplatePlan s_plan;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
                 if (__builtin_amdgcn_ballot_w64(maybe) == 0)
                     continue;
                 if (maybe) {
-                    star_sums_rest<Tab>(ad, plane, F);
+                    star_sums_rest<Tab>(ad, tb, plane, F);
                     for (int p = rd.first; p < rd.first + rd.count; ++p) {
                         const DevProbe pr = plan->probes[p];
                         bool pass = true;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(STAR_MAX_THREADS) void star_plain_kernel(
                 }
             } else if (xv) {
                 int64_t F[NQ];
-                star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, F, plane);
+                star_sums<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s, tb, F, plane);
                 for (int p = rd.first; p < rd.first + rd.count; ++p) {
                     const DevProbe pr = plan->probes[p];
                     bool pass = true;
@@ -159,14 +161,14 @@ __device__ __forceinline__ void star_load(Looks<Tab> &o, const char *L, const ch
     const uint32_t cs1 = (uint32_t)(xc - s) * ES;                // x-s-1
     const uint32_t cr = (uint32_t)(xc + r + 1) * ES;             // x+r
     const uint32_t cr1 = (uint32_t)(xc - r) * ES;                // x-r-1
-    o.a = Tab::load(l_bot + cs, plane);    // L(x+s,   y+s)
-    o.b = Tab::load(l_bot + cs1, plane);   // L(x-s-1, y+s)
-    o.c = Tab::load(l_top + cs, plane);    // L(x+s,   y-s-1)
-    o.d = Tab::load(l_top + cs1, plane);   // L(x-s-1, y-s-1)
-    o.e = Tab::load(r_bot + c0, plane);    // R(x, y+r)
-    o.f = Tab::load(rp_mid + cr1, plane);  // R'(x-r-1, y-1)
-    o.h = Tab::load(rp_mid + cr, plane);   // R'(x+r, y-1)
-    o.k = Tab::load(r_top + c0, plane);    // R(x, y-r-1)
+    o.a = tab_load<Tab>(l_bot + cs, L, plane);     // L(x+s,   y+s)
+    o.b = tab_load<Tab>(l_bot + cs1, L, plane);    // L(x-s-1, y+s)
+    o.c = tab_load<Tab>(l_top + cs, L, plane);     // L(x+s,   y-s-1)
+    o.d = tab_load<Tab>(l_top + cs1, L, plane);    // L(x-s-1, y-s-1)
+    o.e = tab_load<Tab>(r_bot + c0, R, plane);     // R(x, y+r)
+    o.f = tab_load<Tab>(rp_mid + cr1, Rp, plane);  // R'(x-r-1, y-1)
+    o.h = tab_load<Tab>(rp_mid + cr, Rp, plane);   // R'(x+r, y-1)
+    o.k = tab_load<Tab>(r_top + c0, R, plane);     // R(x, y-r-1)
 }
 
 template <typename Tab>
@@ -430,7 +432,9 @@ static hipError_t star_mix(const BuildGeom &g, const void *L, const void *R, con
                            hipStream_t stream, int variant)
 {
     if (g.planar) {
-        if (g.nq == 3 && g.sqi == 1)
+        if (g.rec)
+            star_plain_launch<TabPR>(g, L, R, Rp, plan, eo, sw, stream, variant);
+        else if (g.nq == 3 && g.sqi == 1)
             star_plain_launch<TabPS<3, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);
         else if (g.nq == 2 && g.sqi == 1)
             star_plain_launch<TabPS<2, 1>>(g, L, R, Rp, plan, eo, sw, stream, variant);

@@ -3,6 +3,8 @@
 
 #include "oss_internal.h"
 
+#include <type_traits>
+
 namespace oss {
 
 template <typename T, int NQ>
@@ -208,6 +210,104 @@ struct TabPS {
     }
 };
 
+// Planar record tables (sum, squares, gradient, with every square and
+// diamond sum of the squares below 2^40): the sum plane (32-bit values, as
+// the other planar layouts), then per entry one 8-byte record {squares low
+// word, gradient}, then a byte plane with the squares' bits 32..39.  A
+// square or diamond sum of the squares is formed modulo 2^40 from these
+// and is exact; the other quantities are exact modulo 2^32 as in TabPS.
+// With plane = the sum plane's bytes and base = the table's entry 0:
+//   sum of entry e      at base + 4 e
+//   record of entry e   at base + plane - 4 + 8 e  (entry (0, y) starts a line)
+//   byte of entry e     at base + 3 plane + 3 + e  (likewise)
+// so a lookup at sum address p finds its record and byte from p - base; the
+// second-stage lookups of a staged pass touch one record line and one byte
+// line per lane instead of three plane lines.
+struct TabPR {
+    static constexpr int NQ = 3;
+    static constexpr int64_t ES = 4;
+    static constexpr bool STAGE = true;
+    static constexpr bool REC = true;
+    static constexpr int C = 0;  // the sum: looked up first, alone
+    using V = uint32_t;
+    struct Rest {
+        uint32_t lo, g, hi;
+    };
+    struct E {
+        uint32_t c;
+        Rest r;
+    };
+    __device__ static __forceinline__ V load_c(const char *p, int64_t)
+    {
+        return *reinterpret_cast<const uint32_t *>(p);
+    }
+    __device__ static __forceinline__ Rest load_rest(const char *p, const char *base,
+                                                     int64_t plane)
+    {
+        const int64_t off = p - base;
+        const uint2 r = *reinterpret_cast<const uint2 *>(base + (plane - 4) + 2 * off);
+        const uint8_t h = *reinterpret_cast<const uint8_t *>(base + 3 * plane + 3 + (off >> 2));
+        return {r.x, r.y, (uint32_t)h};
+    }
+    __device__ static __forceinline__ E load(const char *p, const char *base, int64_t plane)
+    {
+        return {load_c(p, plane), load_rest(p, base, plane)};
+    }
+    __device__ static __forceinline__ uint64_t sq(const Rest &r)
+    {
+        return (uint64_t)r.lo | ((uint64_t)r.hi << 32);
+    }
+    __device__ static __forceinline__ int64_t w40(uint64_t v)
+    {
+        return (int64_t)(v & ((1ull << 40) - 1));
+    }
+    __device__ static __forceinline__ void reduce_rest(const Rest &a, const Rest &b, const Rest &c,
+                                                       const Rest &d, const Rest &e, const Rest &f,
+                                                       const Rest &h, const Rest &k, int64_t *F)
+    {
+        F[1] = w40(sq(a) - sq(b) - sq(c) + sq(d)) + w40(sq(e) - sq(f) - sq(h) + sq(k));
+        F[2] = widen((uint32_t)(a.g - b.g - c.g + d.g)) + widen((uint32_t)(e.g - f.g - h.g + k.g));
+    }
+    __device__ static __forceinline__ void reduce(const E &a, const E &b, const E &c, const E &d,
+                                                  const E &e, const E &f, const E &h, const E &k,
+                                                  int64_t *F)
+    {
+        F[0] = widen((uint32_t)(a.c - b.c - c.c + d.c)) + widen((uint32_t)(e.c - f.c - h.c + k.c));
+        reduce_rest(a.r, b.r, c.r, d.r, e.r, f.r, h.r, k.r, F);
+    }
+};
+
+// Layouts whose loads need the table's entry-0 pointer (TabPR).
+template <typename T, typename = void>
+struct IsRec : std::false_type {};
+template <typename T>
+struct IsRec<T, std::void_t<decltype(T::REC)>> : std::true_type {};
+
+// The entry-0 pointers of the three tables of a reference.
+struct TabBases {
+    const char *L, *R, *Rp;
+};
+
+// Load the entry at p of table base (any layout).
+template <typename Tab>
+__device__ __forceinline__ typename Tab::E tab_load(const char *p, const char *base,
+                                                    int64_t plane)
+{
+    if constexpr (IsRec<Tab>::value)
+        return Tab::load(p, base, plane);
+    else
+        return Tab::load(p, plane);
+}
+
+template <typename Tab>
+__device__ __forceinline__ auto tab_load_rest(const char *p, const char *base, int64_t plane)
+{
+    if constexpr (IsRec<Tab>::value)
+        return Tab::load_rest(p, base, plane);
+    else
+        return Tab::load_rest(p, plane);
+}
+
 // Entry at a wave-uniform row base plus this lane's byte offset.
 template <typename E>
 __device__ __forceinline__ E entry_at(const char *row, uint32_t lane_off)
@@ -277,24 +377,24 @@ __device__ __forceinline__ StarAddr star_addr_rows(const char *Ly, const char *R
     return o;
 }
 
-// Star feature sums of every quantity.
+// Star feature sums of every quantity (tb: the tables' entry-0 pointers; the
+// lookups a..d are in L, e and k in R, f and h in R').
 template <typename Tab>
-__device__ __forceinline__ void star_sums_at(const StarAddr &p, int64_t *F, int64_t plane)
+__device__ __forceinline__ void star_sums_at(const StarAddr &p, const TabBases &tb, int64_t *F,
+                                             int64_t plane)
 {
-    Tab::reduce(Tab::load(p.a, plane), Tab::load(p.b, plane), Tab::load(p.c, plane),
-                Tab::load(p.d, plane), Tab::load(p.e, plane), Tab::load(p.f, plane),
-                Tab::load(p.h, plane), Tab::load(p.k, plane), F);
+    Tab::reduce(tab_load<Tab>(p.a, tb.L, plane), tab_load<Tab>(p.b, tb.L, plane),
+                tab_load<Tab>(p.c, tb.L, plane), tab_load<Tab>(p.d, tb.L, plane),
+                tab_load<Tab>(p.e, tb.R, plane), tab_load<Tab>(p.f, tb.Rp, plane),
+                tab_load<Tab>(p.h, tb.Rp, plane), tab_load<Tab>(p.k, tb.R, plane), F);
 }
 
 template <typename Tab>
 __device__ __forceinline__ void star_sums(const char *Lb, const char *Rb, const char *Rpb,
                                           int64_t row_bytes, uint32_t lane_off, int y, int r,
-                                          int s, int64_t *F, int64_t plane)
+                                          int s, const TabBases &tb, int64_t *F, int64_t plane)
 {
-    const StarAddr p = star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s);
-    Tab::reduce(Tab::load(p.a, plane), Tab::load(p.b, plane), Tab::load(p.c, plane),
-                Tab::load(p.d, plane), Tab::load(p.e, plane), Tab::load(p.f, plane),
-                Tab::load(p.h, plane), Tab::load(p.k, plane), F);
+    star_sums_at<Tab>(star_addr<Tab>(Lb, Rb, Rpb, row_bytes, lane_off, y, r, s), tb, F, plane);
 }
 
 // Staged form (planar layouts, Tab::STAGE): the feature sum of quantity
@@ -312,12 +412,14 @@ __device__ __forceinline__ int64_t star_sum_c(const StarAddr &p, int64_t plane)
 }
 
 template <typename Tab>
-__device__ __forceinline__ void star_sums_rest(const StarAddr &p, int64_t plane, int64_t *F)
+__device__ __forceinline__ void star_sums_rest(const StarAddr &p, const TabBases &tb,
+                                               int64_t plane, int64_t *F)
 {
-    Tab::reduce_rest(Tab::load_rest(p.a, plane), Tab::load_rest(p.b, plane),
-                     Tab::load_rest(p.c, plane), Tab::load_rest(p.d, plane),
-                     Tab::load_rest(p.e, plane), Tab::load_rest(p.f, plane),
-                     Tab::load_rest(p.h, plane), Tab::load_rest(p.k, plane), F);
+    Tab::reduce_rest(tab_load_rest<Tab>(p.a, tb.L, plane), tab_load_rest<Tab>(p.b, tb.L, plane),
+                     tab_load_rest<Tab>(p.c, tb.L, plane), tab_load_rest<Tab>(p.d, tb.L, plane),
+                     tab_load_rest<Tab>(p.e, tb.R, plane), tab_load_rest<Tab>(p.f, tb.Rp, plane),
+                     tab_load_rest<Tab>(p.h, tb.Rp, plane), tab_load_rest<Tab>(p.k, tb.R, plane),
+                     F);
 }
 
 // ---------------------------------------------------------------------------

@@ -36,7 +36,14 @@ class Reference:
         self.handle = L.oss_ref_create(ctx.handle, self.desc, self.feat_mask, max_radius)
         info = L.oss_ref_tables(self.handle)
         self.value_bits, self.max_radius = info[5], info[6]
-        self.entry_bytes, self.slots, self.plane_bytes = L.oss_ref_layout(self.handle)
+        # per quantity slot: where its (low) value and its high part sit
+        self.layout, self.plane_bytes = L.oss_ref_layout_q(self.handle)
+        # (offset, stored width in bits) per slot; values narrower than 64
+        # bits are the sums modulo 2^width
+        self.slots = [(o, b + hb) for o, _, b, _, _, hb in self.layout]
+        self.entry_bytes = self.layout[0][1] if self.layout else 0  # first slot's stride
+        # bytes one table entry takes over all planes
+        self.stored_entry_bytes = sum((b + hb) // 8 for _, _, b, _, _, hb in self.layout)
         if build:
             self.build(stream)
 
@@ -60,36 +67,36 @@ class Reference:
 
     def tables_host(self):
         """Copy (L, R, R') to host int64 arrays [H+1, W+1, nq]: each slot's
-        stored value (``self.slots[q][1]`` bits wide: 32 = the sums modulo
-        2^32, zero-extended; 64 = exact); synchronous; for tests and
+        stored value (``self.slots[q][1]`` bits wide: the sums modulo
+        2^width, zero-extended; 64 = exact); synchronous; for tests and
         inspection."""
         Lp, Rp_, Rpp, pitch, nq, vb, _ = L.oss_ref_tables(self.handle)
-        es = self.entry_bytes  # entry stride
         H1 = self.H + 1
         n = H1 * pitch
-        # bytes the table spans on the device, and a host buffer that also
-        # holds the reshaped views' unused tails
-        # 64-bit values in 4-byte planes: low word at off, high word one plane on
-        words = [((off, off + self.plane_bytes) if (bits == 64 and es == 4) else (off,), bits)
-                 for off, bits in self.slots]
-        used = max(o + (n - 1) * es + min(bits // 8, es) for offs, bits in words for o in offs)
-        span = max(o for offs, _ in words for o in offs) + n * es
+        # the byte span of one table: every quantity's low and high parts
+        parts = []
+        for off, st, b, hoff, hst, hb in self.layout:
+            parts.append((off, st, b // 8))
+            if hb:
+                parts.append((hoff, hst, hb // 8))
+        span = max(o + (n - 1) * st + nb for o, st, nb in parts)
         out = []
         for p in (Lp, Rp_, Rpp):
-            raw = np.zeros(span, np.uint8)
-            _hip_memcpy_d2h(raw[:used], p)
-            t = np.empty((H1, self.W + 1, nq), np.int64)
+            raw = np.zeros(span + 8, np.uint8)
+            _hip_memcpy_d2h(raw[:span], p)
 
-            def plane_values(off, nb):
-                v = raw[off:off + n * es].reshape(H1, pitch, es)[:, :self.W + 1, :nb]
-                return np.ascontiguousarray(v).view(np.uint32 if nb == 4 else np.int64)[..., 0]
-            for q, (offs, bits) in enumerate(words):
-                if len(offs) == 2:
-                    lo = plane_values(offs[0], 4).astype(np.uint64)
-                    hi = plane_values(offs[1], 4).astype(np.uint64)
-                    t[..., q] = (lo | (hi << np.uint64(32))).view(np.int64)
-                else:
-                    t[..., q] = plane_values(offs[0], bits // 8).astype(np.int64)
+            def values(off, st, nb):
+                idx = off + np.arange(n, dtype=np.int64).reshape(H1, pitch)[:, :self.W + 1] * st
+                v = np.zeros(idx.shape, np.uint64)
+                for k in range(nb):  # little-endian bytes
+                    v |= raw[idx + k].astype(np.uint64) << np.uint64(8 * k)
+                return v
+            t = np.empty((H1, self.W + 1, nq), np.int64)
+            for q, (off, st, b, hoff, hst, hb) in enumerate(self.layout):
+                v = values(off, st, b // 8)
+                if hb:
+                    v |= values(hoff, hst, hb // 8) << np.uint64(b)
+                t[..., q] = v.view(np.int64)
             out.append(t)
         return out
 

@@ -83,8 +83,8 @@ def test_tables_match_definitions(runner, case, planar, stream):
     want = tables_numpy(img, fm)
     for w_ in want:
         for q, (_, b) in enumerate(slots):
-            if b == 32:
-                w_[..., q] %= 1 << 32
+            if b < 64:
+                w_[..., q] %= 1 << b
     bad = []
     for name, g, w in zip(("L", "R", "R'"), got, want):
         diff = np.argwhere(g.astype(np.int64) != w)
@@ -92,6 +92,49 @@ def test_tables_match_definitions(runner, case, planar, stream):
             bad.append(f"{name}: {len(diff)} wrong entries of {g.size}, first (row, col, q) "
                        f"{diff[:6].tolist()} (table row = y+1, col = x+1)")
     assert not bad, f"tables with slots {slots}: " + "; ".join(bad)
+
+
+@pytest.mark.parametrize("rec", [1, 0], ids=["record", "split"])
+@pytest.mark.parametrize("case", [(129, 100, 12, 40), (61, 530, 8, 200), (20, 400, 12, 180),
+                                  (20, 400, 12, 181)], ids=lambda c: "x".join(map(str, c)))
+def test_record_tables(runner, case, rec):
+    """Planar sum/squares/gradient tables with 64-bit squares: the record
+    layout (squares' low words and the gradient in 8-byte records, the
+    squares' bits 32..39 in a byte plane) wherever every square and diamond
+    sum of the squares stays below 2^40 (12-bit pixels up to radius 180,
+    not 181), else four 32-bit planes; either way every entry equals its
+    definition (modulo 2^40 for recorded squares)."""
+    H, W, depth, max_r = case
+    L = runner.L
+    h = runner.ctx.handle
+    rng = np.random.default_rng(H + 7 * W)
+    dt = np.uint8 if depth == 8 else np.uint16
+    img = rng.integers(0, 2 ** depth, (H, W)).astype(dt)
+    say(f"record tables {case} rec={rec}")
+    assert L.oss_ctx_get_option(h, L.OSS_OPT_TABLE_REC) == 1
+    L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_REC, rec)
+    try:
+        ref = runner.ctx.reference(L.device_image(img, runner.dev), 7, depth, max_radius=max_r)
+    finally:
+        L.oss_ctx_set_option(h, L.OSS_OPT_TABLE_REC, 1)
+    runner.torch.cuda.synchronize()
+    sq40 = (2 ** depth - 1) ** 2 * max(2 * max_r * max_r + 2 * max_r + 1,
+                                        (2 * oc.square_half(max_r) + 1) ** 2) < 2 ** 40
+    widths = [b for _, b in ref.slots]
+    if rec and sq40:
+        assert widths == [32, 40, 32] and ref.stored_entry_bytes == 13
+        with pytest.raises(L.OssError):
+            L.oss_ref_layout(ref.handle)  # one stride for all slots cannot describe it
+    else:
+        assert widths == [32, 64, 32] and ref.stored_entry_bytes == 16
+    got = ref.tables_host()
+    ref.release()
+    want = tables_numpy(img, 7)
+    for g, w_ in zip(got, want):
+        for q, b in enumerate(widths):
+            if b < 64:
+                w_[..., q] %= 1 << b
+        assert np.array_equal(g, w_)
 
 
 # max radius -> storage: the probes' own maximum (32-bit entries unless the
@@ -198,7 +241,9 @@ def test_overflow_edge_constant_max(runner, depth, max_r):
 def test_32bit_storage_near_its_limit(runner):
     """12-bit pixels, radius 10: square sums of squares reach 3.77e9 < 2^32,
     so the reference is stored in 32-bit words; at radius 11 the squares
-    need 64 bits (mixed 16-byte entries) while sums and gradients still fit."""
+    need more than 32 bits while sums and gradients still fit: 64-bit
+    accumulation, the squares stored in 40 bits (record tables, the planar
+    default: their sums stay below 2^40)."""
     rng = np.random.default_rng(4)
     img = rng.integers(3900, 4096, (64, 80)).astype(np.uint16)
     img[20:40, 30:50] = 4095
@@ -211,7 +256,7 @@ def test_32bit_storage_near_its_limit(runner):
     assert np.array_equal(cands, oc.mask_and_list(want)[1]) and n > 0
     mask, cands, n = runner.screen(img, tm, probes, 7, P, Q, bit_depth=12, max_radius=11)
     assert runner.last_value_bits == 64  # 64-bit squares only
-    assert [b for _, b in runner.last_slots] == [32, 64, 32]
+    assert [b for _, b in runner.last_slots] == [32, 40, 32]
     assert np.array_equal(cands, oc.mask_and_list(want)[1])
 
 
@@ -296,10 +341,11 @@ def test_interleaved_tables_same_results(runner, cfg, max_r):
 
 
 def test_default_tables_are_planar(runner):
-    """The default layout is planar for 32-bit storage, for 64-bit squares
-    beside 32-bit sums and gradients (split planes), and for 64-bit storage."""
+    """The default layout is planar for 32-bit storage, for wide squares
+    beside 32-bit sums and gradients (record tables: the squares' sums stay
+    below 2^40 at radius 200 for 8-bit pixels), and for 64-bit storage."""
     w = make_workload(2, 0, H=200, W=230, blobs_per_512sq=800, sig_hi=24)
-    want = {-2: [32, 32, 32], 200: [32, 64, 32], 1 << 20: [64, 64, 64]}
+    want = {-2: [32, 32, 32], 200: [32, 40, 32], 1 << 20: [64, 64, 64]}
     for max_r, bits in want.items():
         _screen_and_compare(runner, w, max_r)
         assert runner.last_plane_bytes > 0
