@@ -437,12 +437,22 @@ inline bool emit_ok(const EmitOut &eo, const BuildGeom &g)
            (eo.seg_count == nullptr) == (eo.stage == nullptr);
 }
 
-// A byte store through a global-memory pointer: a store through a generic
-// pointer becomes a flat store, which also counts on the scalar-load counter
-// and would make the next scalar-load wait for it.
+// Emission stores: through global-memory pointers (a store through a
+// generic pointer becomes a flat store, which also counts on the scalar-load
+// counter and would make the next scalar load wait for it), and streaming
+// (non-temporal), so the mask and staged candidates do not take L2 lines
+// from the tables the star pass is still reading (workload 5: star pass
+// 54.0 -> 53.4 ms).
 __device__ __forceinline__ void store_u8_global(uint8_t *p, uint8_t v)
 {
-    *(__attribute__((address_space(1))) uint8_t *)p = v;
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) uint8_t *)p);
+}
+
+__device__ __forceinline__ void store_u32x2_global(uint2 *p, uint32_t a, uint32_t b)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = {a, b};
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) u32x2 *)p);
 }
 
 __device__ __forceinline__ int lane_rank(uint64_t ballot)
@@ -486,9 +496,9 @@ __device__ __forceinline__ void emit_slot(const EmitOut &eo, const EmitRow &er, 
         const uint64_t bal = __builtin_amdgcn_ballot_w64(on);
         const int64_t seg = (int64_t)tg * er.tseg + er.srow;
         if (er.lane == 0)
-            eo.seg_count[seg] = (uint8_t)__popcll(bal);
+            store_u8_global(eo.seg_count + seg, (uint8_t)__popcll(bal));
         if (on)
-            eo.stage[seg * SEG_W + lane_rank(bal)] = make_uint2((uint32_t)x, v);
+            store_u32x2_global(eo.stage + seg * SEG_W + lane_rank(bal), (uint32_t)x, v);
     }
 }
 
