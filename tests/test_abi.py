@@ -154,6 +154,14 @@ def test_screen_argument_errors_before_any_launch(lib):
                         None) == lib.OSS_E_ARG
     assert L.oss_ref_create(None, None, 7, -1, None) == lib.OSS_E_ARG
     assert L.oss_ref_build(None, None, None) == lib.OSS_E_ARG
+    # table layout queries need a reference and every output
+    out = (lib.oss_quantity_layout * lib.OSS_MAX_QUANTITIES)()
+    nq, plane = C.c_int32(), C.c_int64()
+    assert L.oss_ref_layout_q(None, out, C.byref(nq), C.byref(plane)) == lib.OSS_E_ARG
+    es = C.c_int32()
+    off = (C.c_int64 * lib.OSS_MAX_QUANTITIES)()
+    bits = (C.c_int32 * lib.OSS_MAX_QUANTITIES)()
+    assert L.oss_ref_layout(None, C.byref(es), off, bits, C.byref(plane)) == lib.OSS_E_ARG
 
 
 def test_server_argument_errors(lib):
