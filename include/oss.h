@@ -142,7 +142,7 @@ int oss_ctx_destroy(oss_ctx *ctx);
  *                                multiple of 64; default 512)
  *   OSS_OPT_STAR_BLOCKS_PER_XCD  persistent star blocks per XCD, about the
  *                                rows of one strip an XCD has in flight
- *                                (default 64); a launch uses at most as
+ *                                (default 96); a launch uses at most as
  *                                many as the GPU holds at once for its
  *                                kernel
  *   OSS_OPT_STAR_LDS             1: oss_screen stages the table rows that

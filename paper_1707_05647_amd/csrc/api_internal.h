@@ -32,7 +32,7 @@ struct oss_ctx {
     int next_slot = 0;
     oss::Profiler prof;
     int star_strip = 512;          // OSS_OPT_STAR_STRIP
-    int star_blocks_per_xcd = 64;  // OSS_OPT_STAR_BLOCKS_PER_XCD
+    int star_blocks_per_xcd = 96;  // OSS_OPT_STAR_BLOCKS_PER_XCD
     int star_lds = 0;              // OSS_OPT_STAR_LDS
     int batch_bucket = 0;          // OSS_OPT_BATCH_BUCKET
     int table_planar = 1;          // OSS_OPT_TABLE_PLANAR
