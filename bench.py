@@ -1005,8 +1005,8 @@ def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the screen shards "
-              "by row bands with no exchange on the hot path, but multi-GPU runs are not part "
-              "of this build.", file=sys.stderr)
+              "by row bands with no exchange on the hot path, but multi-GPU runs are not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     dev = torch.device("cuda", 0)
