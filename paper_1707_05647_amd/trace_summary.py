@@ -1,7 +1,7 @@
 """Per-kernel launch durations from a rocprofv3 kernel trace, split by how
 the launch ran.
 
-    python -m paper_1707_05647_amd.trace_summary KERNEL_TRACE_CSV
+    python -m paper_1707_05647_amd.trace_summary KERNEL_TRACE_CSV [--only TEXT ...]
 
 Reads the ``kernel_trace.csv`` of a ``rocprofv3 --kernel-trace`` run and
 prints, per library kernel and launch shape (grid and workgroup size), the
@@ -10,7 +10,10 @@ launches that ran alone and those that overlapped another library launch
 pass beside the other lane's build or star pass, so those launches share the
 compute units and take longer each.  The benchmark's
 one-lane and lanes' HIP-event averages are to be compared with the "alone"
-and "overlapped" rows of the timed launch shape.
+and "overlapped" rows of the timed launch shape.  With ``--only``, the table
+lists only the launches whose full kernel name (template arguments included)
+contains one of the given texts; overlap is still judged against every
+library launch.
 """
 from __future__ import annotations
 
@@ -38,7 +41,7 @@ def load(path):
             grid = _int(row, "Grid_Size_X", "Grid_Size")
             wg = _int(row, "Workgroup_Size_X", "Workgroup_Size")
             out.append((short, int(row["Start_Timestamp"]), int(row["End_Timestamp"]), grid, wg,
-                        _int(row, "Queue_Id")))
+                        _int(row, "Queue_Id"), row.get("Kernel_Name", "")))
     return out
 
 
@@ -57,10 +60,14 @@ def overlapped(launches):
     return flag
 
 
-def summarize(rows):
+def summarize(rows, only=None):
+    """The table; `only`: texts, one of which a listed launch's full kernel
+    name contains (None: every launch)."""
     ov_all = overlapped(rows)
     by_kernel = defaultdict(list)
     for r, o in zip(rows, ov_all):
+        if only and not any(t in r[6] for t in only):
+            continue
         by_kernel[r[0]].append((r, o))
     lines = ["| Kernel | grid x workgroup | launches | ran | avg ms | median ms | min ms | max ms |",
              "|:--|--:|--:|:--|--:|--:|--:|--:|"]
@@ -78,6 +85,11 @@ def summarize(rows):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 2:
+    args = sys.argv[1:]
+    only = None
+    if "--only" in args:
+        i = args.index("--only")
+        only, args = args[i + 1:], args[:i]
+    if len(args) != 1 or (only is not None and not only):
         raise SystemExit(__doc__)
-    print(summarize(load(sys.argv[1])))
+    print(summarize(load(args[0]), only))

@@ -79,3 +79,7 @@ def test_trace_overlap_split(tmp_path):
     text = trace_summary.summarize(rows)
     assert "| star_batch | 768 x 512 | 3 | alone | 8.333 | 10.000 | 5.000 | 10.000 |" in text
     assert "| star_batch | 768 x 512 | 1 | overlapped | 20.000 | 20.000 |" in text
+    # only the list pass listed; its overlap with the star pass still counts
+    only = trace_summary.summarize(rows, only=["compact_list"])
+    assert "star_batch" not in only
+    assert "| compact_list | 768 x 512 | 1 | overlapped | 1.000 |" in only
